@@ -1,0 +1,226 @@
+/*
+ * fast.h -- C-ABI of libfast, an MI355X (gfx950) implementation of the
+ * F.A.S.T. pedestrian model's time step: the data-parallel planning phase
+ * (every agent chooses a desired cell) followed by the sequential motion phase.
+ *
+ * Paper: T. Kretz, "Computation Speed of the F.A.S.T. Model", arXiv:0911.2900.
+ *   Sec. 1  A time step is a planning phase that only reads data common to all
+ *           agents and holds the costly exp evaluations, then a motion phase
+ *           that moves agents one after another and writes the shared data;
+ *           agents never overlap (one agent per cell).
+ *   Sec. 2  k_S = 1.2, k_other = 0; one maximum speed v_m for all agents,
+ *           v_m = 1..5; runs of 396 steps of one simulated second; the
+ *           planning loop "choose_desired_cell(i) for every agent i" is the
+ *           parallel part.
+ * The model details the paper leaves open are fixed as follows (the same
+ * readings the test oracle takes):
+ *   - reach set of an agent on cell c: cells c + (dx, dy) with
+ *     dx^2 + dy^2 <= v_m^2, inside the grid, not a wall, and free at the start
+ *     of the step; the agent's own cell is always a candidate;
+ *   - weight exp(k_S * (S(c) - S(t))) with S the static floor field (exact
+ *     8-neighbour distance to the nearest exit, orthogonal step 1, diagonal
+ *     step sqrt 2, no cutting of wall corners), S in cell units;
+ *   - candidates in raster order (dy outer, dx inner, from -v_m), sequential
+ *     prefix sum C, W = last C, u = (x0 >> 8) * 2^-24 with x0 word 0 of
+ *     Philox4x32-10 at counter (agent id, step, scenario id, 0) and key
+ *     (seed low word, seed high word); the choice is the first cell with
+ *     u * W < C;
+ *   - motion order: ascending (x0 at counter (id, step, scenario, 1), id);
+ *     each agent walks the DDA line to its cell, cell by cell, and stops
+ *     before a wall, an occupied cell or a diagonal step past a wall corner;
+ *     entering an exit removes it at once.
+ *   - seeded placement: partial Fisher-Yates over the eligible cells in raster
+ *     order with index k + ((x0 * (M - k)) >> 32), x0 at counter (k, 0, scn, 2).
+ *
+ * Results are bit-identical to a double-precision evaluation of these rules:
+ * the GPU draws in FP32 from a per-cell exp table and re-resolves, in FP64,
+ * every draw whose u*W lies within a guard band (>= 1e-6 * W, sized from the
+ * FP32 rounding bound) of a CDF boundary, and every agent on a grid tile whose
+ * floor-field range does not fit the FP32 table.
+ *
+ * Conventions
+ *   - Every function returns FAST_OK (0) or a negative status; nothing aborts
+ *     or throws across this boundary.  On error the state is unchanged and
+ *     fast_last_error() describes the cause (thread-local string).
+ *   - Host pointers are read during the call only and deep-copied; the caller
+ *     keeps ownership.  Device memory belongs to the context and comes from
+ *     the allocator given to fast_ctx_create (hipMalloc when NULL).
+ *   - Calls that launch work (plan, move, run) are asynchronous on the
+ *     context's HIP stream; calls that return state synchronise that stream.
+ *   - Cells are addressed row-major: index y * width + x.
+ *   - Limits: 3 <= width, height <= 16384; v_max in 1..5; at most 2^20 - 1
+ *     agents per scenario; at most FAST_MAX_SLOTS live scenarios per context.
+ */
+#ifndef FAST_H
+#define FAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fast_status;
+
+#define FAST_OK            0
+#define FAST_E_INVALID    (-1)   /* an argument or the scenario is invalid           */
+#define FAST_E_NOMEM      (-2)   /* host or device allocation failed                 */
+#define FAST_E_BUDGET     (-3)   /* the context's HBM budget would be exceeded       */
+#define FAST_E_DEVICE     (-4)   /* a HIP runtime call failed                        */
+#define FAST_E_STATE      (-5)   /* call not valid in the current state              */
+#define FAST_E_NOTFOUND   (-6)   /* unknown scenario handle or serving ticket        */
+
+#define FAST_CELL_FREE 0
+#define FAST_CELL_WALL 1
+#define FAST_CELL_EXIT 2
+
+#define FAST_MAX_SLOTS     4096
+#define FAST_MAX_AGENTS    1048575
+
+typedef struct fast_ctx fast_ctx;
+
+/* Device allocator hooks (e.g. PyTorch's caching allocator).  alloc returns a
+ * device pointer of at least `bytes` bytes aligned to 256 B, or NULL. */
+typedef void *(*fast_alloc_fn)(size_t bytes, void *user);
+typedef void (*fast_free_fn)(void *ptr, void *user);
+
+/* One scenario (Sec. 2 parameters plus the geometry the paper leaves open). */
+typedef struct {
+    int32_t width, height;       /* cells of 0.4 m                                   */
+    const uint8_t *cell_type;    /* host, width*height: 0 free, 1 wall, 2 exit;
+                                    free cells no exit reaches are treated as walls  */
+    int32_t n_agents;            /* agents, ids 0..n_agents-1                        */
+    const int32_t *agent_xy;     /* host, 2*n_agents (x, y) pairs, or NULL for the
+                                    seeded placement                                 */
+    int32_t v_max;               /* v_m, 1..5                                        */
+    double k_s;                  /* k_S >= 0 and finite (paper: 1.2)                 */
+    uint64_t seed;               /* Philox key                                       */
+    uint32_t scenario_id;        /* Philox counter word 2                            */
+    int32_t tile_w, tile_h;      /* planning tile in cells; 0, 0 = tuned choice;
+                                    otherwise powers of two in 8..64 with
+                                    tile_w * tile_h <= 1024                          */
+} fast_scenario_desc;
+
+/* Counters of one scenario. */
+typedef struct {
+    int32_t step;                /* steps completed (the next step's number)         */
+    int32_t n_agents;            /* agents at creation                               */
+    int32_t n_active;            /* agents still in the simulation                   */
+    int32_t exited;              /* agents that left through an exit                 */
+    int64_t flagged;             /* draws re-resolved in FP64 (near-tie band)        */
+    int64_t fallback;            /* draws resolved in FP64 on range-fallback tiles   */
+    int32_t last_rounds;         /* reservation rounds of the last motion phase      */
+    int32_t tile_w, tile_h;      /* planning tile in use                             */
+    int32_t n_tiles, n_fallback_tiles;
+    double guard_band;           /* relative half-width of the FP64 re-resolve band  */
+    int64_t device_bytes;        /* device memory held by the scenario               */
+} fast_stats;
+
+/* Creates a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = a non-blocking stream the context creates and owns).  hbm_budget caps the device bytes
+ * held by all scenarios of the context (0 = no cap).  alloc/free_fn may both
+ * be NULL (hipMalloc/hipFree). */
+fast_status fast_ctx_create(int device, void *hip_stream, size_t hbm_budget,
+                            fast_alloc_fn alloc, fast_free_fn free_fn, void *user,
+                            fast_ctx **out);
+
+/* Destroys all scenarios, stops serving and frees the context. */
+fast_status fast_ctx_destroy(fast_ctx *ctx);
+
+/* Builds a scenario on the host (validation, exact floor field, placement,
+ * per-tile FP32 exp table) and copies it to the device.  Step counter 0.
+ * Errors: FAST_E_INVALID for width/height < 3, v_max outside 1..5, k_s < 0 or
+ * not finite, no exit, an agent off-grid, on a wall/exit or sharing a cell,
+ * n_agents above the eligible cells or FAST_MAX_AGENTS; FAST_E_BUDGET when the
+ * device bytes exceed the budget; FAST_E_NOMEM, FAST_E_DEVICE. */
+fast_status fast_init_scenario(fast_ctx *ctx, const fast_scenario_desc *desc, int32_t *handle);
+
+/* Frees a scenario's device memory (after its queued work). */
+fast_status fast_destroy_scenario(fast_ctx *ctx, int32_t handle);
+
+/* One planning phase (Sec. 1 / Sec. 2: choose_desired_cell for every agent
+ * against the occupancy at the start of the step).  Writes the desired cells
+ * on the device; does not advance the step. */
+fast_status fast_plan_step(fast_ctx *ctx, int32_t handle);
+
+/* One motion phase (Sec. 1: agents move one after another in the step's
+ * priority order); advances the scenario's step counter.  Must follow a plan
+ * of the same step (FAST_E_STATE otherwise). */
+fast_status fast_move_step(fast_ctx *ctx, int32_t handle);
+
+/* `steps` full time steps (plan then move) of each of the n scenarios, which
+ * run as one batch: each step is one planning launch over the tiles of all
+ * scenarios and one motion launch, replayed from a captured HIP graph.  Every
+ * scenario keeps its own step counter.  n >= 1, steps >= 0. */
+fast_status fast_run(fast_ctx *ctx, const int32_t *handles, int32_t n, int32_t steps);
+
+/* Copies the state back (synchronises the stream).  Any pointer may be NULL.
+ * xy: 2*n_agents (x, y), (-1, -1) for agents that left; alive: n_agents;
+ * desired: n_agents cells y*width + x of the last plan (-1 when gone). */
+fast_status fast_get_state(fast_ctx *ctx, int32_t handle, int32_t *xy, uint8_t *alive,
+                           int32_t *desired, int32_t *step, int32_t *n_active);
+
+/* Counters of a scenario (synchronises the stream). */
+fast_status fast_get_stats(fast_ctx *ctx, int32_t handle, fast_stats *out);
+
+/* Debug planning phase: as fast_plan_step, and also returns, per agent id,
+ * w32[id * (2v+1)^2 + slot] = the FP32 weight e_t / e_c of each raster slot
+ * (0 outside the reach set; the FP64 weight rounded to FP32 on fallback
+ * tiles), flag[id] = 1 if the draw was re-resolved in FP64 (2 on a fallback
+ * tile), margin[id] = distance of u*W to the nearest CDF boundary over W.
+ * Host buffers sized for n_agents; any may be NULL.  Synchronises. */
+fast_status fast_debug_plan(fast_ctx *ctx, int32_t handle, float *w32, uint8_t *flag,
+                            float *margin);
+
+/* ---- Serving: continuous batching of scenario requests ------------------ */
+
+/* Starts the serving loop on a host thread of the context: requests are
+ * admitted as slots while the device bytes stay within `budget` (0 = the
+ * context's budget) and at most `max_active` scenarios run at once; each
+ * batch step covers all admitted scenarios; finished ones are retired and
+ * their results copied back. */
+fast_status fast_serve_start(fast_ctx *ctx, size_t budget, int32_t max_active);
+
+/* Queues a request for `steps` time steps of the scenario; returns a ticket.
+ * The descriptor's host arrays are copied during the call. */
+fast_status fast_serve_submit(fast_ctx *ctx, const fast_scenario_desc *desc, int32_t steps,
+                              uint64_t *ticket);
+
+/* done = 1 once the request has finished; latency_s = completion time minus
+ * submission time (seconds).  FAST_E_INVALID if the request was rejected. */
+fast_status fast_serve_poll(fast_ctx *ctx, uint64_t ticket, int32_t *done, double *latency_s);
+
+/* Final state of a finished request (as fast_get_state; n_agents sized). */
+fast_status fast_serve_result(fast_ctx *ctx, uint64_t ticket, int32_t *xy, uint8_t *alive,
+                              int32_t *step, int32_t *n_active);
+
+/* Stops admitting, finishes running requests, joins the thread. */
+fast_status fast_serve_stop(fast_ctx *ctx);
+
+/* ---- Host-only helpers (no device work) --------------------------------- */
+
+/* The static floor field exactly as fast_init_scenario computes it: type_out
+ * (width*height) receives the cell types with unreachable free cells turned
+ * into walls, S_out (width*height) the exact walking distance to the nearest
+ * exit rounded to double (+inf on walls).  FAST_E_INVALID on bad sizes/types. */
+fast_status fast_floor_field(int32_t width, int32_t height, const uint8_t *cell_type,
+                             uint8_t *type_out, double *S_out);
+
+/* The seeded placement of fast_init_scenario (agent_xy == NULL): xy_out gets
+ * 2*n_agents (x, y).  cell_type is the raw grid; FAST_E_INVALID if n_agents
+ * exceeds the eligible cells. */
+fast_status fast_place(int32_t width, int32_t height, const uint8_t *cell_type, int32_t n_agents,
+                       uint64_t seed, uint32_t scenario_id, int32_t *xy_out);
+
+/* Relative half-width of the FP64 re-resolve band used for v_max. */
+double fast_guard_band(int32_t v_max);
+
+/* Thread-local description of the last error (never NULL). */
+const char *fast_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FAST_H */

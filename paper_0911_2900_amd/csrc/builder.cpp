@@ -1,0 +1,262 @@
+// builder.cpp -- host-side scenario setup for libfast: validation, the exact
+// static floor field, seeded placement, the padded grid, and the per-tile
+// FP32 exp table with its fallback flags.
+//
+// Floor field (paper Sec. 2 fixes k_S and the exp coupling; the field itself
+// is the model's static distance-to-exit potential): shortest walking length
+// from the nearest exit cell over the 8-neighbour stencil, orthogonal step 1,
+// diagonal step sqrt 2, a diagonal allowed only when both orthogonal
+// neighbours are not walls.  Lengths are kept exactly as a + b sqrt 2 with
+// integers a, b -- sqrt 2 is irrational, so the shortest pair of a cell is
+// unique -- and S = fl(fl(b * sqrt2) + a), a value that does not depend on the
+// order in which the search visits cells.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "fast_dev.h"
+#include "fast_host.h"
+
+namespace fh {
+
+namespace {
+
+constexpr double kSqrt2 = 0x1.6a09e667f3bcdp+0;   // nearest double to sqrt 2
+constexpr double kLn2 = 0x1.62e42fefa39efp-1;     // nearest double to ln 2
+constexpr double kRange = 80.0;                   // |exponent| bound of a table entry
+
+// Sign of p + q sqrt 2 for integers p, q.
+int sign_z2(int64_t p, int64_t q)
+{
+    if (q == 0) return (p > 0) - (p < 0);
+    if (p == 0) return (q > 0) - (q < 0);
+    if ((p > 0) == (q > 0)) return p > 0 ? 1 : -1;
+    const int64_t pp = p * p, qq = 2 * q * q;     // opposite signs: compare magnitudes
+    if (p > 0) return pp > qq ? 1 : -1;
+    return pp > qq ? -1 : 1;
+}
+
+struct Len {
+    int64_t a = -1, b = -1;                       // a + b sqrt 2; a < 0 = unreached
+    bool reached() const { return a >= 0; }
+};
+
+bool shorter(const Len &x, const Len &y) { return sign_z2(x.a - y.a, x.b - y.b) < 0; }
+
+struct QItem {
+    Len len;
+    int32_t cell;
+};
+struct QAfter {
+    bool operator()(const QItem &x, const QItem &y) const
+    {
+        if (shorter(y.len, x.len)) return true;
+        if (shorter(x.len, y.len)) return false;
+        return x.cell > y.cell;
+    }
+};
+
+}  // namespace
+
+// Exact floor field on the unpadded grid; unreachable free cells become walls.
+void floor_field(int W, int H, std::vector<uint8_t> &type, std::vector<double> &S)
+{
+    const int64_t n = (int64_t)W * H;
+    std::vector<Len> L((size_t)n);
+    std::vector<char> settled((size_t)n, 0);
+    std::priority_queue<QItem, std::vector<QItem>, QAfter> q;
+    for (int64_t i = 0; i < n; ++i)
+        if (type[i] == fk::CELL_EXIT) {
+            L[i].a = 0;
+            L[i].b = 0;
+            q.push({L[i], (int32_t)i});
+        }
+    static const int ddx[8] = {1, -1, 0, 0, 1, 1, -1, -1};
+    static const int ddy[8] = {0, 0, 1, -1, 1, -1, 1, -1};
+    while (!q.empty()) {
+        const QItem it = q.top();
+        q.pop();
+        const int32_t c = it.cell;
+        if (settled[c] || it.len.a != L[c].a || it.len.b != L[c].b) continue;
+        settled[c] = 1;
+        const int cx = c % W, cy = c / W;
+        for (int k = 0; k < 8; ++k) {
+            const int nx = cx + ddx[k], ny = cy + ddy[k];
+            if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+            const int64_t t = (int64_t)ny * W + nx;
+            if (type[t] == fk::CELL_WALL || settled[t]) continue;
+            Len cand = L[c];
+            if (k >= 4) {
+                if (type[(int64_t)cy * W + nx] == fk::CELL_WALL ||
+                    type[(int64_t)ny * W + cx] == fk::CELL_WALL)
+                    continue;
+                cand.b += 1;
+            } else {
+                cand.a += 1;
+            }
+            if (!L[t].reached() || shorter(cand, L[t])) {
+                L[t] = cand;
+                q.push({cand, (int32_t)t});
+            }
+        }
+    }
+    S.assign((size_t)n, INFINITY);
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] == fk::CELL_FREE && !L[i].reached()) type[i] = fk::CELL_WALL;
+        if (type[i] != fk::CELL_WALL) {
+            const double bs = (double)L[i].b * kSqrt2;
+            S[i] = bs + (double)L[i].a;
+        }
+    }
+}
+
+// Seeded placement: partial Fisher-Yates over the eligible cells (free and
+// reachable) in raster order, index k + ((x0 * (M - k)) >> 32) with x0 word 0
+// of Philox at counter (k, 0, scenario, 2).
+bool place(int W, int H, const std::vector<uint8_t> &type, int n, uint64_t seed, uint32_t scn,
+           std::vector<int32_t> &xy)
+{
+    std::vector<int32_t> cells;
+    cells.reserve((size_t)W * H);
+    for (int64_t i = 0; i < (int64_t)W * H; ++i)
+        if (type[i] == fk::CELL_FREE) cells.push_back((int32_t)i);
+    const int64_t M = (int64_t)cells.size();
+    if (n > M) return false;
+    xy.resize((size_t)2 * n);
+    for (int k = 0; k < n; ++k) {
+        const uint32_t r = fk::philox_word0((uint32_t)k, 0u, scn, fk::STREAM_PLACE, (uint32_t)seed,
+                                            (uint32_t)(seed >> 32));
+        const int64_t j = k + (int64_t)(((uint64_t)r * (uint64_t)(M - k)) >> 32);
+        std::swap(cells[k], cells[j]);
+        xy[2 * k] = cells[k] % W;
+        xy[2 * k + 1] = cells[k] / W;
+    }
+    return true;
+}
+
+// Rounding-depth bound of the FP32 CDF: rows are pairwise sums (depth
+// ceil(log2(2v+1))), row prefixes and in-row prefixes sequential; a CDF value
+// and W each carry at most d + 1 roundings (d additions plus the table entry),
+// tau one more.  A draw whose |tau - C| exceeds (d_W + d_C + 3) u W decides
+// the same way in exact arithmetic; the band adds 25 % and is never below the
+// 1e-6 W the method asks for (1.01e-6, so that the float band and its product
+// with W stay above 1e-6 W after rounding).
+float guard_band(int v)
+{
+    int dR = 0;
+    while ((1 << dR) < 2 * v + 1) ++dR;
+    const int d = dR + 2 * v;
+    const double band = 1.25 * (2.0 * d + 3.0) * 0x1p-24;
+    return (float)std::max(1.01e-6, band);
+}
+
+int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::string &err)
+{
+    const int W = d.width, H = d.height, v = d.v_max;
+    b = Built();
+    b.W = W; b.H = H; b.v = v; b.tx = tx; b.ty = ty;
+    std::vector<uint8_t> type(d.cell_type, d.cell_type + (size_t)W * H);
+    bool any_exit = false;
+    for (uint8_t t : type) {
+        if (t > fk::CELL_EXIT) { err = "cell_type values must be 0, 1 or 2"; return FAST_E_INVALID; }
+        any_exit = any_exit || t == fk::CELL_EXIT;
+    }
+    if (!any_exit) { err = "the grid has no exit cell"; return FAST_E_INVALID; }
+
+    std::vector<double> S;
+    floor_field(W, H, type, S);
+
+    std::vector<int32_t> xy;
+    if (d.agent_xy) {
+        xy.assign(d.agent_xy, d.agent_xy + (size_t)2 * d.n_agents);
+        std::vector<char> used((size_t)W * H, 0);
+        for (int i = 0; i < d.n_agents; ++i) {
+            const int x = xy[2 * i], y = xy[2 * i + 1];
+            if (x < 0 || y < 0 || x >= W || y >= H) { err = "an agent lies off the grid"; return FAST_E_INVALID; }
+            const int64_t c = (int64_t)y * W + x;
+            if (type[c] != fk::CELL_FREE) { err = "an agent stands on a wall, an exit or an unreachable cell"; return FAST_E_INVALID; }
+            if (used[c]) { err = "two agents share a cell"; return FAST_E_INVALID; }
+            used[c] = 1;
+        }
+    } else if (!place(W, H, type, d.n_agents, d.seed, d.scenario_id, xy)) {
+        err = "more agents than eligible cells";
+        return FAST_E_INVALID;
+    }
+
+    // padded layout
+    b.ntx = (W + tx - 1) / tx;
+    b.nty = (H + ty - 1) / ty;
+    b.Wp = b.ntx * tx + 2 * v;
+    b.Hp = b.nty * ty + 2 * v;
+    const int64_t np = (int64_t)b.Wp * b.Hp;
+    b.type.assign((size_t)np, fk::CELL_WALL);
+    b.S.assign((size_t)np, INFINITY);
+    b.G.assign((size_t)np, 0.0f);
+    b.occ.assign((size_t)np, -1);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const int64_t g = (int64_t)(y + v) * b.Wp + (x + v);
+            b.type[g] = type[(int64_t)y * W + x];
+            b.S[g] = S[(int64_t)y * W + x];
+        }
+    b.n = d.n_agents;
+    b.pos.resize((size_t)b.n);
+    for (int i = 0; i < b.n; ++i) {
+        const int64_t g = (int64_t)(xy[2 * i + 1] + v) * b.Wp + (xy[2 * i] + v);
+        b.pos[i] = (int32_t)g;
+        b.occ[g] = i;
+    }
+
+    // per-tile scale m_T from the midpoint of k_S S over the tile's window
+    const double ks = d.k_s;
+    const int ts = b.ntx + 2;
+    b.tile_m.assign((size_t)ts * (b.nty + 2), 0);
+    std::vector<int32_t> mcell((size_t)np, 0);
+    for (int j = 0; j < b.nty; ++j)
+        for (int i = 0; i < b.ntx; ++i) {
+            double lo = INFINITY, hi = -INFINITY;
+            for (int y = j * ty; y < j * ty + ty + 2 * v; ++y)
+                for (int x = i * tx; x < i * tx + tx + 2 * v; ++x) {
+                    const double s = b.S[(int64_t)y * b.Wp + x];
+                    if (std::isfinite(s)) { lo = std::min(lo, s); hi = std::max(hi, s); }
+                }
+            int32_t m = 0;
+            if (lo <= hi) m = (int32_t)std::llround(ks * 0.5 * (lo + hi) / kLn2);
+            b.tile_m[(size_t)(j + 1) * ts + i + 1] = m;
+            for (int y = j * ty + v; y < j * ty + ty + v; ++y)
+                for (int x = i * tx + v; x < i * tx + tx + v; ++x) mcell[(int64_t)y * b.Wp + x] = m;
+        }
+    // table entries in the scale of their own tile
+    std::vector<char> cell_ok((size_t)np, 1);
+    for (int64_t g = 0; g < np; ++g) {
+        const double s = b.S[g];
+        if (!std::isfinite(s)) continue;
+        const double ex = (double)mcell[g] * kLn2 - ks * s;
+        if (std::fabs(ex) > kRange) { cell_ok[g] = 0; continue; }
+        b.G[g] = (float)std::exp(ex);
+    }
+    // fallback tiles: some window cell outside [e^-80, e^80] in the tile's scale
+    b.tile_fb.assign((size_t)b.ntx * b.nty, 0);
+    b.n_fb = 0;
+    for (int j = 0; j < b.nty; ++j)
+        for (int i = 0; i < b.ntx; ++i) {
+            const int32_t m = b.tile_m[(size_t)(j + 1) * ts + i + 1];
+            bool ok = true;
+            for (int y = j * ty; ok && y < j * ty + ty + 2 * v; ++y)
+                for (int x = i * tx; x < i * tx + tx + 2 * v; ++x) {
+                    const int64_t g = (int64_t)y * b.Wp + x;
+                    const double s = b.S[g];
+                    if (!std::isfinite(s)) continue;
+                    if (!cell_ok[g] || std::fabs((double)m * kLn2 - ks * s) > kRange) { ok = false; break; }
+                }
+            if (!ok) { b.tile_fb[(size_t)j * b.ntx + i] = 1; ++b.n_fb; }
+        }
+    b.eps = guard_band(v);
+    return FAST_OK;
+}
+
+}  // namespace fh

@@ -1,0 +1,111 @@
+// fast_dev.h -- data layout shared by libfast's host runtime and its gfx950
+// kernels: the per-scenario slot descriptor, counters, and Philox4x32-10.
+//
+// Layout of one scenario (a "slot") in HBM.  The grid is padded by v cells of
+// wall on every side and rounded up to whole planning tiles, so that a tile's
+// (tx + 2v) x (ty + 2v) window never needs a bounds check:
+//   padded width  Wp = ntx * tx + 2v,  padded height Hp = nty * ty + 2v,
+//   cell (x, y) of the scenario lives at index (y + v) * Wp + (x + v).
+// Per cell:  type u8 (static), G f32 (static exp table, see below),
+//            S f64 (static floor field, read only by the FP64 re-resolve),
+//            occ i32 (agent id or -1), res u64 (motion reservations).
+// Per agent: pos i32 (padded cell, -1 once gone), desired i32, a pending id
+//            and two reservation-key lists for the motion rounds.
+// Per tile:  m i32 (power-of-two scale of the exp table), fallback u8.
+//
+// Exp table: G(t) = fl32(exp(m_T(t) ln 2 - k_S S(t))) where T(t) is the tile
+// holding t.  A tile T staging a halo cell t of tile T' rescales it by
+// 2^(m_T - m_T'), which is exact, so every value an agent of T sees equals
+// fl32(exp(-k_S (S(t) - beta_T))) with beta_T = m_T ln 2 / k_S.  The weight
+// ratio e_t / e_c is then exp(k_S (S(c) - S(t))) to within 2 roundings.
+// Tiles whose window does not fit [e^-80, e^80] are "fallback" tiles: their
+// agents are drawn directly in FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fk {
+
+enum : int { CELL_FREE = 0, CELL_WALL = 1, CELL_EXIT = 2 };
+
+constexpr int MAX_V = 5;
+constexpr int MAX_TILE_CELLS = 1024;   // tx * ty
+constexpr int MAX_STAGE = 2048;        // (tx + 2v)(ty + 2v) over the allowed tiles
+constexpr int PLAN_THREADS = 256;
+constexpr int MOVE_THREADS = 1024;
+
+// Motion reservation words: [tag:12][~x0:32][~id:20]; the largest word on a
+// cell is the earliest agent of the current round (tags grow every round).
+constexpr int ID_BITS = 20;
+constexpr uint32_t ID_MASK = (1u << ID_BITS) - 1u;
+constexpr int TAG_SHIFT = 52;
+constexpr uint32_t TAG_LIMIT = 4095u;
+
+// int32 counters per slot
+enum : int {
+    C_STEP = 0,      // steps completed
+    C_NACTIVE = 1,   // agents still present
+    C_EXITED = 2,    // agents that left
+    C_PEND = 3,      // movers appended by the last plan
+    C_TAG = 4,       // last reservation tag used
+    C_ROUNDS = 5,    // reservation rounds of the last motion phase
+    C_LIMIT = 6,     // kernels act while step < limit
+    C_NCTR = 8
+};
+// uint64 statistics per slot
+enum : int { S_FLAGGED = 0, S_FALLBACK = 1, S_NSTAT = 4 };
+
+struct SlotDev {
+    int32_t W, H;            // scenario size
+    int32_t Wp, Hp;          // padded size
+    int32_t v;               // v_m; also the pad width
+    int32_t tx, ty;          // planning tile
+    int32_t ntx, nty;        // tiles per row / column
+    int32_t n_agents;
+    uint32_t seed_lo, seed_hi, scn;
+    float eps;               // guard band, relative to W
+    double k_s;
+    const uint8_t *type;     // Wp*Hp
+    const float *G;          // Wp*Hp
+    const double *S;         // Wp*Hp
+    const int32_t *tile_m;   // (ntx+2)*(nty+2), a ring of zeros around
+    const uint8_t *tile_fb;  // ntx*nty
+    int32_t *occ;            // Wp*Hp
+    unsigned long long *res; // Wp*Hp
+    int32_t *pos;            // n_agents
+    int32_t *desired;        // n_agents
+    int32_t *pend;           // n_agents
+    unsigned long long *keys_a, *keys_b;  // n_agents each
+    int32_t *ctr;            // C_NCTR
+    unsigned long long *stat;// S_NSTAT
+    float *dbg_w;            // optional debug outputs (null in normal runs)
+    uint8_t *dbg_flag;
+    float *dbg_margin;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), word 0 of the output
+// block for counter (c0, c1, c2, c3) and key (k0, k1).
+__host__ __device__ inline uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c0;
+}
+
+// Philox streams (counter word 3)
+enum : uint32_t { STREAM_PLAN = 0, STREAM_ORDER = 1, STREAM_PLACE = 2 };
+
+}  // namespace fk

@@ -1,0 +1,44 @@
+// fast_host.h -- host-side pieces of libfast shared by builder.cpp and
+// runtime.cpp: the built scenario and the kernel launchers of kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fast.h"
+#include "fast_dev.h"
+
+namespace fh {
+
+// A scenario laid out for the device (see fast_dev.h for the layout).
+struct Built {
+    int W = 0, H = 0, v = 0, tx = 0, ty = 0, ntx = 0, nty = 0, Wp = 0, Hp = 0;
+    std::vector<uint8_t> type;     // padded
+    std::vector<float> G;          // padded exp table
+    std::vector<double> S;         // padded floor field
+    std::vector<int32_t> tile_m;   // (ntx+2)*(nty+2)
+    std::vector<uint8_t> tile_fb;  // ntx*nty
+    std::vector<int32_t> occ;      // padded
+    std::vector<int32_t> pos;      // padded cell per agent
+    int n = 0;
+    int n_fb = 0;
+    float eps = 0.0f;
+};
+
+void floor_field(int W, int H, std::vector<uint8_t> &type, std::vector<double> &S);
+bool place(int W, int H, const std::vector<uint8_t> &type, int n, uint64_t seed, uint32_t scn,
+           std::vector<int32_t> &xy);
+float guard_band(int v);
+int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::string &err);
+
+}  // namespace fh
+
+extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
+                                     int debug, hipStream_t stream);
+extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const int32_t *slots, int n_slots,
+                                     hipStream_t stream);
+extern "C" hipError_t fk_launch_reset(const fk::SlotDev *table, const int32_t *slots, int n_slots,
+                                      hipStream_t stream);

@@ -1,0 +1,828 @@
+// runtime.cpp -- libfast's host runtime and C-ABI (include/fast.h): contexts,
+// scenario slots in HBM, single-scenario plan / move launches, batched runs
+// replayed from captured HIP graphs, and the continuous-batching server.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "fast_dev.h"
+#include "fast_host.h"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+fast_status fail(fast_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(FAST_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Slot {
+    bool live = false;
+    fk::SlotDev dev{};           // host copy of the device descriptor
+    void *block = nullptr;       // one allocation holding all of the slot's buffers
+    size_t bytes = 0;
+    uint32_t *items = nullptr;   // device: plan work items of this slot alone
+    int32_t *self = nullptr;     // device: [slot index]
+    int n_items = 0;
+    int n_fb_tiles = 0;
+    int host_steps = 0;          // steps launched (== device step once the stream drains)
+    bool planned = false;        // a plan was launched after the last motion phase
+    int n_agents = 0;
+};
+
+struct Batch {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    uint32_t *items = nullptr;
+    int32_t *slots = nullptr;
+    void *block = nullptr;
+    size_t bytes = 0;
+    std::vector<int32_t> members;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    fast_scenario_desc desc{};
+    std::vector<uint8_t> cells;
+    std::vector<int32_t> xy;
+    int steps = 0;
+    double t_submit = 0, t_done = 0;
+    int state = 0;               // 0 queued, 1 running, 2 done, -1 rejected
+    int32_t handle = -1;
+    std::vector<int32_t> out_xy;
+    std::vector<uint8_t> out_alive;
+    int32_t out_step = 0, out_active = 0;
+};
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct fast_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0, used = 0;
+    fast_alloc_fn alloc = nullptr;
+    fast_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    fk::SlotDev *table = nullptr;    // device, FAST_MAX_SLOTS entries
+    std::vector<Slot> slots;
+    std::map<std::vector<int32_t>, Batch> batches;
+    std::recursive_mutex mu;         // guards everything above
+
+    // serving
+    std::thread server;
+    std::mutex smu;
+    std::condition_variable scv;
+    bool serving = false, stopping = false;
+    size_t serve_budget = 0;
+    int serve_max_active = 0;
+    uint64_t next_ticket = 1;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+};
+
+namespace {
+
+fast_status dev_alloc(fast_ctx *c, size_t bytes, void **out)
+{
+    bytes = align_up(std::max<size_t>(bytes, 256), 256);
+    if (c->budget && c->used + bytes > c->budget)
+        return fail(FAST_E_BUDGET, "device budget exceeded: %zu + %zu > %zu bytes", c->used, bytes,
+                    c->budget);
+    void *p = nullptr;
+    if (c->alloc) {
+        p = c->alloc(bytes, c->user);
+        if (!p) return fail(FAST_E_NOMEM, "allocator returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) return fail(FAST_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    c->used += bytes;
+    *out = p;
+    return FAST_OK;
+}
+
+void dev_free(fast_ctx *c, void *p, size_t bytes)
+{
+    if (!p) return;
+    bytes = align_up(std::max<size_t>(bytes, 256), 256);
+    if (c->free_fn) c->free_fn(p, c->user);
+    else (void)hipFree(p);
+    c->used -= std::min(c->used, bytes);
+}
+
+// Planning tile when the descriptor leaves it open: the largest tile that
+// still gives the launch at least ~2 workgroups per compute unit on the grid,
+// so that small scenarios fill the chip while large ones keep the halo
+// (re-staged cells) small.
+void choose_tile(int W, int H, int v, int *tx, int *ty)
+{
+    static const int cand[][2] = {{32, 32}, {32, 16}, {16, 16}, {16, 8}, {8, 8}};
+    for (auto &c : cand) {
+        const long tiles = (long)((W + c[0] - 1) / c[0]) * ((H + c[1] - 1) / c[1]);
+        if (tiles >= 512) { *tx = c[0]; *ty = c[1]; return; }
+    }
+    (void)v;
+    *tx = 8;
+    *ty = 8;
+}
+
+bool valid_tile_dim(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
+
+fast_status check_desc(const fast_scenario_desc *d)
+{
+    if (!d) return fail(FAST_E_INVALID, "descriptor is NULL");
+    if (d->width < 3 || d->height < 3 || d->width > 16384 || d->height > 16384)
+        return fail(FAST_E_INVALID, "grid %dx%d outside 3..16384", d->width, d->height);
+    if (!d->cell_type) return fail(FAST_E_INVALID, "cell_type is NULL");
+    if (d->v_max < 1 || d->v_max > fk::MAX_V)
+        return fail(FAST_E_INVALID, "v_max %d outside 1..5", d->v_max);
+    if (!(d->k_s >= 0.0) || !std::isfinite(d->k_s))
+        return fail(FAST_E_INVALID, "k_s must be finite and >= 0");
+    if (d->n_agents < 0 || d->n_agents > FAST_MAX_AGENTS)
+        return fail(FAST_E_INVALID, "n_agents %d outside 0..%d", d->n_agents, FAST_MAX_AGENTS);
+    if (d->tile_w || d->tile_h) {
+        if (!valid_tile_dim(d->tile_w) || !valid_tile_dim(d->tile_h) || d->tile_w * d->tile_h > 1024)
+            return fail(FAST_E_INVALID, "tile %dx%d: powers of two in 8..64, at most 1024 cells",
+                        d->tile_w, d->tile_h);
+    }
+    return FAST_OK;
+}
+
+Slot *get_slot(fast_ctx *c, int32_t h)
+{
+    if (h < 0 || h >= (int32_t)c->slots.size() || !c->slots[h].live) return nullptr;
+    return &c->slots[h];
+}
+
+void drop_batches_with(fast_ctx *c, int32_t h)
+{
+    for (auto it = c->batches.begin(); it != c->batches.end();) {
+        if (std::find(it->first.begin(), it->first.end(), h) != it->first.end()) {
+            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+            if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
+            dev_free(c, it->second.block, it->second.bytes);
+            it = c->batches.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// Builds a scenario into a free slot; `limit` is the step at which its kernels
+// stop acting (INT_MAX for scenarios stepped by the caller).
+fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32_t *handle)
+{
+    fast_status st = check_desc(d);
+    if (st) return st;
+    int tx = d->tile_w, ty = d->tile_h;
+    if (!tx) choose_tile(d->width, d->height, d->v_max, &tx, &ty);
+
+    fh::Built b;
+    std::string err;
+    st = fh::build_scenario(*d, tx, ty, b, err);
+    if (st) return fail(st, "%s", err.c_str());
+
+    int32_t h = -1;
+    for (int32_t i = 0; i < (int32_t)c->slots.size(); ++i)
+        if (!c->slots[i].live) { h = i; break; }
+    if (h < 0) {
+        if ((int)c->slots.size() >= FAST_MAX_SLOTS)
+            return fail(FAST_E_STATE, "all %d scenario slots are in use", FAST_MAX_SLOTS);
+        c->slots.emplace_back();
+        h = (int32_t)c->slots.size() - 1;
+    }
+
+    const size_t cells = (size_t)b.Wp * b.Hp;
+    const size_t n = (size_t)std::max(b.n, 1);
+    const size_t ntiles = (size_t)b.ntx * b.nty;
+    const size_t tm = (size_t)(b.ntx + 2) * (b.nty + 2);
+    // carve one block: 256-byte aligned sub-buffers
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t o_S = take(cells * 8), o_res = take(cells * 8), o_G = take(cells * 4),
+                 o_occ = take(cells * 4), o_type = take(cells), o_tm = take(tm * 4),
+                 o_fb = take(ntiles), o_pos = take(n * 4), o_des = take(n * 4),
+                 o_pend = take(n * 4), o_ka = take(n * 8), o_kb = take(n * 8),
+                 o_ctr = take(fk::C_NCTR * 4), o_stat = take(fk::S_NSTAT * 8),
+                 o_items = take(ntiles * 4), o_self = take(4);
+    void *block = nullptr;
+    st = dev_alloc(c, off, &block);
+    if (st) return st;
+    char *base = (char *)block;
+
+    fk::SlotDev sd{};
+    sd.W = b.W; sd.H = b.H; sd.Wp = b.Wp; sd.Hp = b.Hp; sd.v = b.v;
+    sd.tx = b.tx; sd.ty = b.ty; sd.ntx = b.ntx; sd.nty = b.nty; sd.n_agents = b.n;
+    sd.seed_lo = (uint32_t)d->seed; sd.seed_hi = (uint32_t)(d->seed >> 32);
+    sd.scn = d->scenario_id; sd.eps = b.eps; sd.k_s = d->k_s;
+    sd.S = (const double *)(base + o_S);
+    sd.res = (unsigned long long *)(base + o_res);
+    sd.G = (const float *)(base + o_G);
+    sd.occ = (int32_t *)(base + o_occ);
+    sd.type = (const uint8_t *)(base + o_type);
+    sd.tile_m = (const int32_t *)(base + o_tm);
+    sd.tile_fb = (const uint8_t *)(base + o_fb);
+    sd.pos = (int32_t *)(base + o_pos);
+    sd.desired = (int32_t *)(base + o_des);
+    sd.pend = (int32_t *)(base + o_pend);
+    sd.keys_a = (unsigned long long *)(base + o_ka);
+    sd.keys_b = (unsigned long long *)(base + o_kb);
+    sd.ctr = (int32_t *)(base + o_ctr);
+    sd.stat = (unsigned long long *)(base + o_stat);
+
+    std::vector<int32_t> ctr(fk::C_NCTR, 0);
+    ctr[fk::C_NACTIVE] = b.n;
+    ctr[fk::C_LIMIT] = limit;
+    std::vector<uint32_t> items(ntiles);
+    for (size_t i = 0; i < ntiles; ++i) items[i] = ((uint32_t)h << 20) | (uint32_t)i;
+    const int32_t self = h;
+
+    hipError_t e = hipSuccess;
+    auto cp = [&](size_t o, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice);
+    };
+    cp(o_S, b.S.data(), cells * 8);
+    if (e == hipSuccess) e = hipMemset(base + o_res, 0, cells * 8);
+    cp(o_G, b.G.data(), cells * 4);
+    cp(o_occ, b.occ.data(), cells * 4);
+    cp(o_type, b.type.data(), cells);
+    cp(o_tm, b.tile_m.data(), tm * 4);
+    cp(o_fb, b.tile_fb.data(), ntiles);
+    cp(o_pos, b.pos.data(), (size_t)b.n * 4);
+    cp(o_des, b.pos.data(), (size_t)b.n * 4);          // desired = own cell until planned
+    cp(o_ctr, ctr.data(), fk::C_NCTR * 4);
+    if (e == hipSuccess) e = hipMemset(base + o_stat, 0, fk::S_NSTAT * 8);
+    cp(o_items, items.data(), ntiles * 4);
+    cp(o_self, &self, 4);
+    if (e == hipSuccess) e = hipMemcpy(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dev_free(c, block, off);
+        return fail(FAST_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+
+    Slot &s = c->slots[h];
+    s = Slot();
+    s.live = true;
+    s.dev = sd;
+    s.block = block;
+    s.bytes = off;
+    s.items = (uint32_t *)(base + o_items);
+    s.self = (int32_t *)(base + o_self);
+    s.n_items = (int)ntiles;
+    s.n_fb_tiles = b.n_fb;
+    s.n_agents = b.n;
+    *handle = h;
+    return FAST_OK;
+}
+
+fast_status destroy_slot(fast_ctx *c, int32_t h)
+{
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    drop_batches_with(c, h);
+    dev_free(c, s->block, s->bytes);
+    *s = Slot();
+    return FAST_OK;
+}
+
+fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_t *desired,
+                       int32_t *step, int32_t *n_active)
+{
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int n = s->n_agents;
+    std::vector<int32_t> pos((size_t)std::max(n, 1)), des((size_t)std::max(n, 1)), ctr(fk::C_NCTR);
+    HIP_TRY(hipMemcpy(ctr.data(), s->dev.ctr, fk::C_NCTR * 4, hipMemcpyDeviceToHost));
+    if (n) {
+        HIP_TRY(hipMemcpy(pos.data(), s->dev.pos, (size_t)n * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(des.data(), s->dev.desired, (size_t)n * 4, hipMemcpyDeviceToHost));
+    }
+    const int Wp = s->dev.Wp, v = s->dev.v, W = s->dev.W;
+    for (int i = 0; i < n; ++i) {
+        const int p = pos[i];
+        if (xy) {
+            xy[2 * i] = p < 0 ? -1 : p % Wp - v;
+            xy[2 * i + 1] = p < 0 ? -1 : p / Wp - v;
+        }
+        if (alive) alive[i] = p >= 0 ? 1 : 0;
+        if (desired) {
+            const int q = des[i];
+            desired[i] = (p < 0 || q < 0) ? -1 : (q / Wp - v) * W + (q % Wp - v);
+        }
+    }
+    if (step) *step = ctr[fk::C_STEP];
+    if (n_active) *n_active = ctr[fk::C_NACTIVE];
+    return FAST_OK;
+}
+
+fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
+{
+    auto it = c->batches.find(hs);
+    if (it != c->batches.end()) { *out = &it->second; return FAST_OK; }
+    // work items: all tiles of all members; the larger scenarios first so
+    // their tiles start early on the hardware queue
+    std::vector<int32_t> order(hs);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return c->slots[a].n_agents > c->slots[b].n_agents;
+    });
+    std::vector<uint32_t> items;
+    for (int32_t h : order) {
+        const Slot &s = c->slots[h];
+        for (int i = 0; i < s.n_items; ++i) items.push_back(((uint32_t)h << 20) | (uint32_t)i);
+    }
+    Batch b;
+    b.members = hs;
+    const size_t ib = align_up(items.size() * 4, 256);
+    b.bytes = ib + order.size() * 4;
+    fast_status st = dev_alloc(c, b.bytes, &b.block);
+    if (st) return st;
+    b.items = (uint32_t *)b.block;
+    b.slots = (int32_t *)((char *)b.block + ib);
+    HIP_TRY(hipMemcpy(b.items, items.data(), items.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b.slots, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+
+    // capture one time step: one planning launch over every tile, one motion
+    // launch with a workgroup per scenario
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = fk_launch_plan(c->table, b.items, (int)items.size(), 0, c->stream);
+    hipError_t e2 = fk_launch_move(c->table, b.slots, (int)order.size(), c->stream);
+    hipError_t e3 = hipStreamEndCapture(c->stream, &b.graph);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        if (b.graph) (void)hipGraphDestroy(b.graph);
+        dev_free(c, b.block, b.bytes);
+        return fail(FAST_E_DEVICE, "graph capture failed: %s / %s / %s", hipGetErrorString(e1),
+                    hipGetErrorString(e2), hipGetErrorString(e3));
+    }
+    hipError_t e4 = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+    if (e4 != hipSuccess) {
+        (void)hipGraphDestroy(b.graph);
+        dev_free(c, b.block, b.bytes);
+        return fail(FAST_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e4));
+    }
+    auto res = c->batches.emplace(hs, b);
+    *out = &res.first->second;
+    return FAST_OK;
+}
+
+fast_status run_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
+{
+    for (int32_t h : hs) {
+        Slot *s = get_slot(c, h);
+        if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+        if (s->planned) return fail(FAST_E_STATE, "scenario %d has a plan without its motion phase", h);
+    }
+    if (steps == 0) return FAST_OK;
+    Batch *b = nullptr;
+    fast_status st = get_batch(c, hs, &b);
+    if (st) return st;
+    for (int k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(b->exec, c->stream));
+    for (int32_t h : hs) c->slots[h].host_steps += steps;
+    return FAST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving: a host thread admits queued requests as slots while the budget and
+// the active cap allow, advances every active scenario by one batched step
+// per iteration, retires finished ones, and records completion times.
+// ---------------------------------------------------------------------------
+void serve_loop(fast_ctx *c)
+{
+    std::vector<uint64_t> active;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(c->smu);
+            if (active.empty()) {
+                c->scv.wait(lk, [&] { return c->stopping || !c->queue.empty(); });
+                if (c->stopping && c->queue.empty()) break;
+            }
+        }
+        // admit
+        for (;;) {
+            uint64_t t = 0;
+            Request *r = nullptr;
+            {
+                std::lock_guard<std::mutex> lk(c->smu);
+                if (c->queue.empty()) break;
+                if (c->serve_max_active && (int)active.size() >= c->serve_max_active) break;
+                t = c->queue.front();
+                r = c->reqs[t].get();
+            }
+            std::lock_guard<std::recursive_mutex> g(c->mu);
+            const size_t saved = c->budget;
+            if (c->serve_budget) c->budget = c->serve_budget;
+            int32_t h = -1;
+            fast_status st = init_slot(c, &r->desc, r->steps, &h);
+            c->budget = saved;
+            if (st == FAST_E_BUDGET && !active.empty()) break;      // wait for memory
+            std::lock_guard<std::mutex> lk(c->smu);
+            c->queue.pop_front();
+            if (st) { r->state = -1; r->t_done = now_s(); continue; }
+            r->handle = h;
+            r->state = 1;
+            active.push_back(t);
+        }
+        if (active.empty()) continue;
+        // one batched step over the active scenarios
+        std::vector<int32_t> hs;
+        {
+            std::lock_guard<std::mutex> lk(c->smu);
+            for (uint64_t t : active) hs.push_back(c->reqs[t]->handle);
+        }
+        std::sort(hs.begin(), hs.end());
+        int chunk = INT_MAX;
+        {
+            std::lock_guard<std::mutex> lk(c->smu);
+            for (uint64_t t : active) {
+                Request *r = c->reqs[t].get();
+                chunk = std::min(chunk, r->steps - c->slots[r->handle].host_steps);
+            }
+        }
+        chunk = std::max(1, std::min(chunk, 8));
+        {
+            std::lock_guard<std::recursive_mutex> g(c->mu);
+            if (run_batch(c, hs, chunk)) {
+                std::lock_guard<std::mutex> lk(c->smu);
+                for (uint64_t t : active) { c->reqs[t]->state = -1; c->reqs[t]->t_done = now_s(); }
+                active.clear();
+                continue;
+            }
+            (void)hipStreamSynchronize(c->stream);
+        }
+        // retire
+        std::vector<uint64_t> still;
+        for (uint64_t t : active) {
+            Request *r;
+            {
+                std::lock_guard<std::mutex> lk(c->smu);
+                r = c->reqs[t].get();
+            }
+            std::lock_guard<std::recursive_mutex> g(c->mu);
+            Slot &s = c->slots[r->handle];
+            if (s.host_steps < r->steps) { still.push_back(t); continue; }
+            const int n = s.n_agents;
+            r->out_xy.assign((size_t)2 * std::max(n, 1), -1);
+            r->out_alive.assign((size_t)std::max(n, 1), 0);
+            read_state(c, &s, r->out_xy.data(), r->out_alive.data(), nullptr, &r->out_step,
+                       &r->out_active);
+            destroy_slot(c, r->handle);
+            std::lock_guard<std::mutex> lk(c->smu);
+            r->state = 2;
+            r->t_done = now_s();
+        }
+        active.swap(still);
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char *fast_last_error(void) { return g_err.c_str(); }
+
+static fast_status check_grid(int32_t width, int32_t height, const uint8_t *cell_type)
+{
+    if (width < 3 || height < 3 || width > 16384 || height > 16384 || !cell_type)
+        return fail(FAST_E_INVALID, "grid %dx%d outside 3..16384 or NULL", width, height);
+    for (int64_t i = 0; i < (int64_t)width * height; ++i)
+        if (cell_type[i] > fk::CELL_EXIT) return fail(FAST_E_INVALID, "cell_type values must be 0, 1 or 2");
+    return FAST_OK;
+}
+
+fast_status fast_floor_field(int32_t width, int32_t height, const uint8_t *cell_type,
+                             uint8_t *type_out, double *S_out)
+{
+    fast_status st = check_grid(width, height, cell_type);
+    if (st) return st;
+    std::vector<uint8_t> t(cell_type, cell_type + (size_t)width * height);
+    std::vector<double> S;
+    fh::floor_field(width, height, t, S);
+    if (type_out) std::memcpy(type_out, t.data(), t.size());
+    if (S_out) std::memcpy(S_out, S.data(), S.size() * sizeof(double));
+    return FAST_OK;
+}
+
+fast_status fast_place(int32_t width, int32_t height, const uint8_t *cell_type, int32_t n_agents,
+                       uint64_t seed, uint32_t scenario_id, int32_t *xy_out)
+{
+    fast_status st = check_grid(width, height, cell_type);
+    if (st) return st;
+    if (n_agents < 0 || !xy_out) return fail(FAST_E_INVALID, "bad n_agents or xy_out");
+    std::vector<uint8_t> t(cell_type, cell_type + (size_t)width * height);
+    std::vector<double> S;
+    fh::floor_field(width, height, t, S);
+    std::vector<int32_t> xy;
+    if (!fh::place(width, height, t, n_agents, seed, scenario_id, xy))
+        return fail(FAST_E_INVALID, "more agents than eligible cells");
+    if (n_agents) std::memcpy(xy_out, xy.data(), xy.size() * sizeof(int32_t));
+    return FAST_OK;
+}
+
+double fast_guard_band(int32_t v_max)
+{
+    if (v_max < 1 || v_max > fk::MAX_V) return -1.0;
+    return (double)fh::guard_band(v_max);
+}
+
+fast_status fast_ctx_create(int device, void *hip_stream, size_t hbm_budget, fast_alloc_fn alloc,
+                            fast_free_fn free_fn, void *user, fast_ctx **out)
+{
+    if (!out) return fail(FAST_E_INVALID, "out is NULL");
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(FAST_E_INVALID, "alloc and free_fn must both be set or both be NULL");
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(FAST_E_INVALID, "device %d of %d", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    std::unique_ptr<fast_ctx> c(new fast_ctx());
+    c->device = device;
+    c->budget = hbm_budget;
+    c->alloc = alloc;
+    c->free_fn = free_fn;
+    c->user = user;
+    c->slots.reserve(FAST_MAX_SLOTS);     // handles index a vector that never moves
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    hipError_t e = hipMalloc(&c->table, sizeof(fk::SlotDev) * FAST_MAX_SLOTS);
+    if (e != hipSuccess) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        return fail(FAST_E_NOMEM, "slot table: %s", hipGetErrorString(e));
+    }
+    *out = c.release();
+    return FAST_OK;
+}
+
+fast_status fast_ctx_destroy(fast_ctx *c)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    fast_serve_stop(c);
+    {
+        std::lock_guard<std::recursive_mutex> g(c->mu);
+        (void)hipStreamSynchronize(c->stream);
+        for (int32_t h = 0; h < (int32_t)c->slots.size(); ++h)
+            if (c->slots[h].live) destroy_slot(c, h);
+        for (auto &kv : c->batches) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+            dev_free(c, kv.second.block, kv.second.bytes);
+        }
+        c->batches.clear();
+        (void)hipFree(c->table);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    }
+    delete c;
+    return FAST_OK;
+}
+
+fast_status fast_init_scenario(fast_ctx *c, const fast_scenario_desc *d, int32_t *handle)
+{
+    if (!c || !handle) return fail(FAST_E_INVALID, "ctx or handle is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    return init_slot(c, d, INT_MAX, handle);
+}
+
+fast_status fast_destroy_scenario(fast_ctx *c, int32_t h)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    return destroy_slot(c, h);
+}
+
+fast_status fast_plan_step(fast_ctx *c, int32_t h)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    if (s->planned) HIP_TRY(fk_launch_reset(c->table, s->self, 1, c->stream));
+    HIP_TRY(fk_launch_plan(c->table, s->items, s->n_items, 0, c->stream));
+    s->planned = true;
+    return FAST_OK;
+}
+
+fast_status fast_move_step(fast_ctx *c, int32_t h)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    if (!s->planned) return fail(FAST_E_STATE, "scenario %d: motion without a plan of this step", h);
+    HIP_TRY(fk_launch_move(c->table, s->self, 1, c->stream));
+    s->planned = false;
+    s->host_steps += 1;
+    return FAST_OK;
+}
+
+fast_status fast_run(fast_ctx *c, const int32_t *hs, int32_t n, int32_t steps)
+{
+    if (!c || !hs || n < 1 || steps < 0) return fail(FAST_E_INVALID, "bad arguments to fast_run");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    std::vector<int32_t> v(hs, hs + n);
+    std::sort(v.begin(), v.end());
+    if (std::adjacent_find(v.begin(), v.end()) != v.end())
+        return fail(FAST_E_INVALID, "a handle appears twice");
+    return run_batch(c, v, steps);
+}
+
+fast_status fast_get_state(fast_ctx *c, int32_t h, int32_t *xy, uint8_t *alive, int32_t *desired,
+                           int32_t *step, int32_t *n_active)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    return read_state(c, s, xy, alive, desired, step, n_active);
+}
+
+fast_status fast_get_stats(fast_ctx *c, int32_t h, fast_stats *out)
+{
+    if (!c || !out) return fail(FAST_E_INVALID, "ctx or out is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int32_t ctr[fk::C_NCTR];
+    unsigned long long stat[fk::S_NSTAT];
+    HIP_TRY(hipMemcpy(ctr, s->dev.ctr, sizeof ctr, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(stat, s->dev.stat, sizeof stat, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof *out);
+    out->step = ctr[fk::C_STEP];
+    out->n_agents = s->n_agents;
+    out->n_active = ctr[fk::C_NACTIVE];
+    out->exited = ctr[fk::C_EXITED];
+    out->flagged = (int64_t)stat[fk::S_FLAGGED];
+    out->fallback = (int64_t)stat[fk::S_FALLBACK];
+    out->last_rounds = ctr[fk::C_ROUNDS];
+    out->tile_w = s->dev.tx;
+    out->tile_h = s->dev.ty;
+    out->n_tiles = s->n_items;
+    out->n_fallback_tiles = s->n_fb_tiles;
+    out->guard_band = s->dev.eps;
+    out->device_bytes = (int64_t)s->bytes;
+    return FAST_OK;
+}
+
+fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, float *margin)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    const int n = std::max(s->n_agents, 1);
+    const int side = 2 * s->dev.v + 1;
+    const size_t bw = align_up((size_t)n * side * side * 4, 256), bf = align_up((size_t)n, 256),
+                 bm = (size_t)n * 4;
+    void *block = nullptr;
+    fast_status st = dev_alloc(c, bw + bf + bm, &block);
+    if (st) return st;
+    fk::SlotDev sd = s->dev;
+    sd.dbg_w = (float *)block;
+    sd.dbg_flag = (uint8_t *)((char *)block + bw);
+    sd.dbg_margin = (float *)((char *)block + bw + bf);
+    hipError_t e = hipMemsetAsync(block, 0, bw + bf + bm, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && s->planned) e = fk_launch_reset(c->table, s->self, 1, c->stream);
+    if (e == hipSuccess) e = fk_launch_plan(c->table, s->items, s->n_items, 1, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->table + h, &s->dev, sizeof sd, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) {
+        s->planned = true;
+        const int na = s->n_agents;
+        if (w32 && na) e = hipMemcpy(w32, sd.dbg_w, (size_t)na * side * side * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && flag && na) e = hipMemcpy(flag, sd.dbg_flag, (size_t)na, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && margin && na) e = hipMemcpy(margin, sd.dbg_margin, (size_t)na * 4, hipMemcpyDeviceToHost);
+    }
+    dev_free(c, block, bw + bf + bm);
+    if (e != hipSuccess) return fail(FAST_E_DEVICE, "debug plan: %s", hipGetErrorString(e));
+    return FAST_OK;
+}
+
+fast_status fast_serve_start(fast_ctx *c, size_t budget, int32_t max_active)
+{
+    if (!c || max_active < 0) return fail(FAST_E_INVALID, "bad arguments to fast_serve_start");
+    std::lock_guard<std::mutex> lk(c->smu);
+    if (c->serving) return fail(FAST_E_STATE, "already serving");
+    c->serve_budget = budget;
+    c->serve_max_active = max_active;
+    c->stopping = false;
+    c->serving = true;
+    c->server = std::thread(serve_loop, c);
+    return FAST_OK;
+}
+
+fast_status fast_serve_submit(fast_ctx *c, const fast_scenario_desc *d, int32_t steps,
+                              uint64_t *ticket)
+{
+    if (!c || !ticket || steps < 0) return fail(FAST_E_INVALID, "bad arguments to fast_serve_submit");
+    fast_status st = check_desc(d);
+    if (st) return st;
+    std::unique_ptr<Request> r(new Request());
+    r->desc = *d;
+    r->cells.assign(d->cell_type, d->cell_type + (size_t)d->width * d->height);
+    r->desc.cell_type = r->cells.data();
+    if (d->agent_xy) {
+        r->xy.assign(d->agent_xy, d->agent_xy + (size_t)2 * d->n_agents);
+        r->desc.agent_xy = r->xy.data();
+    }
+    r->steps = steps;
+    r->t_submit = now_s();
+    std::lock_guard<std::mutex> lk(c->smu);
+    if (!c->serving) return fail(FAST_E_STATE, "serving is not started");
+    r->ticket = c->next_ticket++;
+    *ticket = r->ticket;
+    c->queue.push_back(r->ticket);
+    c->reqs[r->ticket] = std::move(r);
+    c->scv.notify_one();
+    return FAST_OK;
+}
+
+fast_status fast_serve_poll(fast_ctx *c, uint64_t ticket, int32_t *done, double *latency_s)
+{
+    if (!c || !done) return fail(FAST_E_INVALID, "bad arguments to fast_serve_poll");
+    std::lock_guard<std::mutex> lk(c->smu);
+    auto it = c->reqs.find(ticket);
+    if (it == c->reqs.end()) return fail(FAST_E_NOTFOUND, "unknown ticket");
+    Request *r = it->second.get();
+    if (r->state == -1) return fail(FAST_E_INVALID, "request was rejected");
+    *done = r->state == 2 ? 1 : 0;
+    if (latency_s) *latency_s = r->state == 2 ? r->t_done - r->t_submit : now_s() - r->t_submit;
+    return FAST_OK;
+}
+
+fast_status fast_serve_result(fast_ctx *c, uint64_t ticket, int32_t *xy, uint8_t *alive,
+                              int32_t *step, int32_t *n_active)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(c->smu);
+    auto it = c->reqs.find(ticket);
+    if (it == c->reqs.end()) return fail(FAST_E_NOTFOUND, "unknown ticket");
+    Request *r = it->second.get();
+    if (r->state != 2) return fail(FAST_E_STATE, "request not finished");
+    const int n = r->desc.n_agents;
+    if (xy && n) std::memcpy(xy, r->out_xy.data(), (size_t)2 * n * 4);
+    if (alive && n) std::memcpy(alive, r->out_alive.data(), (size_t)n);
+    if (step) *step = r->out_step;
+    if (n_active) *n_active = r->out_active;
+    return FAST_OK;
+}
+
+fast_status fast_serve_stop(fast_ctx *c)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    {
+        std::lock_guard<std::mutex> lk(c->smu);
+        if (!c->serving) return FAST_OK;
+        c->stopping = true;
+        c->scv.notify_all();
+    }
+    if (c->server.joinable()) c->server.join();
+    std::lock_guard<std::mutex> lk(c->smu);
+    c->serving = false;
+    return FAST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+"""Thin Python binding of libfast (include/fast.h): argument marshalling only.
+
+Every step of the method runs in libfast's HIP kernels; PyTorch supplies the
+device allocator (its caching allocator) and the HIP stream.  Importing this
+module fails loudly when libfast.so has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfast.so")
+
+FAST_OK = 0
+ERRORS = {-1: "FAST_E_INVALID", -2: "FAST_E_NOMEM", -3: "FAST_E_BUDGET", -4: "FAST_E_DEVICE",
+          -5: "FAST_E_STATE", -6: "FAST_E_NOTFOUND"}
+
+
+class FastError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ScenarioDesc(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("cell_type", ctypes.c_void_p),
+        ("n_agents", ctypes.c_int32), ("agent_xy", ctypes.c_void_p),
+        ("v_max", ctypes.c_int32), ("k_s", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("scenario_id", ctypes.c_uint32),
+        ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int32), ("n_agents", ctypes.c_int32), ("n_active", ctypes.c_int32),
+        ("exited", ctypes.c_int32), ("flagged", ctypes.c_int64), ("fallback", ctypes.c_int64),
+        ("last_rounds", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+        ("n_tiles", ctypes.c_int32), ("n_fallback_tiles", ctypes.c_int32),
+        ("guard_band", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0911_2900_amd.build`"
+                          " (the HIP library is required; there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
+    sig = {
+        "fast_ctx_create": [ctypes.c_int, P, ctypes.c_size_t, ALLOC_FN, FREE_FN, P, P],
+        "fast_ctx_destroy": [P],
+        "fast_init_scenario": [P, P, P],
+        "fast_destroy_scenario": [P, I32],
+        "fast_plan_step": [P, I32],
+        "fast_move_step": [P, I32],
+        "fast_run": [P, P, I32, I32],
+        "fast_get_state": [P, I32, P, P, P, P, P],
+        "fast_get_stats": [P, I32, P],
+        "fast_debug_plan": [P, I32, P, P, P],
+        "fast_serve_start": [P, ctypes.c_size_t, I32],
+        "fast_serve_submit": [P, P, I32, P],
+        "fast_serve_poll": [P, U64, P, P],
+        "fast_serve_result": [P, U64, P, P, P, P],
+        "fast_serve_stop": [P],
+    }
+    sig["fast_floor_field"] = [I32, I32, P, P, P]
+    sig["fast_place"] = [I32, I32, P, I32, U64, ctypes.c_uint32, P]
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L.fast_guard_band.restype = ctypes.c_double
+    L.fast_guard_band.argtypes = [I32]
+    L.fast_last_error.restype = ctypes.c_char_p
+    L.fast_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != FAST_OK:
+        raise FastError(code, lib().fast_last_error().decode())
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def floor_field(cell_type: np.ndarray):
+    """Host floor field of the library: (types after, S)."""
+    ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
+    H, W = ct.shape
+    t = np.zeros_like(ct)
+    S = np.zeros((H, W), dtype=np.float64)
+    _check(lib().fast_floor_field(W, H, _ptr(ct), _ptr(t), _ptr(S)))
+    return t, S
+
+
+def place(cell_type: np.ndarray, n: int, seed: int, scn: int) -> np.ndarray:
+    """Host seeded placement of the library: (n, 2) int32 (x, y)."""
+    ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
+    H, W = ct.shape
+    xy = np.zeros((max(n, 1), 2), dtype=np.int32)
+    _check(lib().fast_place(W, H, _ptr(ct), int(n), int(seed), int(scn), _ptr(xy)))
+    return xy[:n]
+
+
+def guard_band(v: int) -> float:
+    return lib().fast_guard_band(int(v))
+
+
+def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, seed: int = 1,
+              scn: int = 0, agent_xy=None, tile=None):
+    """Descriptor plus the host arrays it points to (keep both alive)."""
+    ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
+    H, W = ct.shape
+    xy = None
+    if agent_xy is not None:
+        xy = np.ascontiguousarray(np.asarray(agent_xy, dtype=np.int32).reshape(-1, 2))
+        n_agents = len(xy)
+    d = ScenarioDesc()
+    d.width, d.height = W, H
+    d.cell_type = _ptr(ct)
+    d.n_agents = int(n_agents)
+    d.agent_xy = _ptr(xy) if xy is not None and len(xy) else None
+    d.v_max, d.k_s = int(v), float(k_s)
+    d.seed, d.scenario_id = int(seed), int(scn)
+    d.tile_w, d.tile_h = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
+    return d, (ct, xy)
+
+
+class Context:
+    """A libfast context on one GPU, issuing work on a PyTorch stream."""
+
+    def __init__(self, device: int = 0, stream=None, budget: int = 0, torch_alloc: bool = True):
+        import torch
+
+        self._torch = torch
+        self.device = device
+        torch.cuda.set_device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self._keep = []
+        alloc_cb, free_cb = ALLOC_FN(), FREE_FN()
+        if torch_alloc:
+            tstream = self.stream
+
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, tstream)
+                except Exception:          # out of memory: report NULL to the library
+                    return None
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            alloc_cb, free_cb = ALLOC_FN(_alloc), FREE_FN(_free)
+        self._alloc_cb, self._free_cb = alloc_cb, free_cb
+        ctx = ctypes.c_void_p()
+        _check(lib().fast_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream), int(budget),
+                                     alloc_cb, free_cb, None, ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.n_agents = {}
+        self.v = {}
+
+    # -- scenarios ---------------------------------------------------------
+    def init_scenario(self, cell_type, n_agents=0, v=4, k_s=1.2, seed=1, scn=0, agent_xy=None,
+                      tile=None) -> int:
+        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_xy, tile)
+        h = ctypes.c_int32(-1)
+        _check(lib().fast_init_scenario(self.ctx, ctypes.byref(d), ctypes.byref(h)))
+        self.n_agents[h.value] = d.n_agents
+        self.v[h.value] = int(v)
+        return h.value
+
+    def init_from(self, sc, tile=None) -> int:
+        """From a paper_0911_2900_amd.scenarios.Scenario."""
+        return self.init_scenario(sc.cell_type, sc.n_agents, sc.v, sc.k_s, sc.seed, sc.scn,
+                                  tile=tile)
+
+    def destroy(self, h: int):
+        _check(lib().fast_destroy_scenario(self.ctx, h))
+        self.n_agents.pop(h, None)
+
+    # -- steps -------------------------------------------------------------
+    def plan(self, h: int):
+        _check(lib().fast_plan_step(self.ctx, h))
+
+    def move(self, h: int):
+        _check(lib().fast_move_step(self.ctx, h))
+
+    def run(self, handles, steps: int):
+        hs = np.ascontiguousarray(np.asarray(list(handles), dtype=np.int32))
+        _check(lib().fast_run(self.ctx, _ptr(hs), len(hs), int(steps)))
+
+    # -- state -------------------------------------------------------------
+    def state(self, h: int) -> dict:
+        n = self.n_agents[h]
+        m = max(n, 1)
+        xy = np.zeros((m, 2), dtype=np.int32)
+        alive = np.zeros(m, dtype=np.uint8)
+        desired = np.zeros(m, dtype=np.int32)
+        step, n_active = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().fast_get_state(self.ctx, h, _ptr(xy), _ptr(alive), _ptr(desired),
+                                    ctypes.byref(step), ctypes.byref(n_active)))
+        return {"xy": xy[:n], "alive": alive[:n], "desired": desired[:n], "step": step.value,
+                "n_active": n_active.value}
+
+    def stats(self, h: int) -> dict:
+        st = Stats()
+        _check(lib().fast_get_stats(self.ctx, h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def debug_plan(self, h: int):
+        n, v = self.n_agents[h], self.v[h]
+        side = 2 * v + 1
+        m = max(n, 1)
+        w = np.zeros((m, side * side), dtype=np.float32)
+        flag = np.zeros(m, dtype=np.uint8)
+        margin = np.zeros(m, dtype=np.float32)
+        _check(lib().fast_debug_plan(self.ctx, h, _ptr(w), _ptr(flag), _ptr(margin)))
+        return w[:n], flag[:n], margin[:n]
+
+    # -- serving -----------------------------------------------------------
+    def serve_start(self, budget: int = 0, max_active: int = 0):
+        _check(lib().fast_serve_start(self.ctx, int(budget), int(max_active)))
+
+    def serve_submit(self, cell_type, n_agents, v, k_s=1.2, seed=1, scn=0, steps=396) -> int:
+        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn)
+        t = ctypes.c_uint64(0)
+        _check(lib().fast_serve_submit(self.ctx, ctypes.byref(d), int(steps), ctypes.byref(t)))
+        self.n_agents[("ticket", t.value)] = d.n_agents
+        return t.value
+
+    def serve_poll(self, ticket: int):
+        done, lat = ctypes.c_int32(0), ctypes.c_double(0.0)
+        _check(lib().fast_serve_poll(self.ctx, ticket, ctypes.byref(done), ctypes.byref(lat)))
+        return bool(done.value), lat.value
+
+    def serve_result(self, ticket: int) -> dict:
+        n = self.n_agents[("ticket", ticket)]
+        m = max(n, 1)
+        xy = np.zeros((m, 2), dtype=np.int32)
+        alive = np.zeros(m, dtype=np.uint8)
+        step, n_active = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().fast_serve_result(self.ctx, ticket, _ptr(xy), _ptr(alive), ctypes.byref(step),
+                                       ctypes.byref(n_active)))
+        return {"xy": xy[:n], "alive": alive[:n], "step": step.value, "n_active": n_active.value}
+
+    def serve_stop(self):
+        _check(lib().fast_serve_stop(self.ctx))
+
+    def close(self):
+        if self.ctx:
+            _check(lib().fast_ctx_destroy(self.ctx))
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

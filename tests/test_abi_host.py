@@ -1,0 +1,109 @@
+"""C-ABI library (no GPU): it loads, exports every function the header
+declares, and its host-side setup -- floor field, seeded placement, guard
+band -- agrees with the oracle bit for bit on the workloads' grids."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0911_2900_amd import scenarios as sc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fast.h")
+
+
+@pytest.fixture(scope="module")
+def fast():
+    from paper_0911_2900_amd import fast as f
+    try:
+        f.lib()
+    except ImportError as e:
+        pytest.skip(str(e))
+    return f
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(fast_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(n for n in names if not n.endswith("_fn")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["fast_ctx_create", "fast_init_scenario", "fast_plan_step", "fast_move_step",
+                     "fast_run", "fast_get_state", "fast_debug_plan", "fast_serve_submit",
+                     "fast_serve_poll", "fast_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(fast):
+    lib = fast.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _grids():
+    yield sc.corridor().cell_type
+    yield sc.room(size=400).cell_type
+    for k in (0, 3, 17, 101):
+        yield sc.ensemble_member(k).cell_type
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        yield sc.random_small(rng, int(rng.integers(5, 40)), int(rng.integers(5, 40)),
+                              float(rng.uniform(0, 0.3)), 10, 3, n_exits=2).cell_type
+
+
+@pytest.mark.parametrize("k", range(11))
+def test_host_floor_field_equals_oracle(fast, k):
+    grid = list(_grids())[k]
+    t_o, S_o, _, _ = oracle.floor_field(grid)
+    t_f, S_f = fast.floor_field(grid)
+    assert np.array_equal(t_o, t_f)
+    assert np.array_equal(S_o, S_f)           # bit-identical, inf on walls
+
+
+def test_host_floor_field_large_member(fast):
+    grid = sc.large_member(0).cell_type
+    t_o, S_o, _, _ = oracle.floor_field(grid)
+    t_f, S_f = fast.floor_field(grid)
+    assert np.array_equal(t_o, t_f) and np.array_equal(S_o, S_f)
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_host_placement_equals_oracle(fast, k):
+    grid = list(_grids())[k]
+    free = int((oracle.floor_field(grid)[0] == sc.FREE).sum())
+    n = min(free, [200, 40000, 500, 1000, 50, 5000][k])
+    t_o, S_o, _, _ = oracle.floor_field(grid)
+    x, y = oracle.place(t_o, S_o, n, seed=1 + k, scn=k)
+    xy = fast.place(grid, n, seed=1 + k, scn=k)
+    assert np.array_equal(xy[:, 0], x) and np.array_equal(xy[:, 1], y)
+
+
+def test_placement_rejects_overfull(fast):
+    grid = sc.walled_box(5, 5)
+    grid[2, 4] = sc.EXIT
+    with pytest.raises(fast.FastError):
+        fast.place(grid, 10, 1, 0)
+
+
+def test_floor_field_rejects_bad_types(fast):
+    grid = sc.walled_box(5, 5)
+    grid[2, 2] = 7
+    with pytest.raises(fast.FastError):
+        fast.floor_field(grid)
+
+
+def test_guard_band_covers_the_fp32_rounding_bound(fast):
+    u = 2.0 ** -24
+    for v in range(1, 6):
+        band = fast.guard_band(v)
+        assert band >= 1e-6
+        # depth of a CDF value: pairwise row sums plus sequential row/in-row prefixes
+        d = int(np.ceil(np.log2(2 * v + 1))) + 2 * v
+        assert band > (2 * d + 3) * u
+        assert band < 5e-6
+    assert fast.guard_band(0) < 0 and fast.guard_band(6) < 0

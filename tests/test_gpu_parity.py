@@ -1,0 +1,295 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Bar: desired cells, positions, alive flags and exit counts bit-identical to
+the oracle on the same seeded inputs; FP32 weights within 1e-6 relative of the
+oracle's FP64 weights (weights below 2^-60 W may be 0, cross-wall underflow).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0911_2900_amd import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0911_2900_amd import fast
+    c = fast.Context()
+    yield c
+    c.close()
+
+
+def make_pair(ctx, s, tile=None, agent_xy=None):
+    if agent_xy is None:
+        sim = oracle.Sim(s.cell_type, s.v, s.k_s, s.seed, s.scn, n_agents=s.n_agents)
+        h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=tile)
+    else:
+        sim = oracle.Sim(s.cell_type, s.v, s.k_s, s.seed, s.scn, agent_xy=agent_xy)
+        h = ctx.init_scenario(s.cell_type, 0, s.v, s.k_s, s.seed, s.scn, agent_xy=agent_xy, tile=tile)
+    st = ctx.state(h)
+    assert np.array_equal(st["xy"], sim.positions())
+    return sim, h
+
+
+def compare_state(ctx, sim, h, check_desired=False, where=""):
+    st = ctx.state(h)
+    n = sim.n
+    alive_o = sim.alive[:n].astype(bool)
+    assert np.array_equal(st["alive"].astype(bool), alive_o), f"alive differs {where}"
+    assert np.array_equal(st["xy"], sim.positions()), f"positions differ {where}"
+    assert st["n_active"] == int(alive_o.sum())
+    if check_desired:
+        d_o = sim.desired[:n]
+        bad = np.nonzero(st["desired"][alive_o] != d_o[alive_o])[0]
+        assert len(bad) == 0, f"desired differs for {len(bad)} agents {where}: first ids " \
+                              f"{np.nonzero(alive_o)[0][bad[:5]]}"
+    return st
+
+
+def step_both(ctx, sim, h, steps, check_every=1, where=""):
+    for s in range(steps):
+        ctx.plan(h)
+        sim.plan()
+        if check_every and s % check_every == 0:
+            st = ctx.state(h)
+            alive = sim.alive[: sim.n].astype(bool)
+            bad = np.nonzero(st["desired"][alive] != sim.desired[: sim.n][alive])[0]
+            assert len(bad) == 0, f"plan of step {s} differs for {len(bad)} agents {where}"
+        ctx.move(h)
+        sim.move()
+        sim.end_step()
+        if check_every and s % check_every == 0:
+            compare_state(ctx, sim, h, where=f"after step {s} {where}")
+    compare_state(ctx, sim, h, where=f"at the end {where}")
+
+
+def check_weights(ctx, sim, h, sample=None):
+    """FP32 debug weights vs the oracle's FP64 weights, and the flags."""
+    w32, flag, margin = ctx.debug_plan(h)
+    sim.plan()
+    alive = np.nonzero(sim.alive[: sim.n])[0]
+    ids = alive if sample is None else np.random.default_rng(0).choice(alive, min(sample, len(alive)),
+                                                                       replace=False)
+    worst = 0.0
+    for i in ids:
+        d, w64, C, u, slot = sim.plan_agent(int(i))
+        W64 = w64.sum()
+        w = w32[i].astype(np.float64)
+        big = w64 >= 2.0 ** -60 * W64
+        if flag[i] == 2:       # fallback tile: weights are the FP64 ones rounded
+            assert np.all(np.abs(w[big] - w64[big]) <= 1e-6 * w64[big])
+            continue
+        rel = np.abs(w[big] - w64[big]) / w64[big]
+        worst = max(worst, float(rel.max()) if rel.size else 0.0)
+        assert np.all(rel <= 1e-6), f"agent {i}: weight rel err {rel.max():.3e}"
+        assert np.all(w[~big] <= 2.0 ** -60 * w.sum())
+    st = ctx.state(h)
+    a = sim.alive[: sim.n].astype(bool)
+    assert np.array_equal(st["desired"][a], sim.desired[: sim.n][a])
+    return worst, flag, margin
+
+
+# ---------------------------------------------------------------------------
+# corridor 60 x 25, 200 agents, v_m = 4, 396 steps
+# ---------------------------------------------------------------------------
+
+def test_corridor_plan_weights(ctx):
+    s = sc.corridor()
+    sim, h = make_pair(ctx, s)
+    worst, flag, margin = check_weights(ctx, sim, h)
+    say("corridor worst weight rel err", worst)
+    ctx.move(h)
+    sim.move()
+    sim.end_step()
+    compare_state(ctx, sim, h)
+    ctx.destroy(h)
+
+
+def test_corridor_396_steps_bit_exact(ctx):
+    s = sc.corridor()
+    sim, h = make_pair(ctx, s)
+    step_both(ctx, sim, h, 396, check_every=1, where="corridor")
+    st = ctx.stats(h)
+    say("corridor stats", st)
+    assert st["step"] == 396 and st["exited"] == sim.exited
+    ctx.destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# room 400 x 400, 40,000 agents
+# ---------------------------------------------------------------------------
+
+def test_room_v4_plan_weights(ctx):
+    s = sc.room(v=4)
+    sim, h = make_pair(ctx, s)
+    worst, flag, margin = check_weights(ctx, sim, h, sample=3000)
+    say("room v4 worst weight rel err", worst, "flagged", int((flag == 1).sum()))
+    ctx.destroy(h)
+
+
+def test_room_v4_396_steps_bit_exact(ctx):
+    s = sc.room(v=4)
+    sim, h = make_pair(ctx, s)
+    step_both(ctx, sim, h, 396, check_every=11, where="room v4")
+    st = ctx.stats(h)
+    say("room v4 stats", st)
+    assert st["exited"] == sim.exited
+    ctx.destroy(h)
+
+
+@pytest.mark.parametrize("v", [1, 2, 3, 5])
+def test_room_other_speeds(ctx, v):
+    s = sc.room(v=v)
+    sim, h = make_pair(ctx, s)
+    step_both(ctx, sim, h, 25, check_every=1, where=f"room v{v}")
+    ctx.destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# tiles, geometry, fallback tiles, edge cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_small_scenarios(ctx, case):
+    rng = np.random.default_rng(900 + case)
+    v = int(rng.integers(1, 6))
+    W, H = int(rng.integers(5, 90)), int(rng.integers(5, 90))
+    s = sc.random_small(rng, W, H, float(rng.uniform(0, 0.2)), int(rng.integers(1, 1500)), v,
+                        seed=int(rng.integers(0, 2**63)), scn=int(rng.integers(0, 2**31)),
+                        n_exits=int(rng.integers(1, 4)))
+    tiles = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 16), (32, 32), (64, 16), (16, 64), (64, 8)]
+    tile = tiles[case % len(tiles)]
+    say(f"case {case}: {W}x{H} v={v} n={s.n_agents} tile={tile}")
+    sim, h = make_pair(ctx, s, tile=tile)
+    step_both(ctx, sim, h, 30, check_every=1, where=f"case {case}")
+    ctx.destroy(h)
+
+
+@pytest.mark.parametrize("k_s", [0.0, 4.0, 9.0])
+def test_extreme_k_s_and_fallback_tiles(ctx, k_s):
+    rng = np.random.default_rng(77)
+    s = sc.random_small(rng, 70, 50, 0.15, 900, 4, k_s=k_s, seed=5, scn=3, n_exits=2)
+    sim, h = make_pair(ctx, s, tile=(32, 32))
+    st = ctx.stats(h)
+    say("k_s", k_s, "fallback tiles", st["n_fallback_tiles"], "of", st["n_tiles"])
+    if k_s >= 4.0:
+        assert st["n_fallback_tiles"] > 0
+    worst, flag, margin = check_weights(ctx, sim, h)
+    ctx.move(h)
+    sim.move()
+    sim.end_step()
+    step_both(ctx, sim, h, 20, check_every=1, where=f"k_s={k_s}")
+    ctx.destroy(h)
+
+
+def test_no_agents_and_single_agent(ctx):
+    s = sc.corridor(n_agents=0)
+    sim, h = make_pair(ctx, s)
+    step_both(ctx, sim, h, 5)
+    ctx.destroy(h)
+    s1 = sc.corridor(n_agents=1)
+    sim, h = make_pair(ctx, s1)
+    step_both(ctx, sim, h, 40)
+    ctx.destroy(h)
+
+
+def test_dense_room_all_cells_but_one(ctx):
+    t = sc.walled_box(12, 10)
+    t[5, 11] = sc.EXIT
+    free = [(x, y) for y in range(1, 9) for x in range(1, 11)]
+    agents = free[:-1]                       # every free cell but one is occupied
+    s = sc.Scenario("dense", t, len(agents), 3, 1.2, 4, 1)
+    sim, h = make_pair(ctx, s, tile=(8, 8), agent_xy=agents)
+    step_both(ctx, sim, h, 60)
+    ctx.destroy(h)
+
+
+def test_plan_twice_then_move(ctx):
+    s = sc.corridor()
+    sim, h = make_pair(ctx, s)
+    ctx.plan(h)
+    ctx.plan(h)             # a second plan of the same step resets the mover list
+    sim.plan()
+    ctx.move(h)
+    sim.move()
+    sim.end_step()
+    compare_state(ctx, sim, h)
+    ctx.destroy(h)
+
+
+def test_state_errors(ctx):
+    from paper_0911_2900_amd import fast
+    s = sc.corridor()
+    h = ctx.init_from(s)
+    with pytest.raises(fast.FastError):
+        ctx.move(h)                              # motion without a plan
+    with pytest.raises(fast.FastError):
+        ctx.plan(h + 1000)                       # unknown handle
+    bad = s.cell_type.copy()
+    bad[bad == sc.EXIT] = sc.WALL
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(bad, 10, 4)            # no exit
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(s.cell_type, 10, 6)    # v_max out of range
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(s.cell_type, 10, 4, k_s=-1.0)
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(s.cell_type, 5000, 4)  # more agents than cells
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(s.cell_type, 0, 4, agent_xy=[(3, 3), (3, 3)])
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(s.cell_type, 0, 4, agent_xy=[(0, 0)])       # on a wall
+    ctx.destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# batched runs: every scenario in the mix equals the oracle and itself alone
+# ---------------------------------------------------------------------------
+
+def test_batched_ensemble_members_match_oracle(ctx):
+    members = [sc.ensemble_member(k) for k in (0, 1, 2, 5, 8, 13, 21, 34)]
+    sims, hs = [], []
+    for m in members:
+        sim, h = make_pair(ctx, m)
+        sims.append(sim)
+        hs.append(h)
+    steps = 40
+    ctx.run(hs, steps)
+    for m, sim, h in zip(members, sims, hs):
+        sim.run(steps)
+        compare_state(ctx, sim, h, where=m.name)
+        ctx.destroy(h)
+
+
+def test_batched_large_grid_sampled(ctx):
+    """The 1000 x 1000, 200,000-agent workload at full size: one plan step
+    checked on 4,000 sampled agents against the oracle's per-agent draw, then
+    one full motion phase compared cell by cell."""
+    s = sc.large_member(0)
+    sim, h = make_pair(ctx, s)
+    ctx.plan(h)
+    st = ctx.state(h)
+    alive = np.nonzero(sim.alive[: sim.n])[0]
+    pick = np.random.default_rng(1).choice(alive, 4000, replace=False)
+    for i in pick:
+        d = sim.plan_agent(int(i))[0]
+        assert st["desired"][i] == d, f"agent {i}"
+    sim.plan()
+    assert np.array_equal(st["desired"], sim.desired[: sim.n])
+    ctx.move(h)
+    sim.move()
+    sim.end_step()
+    compare_state(ctx, sim, h, where="large step 0")
+    ctx.destroy(h)
