@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Benchmark of the F.A.S.T. planning phase on one MI355X.
+
+Headline workload: the 400 x 400 room with 40,000 agents at v_m = 4,
+k_S = 1.2, k_other = 0 (paper Sec. 2 parameters; the paper times 396 steps of
+40,000 agents).  A step is one planning phase plus one motion phase; the
+`warmup` first steps of the run are untimed, the next `steps` are timed (the
+defaults cover the paper's 396 steps).  `value` is planning agent-updates/s:
+agents planned over the timed steps divided by the summed duration of the
+planning kernel, taken with HIP events on the stream the kernel runs on.
+
+Also printed on the same JSON line:
+  roofline      the planning kernel's algorithmic bytes per launch (5 B per
+                cell inside some agent's reach window: occupancy 1 B + exp
+                table 4 B; 12 B per agent: position 8 B + desired cell 4 B)
+                over its average duration, against 8 TB/s of HBM.
+  ensemble      the 256-scenario ensemble workload run as one batch (one
+                planning and one motion launch per step, replayed from a HIP
+                graph), scenario-steps/s, next to the same scenarios stepped
+                one at a time with plain launches.
+  cpu_baseline  the CPU oracle's planning loop (the paper's OpenMP schedule)
+                on the host's cores, on the first steps of the same run.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def window_cells(cell_type: np.ndarray, xy: np.ndarray, v: int) -> int:
+    """Cells inside the reach disc of at least one agent (the planning
+    phase's algorithmic footprint)."""
+    H, W = cell_type.shape
+    mask = np.zeros((H + 2 * v, W + 2 * v), dtype=bool)
+    occ = np.zeros_like(mask)
+    occ[xy[:, 1] + v, xy[:, 0] + v] = True
+    for dy in range(-v, v + 1):
+        for dx in range(-v, v + 1):
+            if dx * dx + dy * dy <= v * v:
+                mask |= np.roll(np.roll(occ, dy, 0), dx, 1)
+    return int(mask[v:v + H, v:v + W].sum())
+
+
+def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4):
+    from paper_0911_2900_amd import scenarios as sc
+
+    s = sc.room(v=v)
+    h = ctx.init_from(s)
+    for _ in range(warmup):
+        ctx.plan(h)
+        ctx.move(h)
+    st = ctx.state(h)
+    alive = st["alive"].astype(bool)
+    cells = window_cells(s.cell_type, st["xy"][alive], v)
+    planned0 = ctx.stats(h)["planned"]
+    stream = ctx.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_start.record(stream)
+    for k in range(steps):
+        ev[k][0].record(stream)
+        ctx.plan(h)
+        ev[k][1].record(stream)
+        ctx.move(h)
+    e_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan_ms = [a.elapsed_time(b) for a, b in ev]
+    total_ms = e_start.elapsed_time(e_end)
+    stt = ctx.stats(h)
+    planned = stt["planned"] - planned0
+    res = {
+        "planned": planned, "plan_ms": plan_ms, "total_ms": total_ms, "wall_s": wall,
+        "cells": cells, "stats": stt, "handle": h,
+    }
+    ctx.destroy(h)
+    return res
+
+
+def bench_ensemble(ctx, torch, warmup: int, steps: int, plain_steps: int):
+    from paper_0911_2900_amd import scenarios as sc
+
+    ens = sc.ensemble(256)
+    t0 = time.perf_counter()
+    hs = [ctx.init_from(m) for m in ens]
+    init_s = time.perf_counter() - t0
+    ctx.run(hs, warmup)
+    planned0 = sum(ctx.stats(h)["planned"] for h in hs)
+    stream = ctx.stream
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    ctx.run(hs, steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    batched_ms = a.elapsed_time(b)
+    planned = sum(ctx.stats(h)["planned"] for h in hs) - planned0
+    # the same scenarios, one at a time, with plain (non-graph) launches
+    a2, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a2.record(stream)
+    for _ in range(plain_steps):
+        for h in hs:
+            ctx.plan(h)
+            ctx.move(h)
+    b2.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = a2.elapsed_time(b2)
+    for h in hs:
+        ctx.destroy(h)
+    n = len(hs)
+    return {
+        "workload": "ensemble: 256 scenarios, grids 30..300 cells a side, 0-15 % pillars, "
+                    "1-4 exits, 50-20,000 agents each, v_m 1..5",
+        "scenarios": n, "cells": int(sum(m.W * m.H for m in ens)),
+        "agents": int(sum(m.n_agents for m in ens)),
+        "steps": steps,
+        "batched_scenario_steps_per_s": n * steps / (batched_ms / 1e3),
+        "batched_agent_updates_per_s": planned / (batched_ms / 1e3),
+        "plain_loop_scenario_steps_per_s": n * plain_steps / (plain_ms / 1e3),
+        "batched_over_plain": (n * steps / batched_ms) / (n * plain_steps / plain_ms),
+        "ms_per_batched_step": batched_ms / steps,
+        "init_s": init_s,
+    }
+
+
+def cpu_baseline(budget_s: float = 15.0, max_steps: int = 396, v: int = 4):
+    """The oracle as it stands: its OpenMP planning loop (paper Sec. 2
+    schedule) on every host thread, sequential motion, on the room workload."""
+    import oracle
+    from paper_0911_2900_amd import scenarios as sc
+
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    s = sc.room(v=v)
+    sim = oracle.Sim(s.cell_type, s.v, s.k_s, s.seed, s.scn, n_agents=s.n_agents)
+    planned, plan_s, steps = 0, 0.0, 0
+    t_all = time.perf_counter()
+    while steps < max_steps and time.perf_counter() - t_all < budget_s:
+        n = sim.n_alive()
+        t0 = time.perf_counter()
+        sim.plan_omp(cores)
+        plan_s += time.perf_counter() - t0
+        planned += n
+        sim.move()
+        sim.end_step()
+        steps += 1
+    return {
+        "value": planned / plan_s, "unit": "agent-updates/s", "cores": cores, "kind": "oracle",
+        "sample": f"first {steps} steps of the 400x400 room, 40,000 agents, v_m={v}: FP64 "
+                  f"planning loop with schedule(dynamic, max(min(N/cores, 32767), 1)) on "
+                  f"{cores} threads (timed), sequential motion (untimed)",
+        "whole_steps_s": time.perf_counter() - t_all,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=386)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--ensemble-steps", type=int, default=60)
+    ap.add_argument("--plain-steps", type=int, default=4)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs each scenario on a single MI355X and "
+              "has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0911_2900_amd import fast
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    ctx = fast.Context(device=0)
+    log(f"room: warmup {args.warmup}, timed {args.steps} steps")
+    r = bench_room(ctx, torch, args.warmup, args.steps)
+    plan_s = sum(r["plan_ms"]) / 1e3
+    value = r["planned"] / plan_s
+    avg_plan_ms = float(np.mean(r["plan_ms"]))
+    bytes_per_launch = 5.0 * r["cells"] + 12.0 * r["planned"] / args.steps
+    achieved = bytes_per_launch / (avg_plan_ms / 1e3) / 1e9
+    log(f"room: planning {value:.4g} agent-updates/s, plan {avg_plan_ms * 1e3:.2f} us/step, "
+        f"whole step {r['total_ms'] / args.steps * 1e3:.1f} us, stats {r['stats']}")
+
+    ens = None
+    if not args.no_ensemble:
+        log("ensemble ...")
+        ens = bench_ensemble(ctx, torch, 5, args.ensemble_steps, args.plain_steps)
+        log(f"ensemble: {ens}")
+    ctx.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        cpu = cpu_baseline()
+        log(f"cpu: {cpu}")
+
+    out = {
+        "metric": "planning agent-updates/s (40k agents, v_m=4) + batched ensemble steps/s",
+        "value": value,
+        "unit": "agent-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["total_ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "room 400x400 cells, 10-cell exit, 40,000 agents, v_m=4, k_S=1.2, "
+                        "k_other=0; steps 0..395 of the 396-step run (warmup first)",
+            "agents": 40000, "grid": [400, 400], "v_m": 4, "k_S": 1.2,
+            "parallelism": "1 GPU",
+        },
+        "whole_step_agent_updates_per_s": r["planned"] / (r["total_ms"] / 1e3),
+        "plan_us_per_step": avg_plan_ms * 1e3,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "plan_kernel", "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": avg_plan_ms * 1e3,
+        },
+        "ensemble": ens,
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in
+                                                 ("value", "unit", "cores", "kind", "sample")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -115,6 +115,7 @@ typedef struct {
     int32_t n_tiles, n_fallback_tiles;
     double guard_band;           /* relative half-width of the FP64 re-resolve band  */
     int64_t device_bytes;        /* device memory held by the scenario               */
+    int64_t planned;             /* agent plans made so far (sum of N_active)        */
 } fast_stats;
 
 /* Creates a context on HIP device `device`, issuing work on `hip_stream`

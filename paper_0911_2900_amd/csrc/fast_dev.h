@@ -33,7 +33,11 @@ constexpr int MAX_V = 5;
 constexpr int MAX_TILE_CELLS = 1024;   // tx * ty
 constexpr int MAX_STAGE = 2048;        // (tx + 2v)(ty + 2v) over the allowed tiles
 constexpr int PLAN_THREADS = 256;
-constexpr int MOVE_THREADS = 1024;
+constexpr int MOVE_THREADS = 256;
+constexpr int MOVE_GROUP_MAX = 64;        // workgroups per scenario in the motion phase
+constexpr int MOVE_AGENTS_PER_WG = 1024;  // group size = ceil(agents / this), capped
+constexpr int MOVE_SOLO_N = 2048;         // rounds with fewer movers run in one workgroup
+constexpr uint32_t SPIN_LIMIT = 1u << 22; // bound on a group-barrier wait (never hangs)
 
 // Motion reservation words: [tag:12][~x0:32][~id:20]; the largest word on a
 // cell is the earliest agent of the current round (tags grow every round).
@@ -51,10 +55,21 @@ enum : int {
     C_TAG = 4,       // last reservation tag used
     C_ROUNDS = 5,    // reservation rounds of the last motion phase
     C_LIMIT = 6,     // kernels act while step < limit
-    C_NCTR = 8
+    C_CNT0 = 7,      // movers left after an even / odd reservation round
+    C_CNT1 = 8,
+    C_BAR = 9,       // group-barrier arrivals of the running motion phase
+    C_ERR = 10,      // nonzero: a group barrier timed out, the state is invalid
+    C_NCTR = 16
+};
+
+// A mover of the running motion phase: priority word and packed coordinates
+// (x | y << 16, padded) of its start and desired cells.
+struct Mover {
+    unsigned long long key;
+    uint32_t cxy, dxy;
 };
 // uint64 statistics per slot
-enum : int { S_FLAGGED = 0, S_FALLBACK = 1, S_NSTAT = 4 };
+enum : int { S_FLAGGED = 0, S_FALLBACK = 1, S_PLANNED = 2, S_NSTAT = 4 };
 
 struct SlotDev {
     int32_t W, H;            // scenario size
@@ -76,7 +91,7 @@ struct SlotDev {
     int32_t *pos;            // n_agents
     int32_t *desired;        // n_agents
     int32_t *pend;           // n_agents
-    unsigned long long *keys_a, *keys_b;  // n_agents each
+    Mover *mv_a, *mv_b;      // n_agents each: movers of the current / next round
     int32_t *ctr;            // C_NCTR
     unsigned long long *stat;// S_NSTAT
     float *dbg_w;            // optional debug outputs (null in normal runs)

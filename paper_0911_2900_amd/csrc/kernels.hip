@@ -227,6 +227,7 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
     __syncthreads();
     const int na = sh.n_agents;
     const uint32_t kseed0 = s.seed_lo, kseed1 = s.seed_hi;
+    if (tid == 0 && na > 0) atomicAdd(&s.stat[S_PLANNED], (unsigned long long)na);
 
     if (fallback) {
         // every draw of this tile in FP64, one lane per agent
@@ -363,6 +364,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void plan_kernel(const SlotDev *__res
     const int step = s.ctr[C_STEP];
     if (step >= s.ctr[C_LIMIT]) return;
     const int tile_y = tile / s.ntx, tile_x = tile - tile_y * s.ntx;
+    if (tile == 0 && threadIdx.x == 0) s.ctr[C_BAR] = 0;     // fresh barrier for the motion phase
     switch (s.v) {
         case 1: plan_tile<1, DEBUG>(s, tile_x, tile_y, step, sh); break;
         case 2: plan_tile<2, DEBUG>(s, tile_x, tile_y, step, sh); break;
@@ -374,148 +376,231 @@ __global__ __launch_bounds__(PLAN_THREADS) void plan_kernel(const SlotDev *__res
 }
 
 // ---------------------------------------------------------------------------
-// Motion kernel: deterministic reservations, one workgroup per scenario.
+// Motion kernel: deterministic reservations.  A scenario's movers are split
+// over a group of G workgroups that meet at a group barrier between phases;
+// once few movers remain, workgroup 0 finishes the rounds alone.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int isgn(int a) { return (a > 0) - (a < 0); }
 
-__device__ __forceinline__ unsigned long long load_res(const unsigned long long *p)
+__device__ __forceinline__ int ld_agent(const int32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ int load_occ(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_occ(int32_t *p, int v)
+__device__ __forceinline__ void st_agent(int32_t *p, int v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned long long ld_res(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-// Path of an agent from cell c to cell d (padded indices): the DDA line
-// p_k = c + (sgn dx floor((2k|dx| + m) / 2m), sgn dy floor((2k|dy| + m) / 2m)),
-// k = 0..m with m = max(|dx|, |dy|).
-struct Path {
-    int cx, cy, dx, dy, adx, ady, m;
-    __device__ __forceinline__ int cell(int k, int Wp) const
+// Cells of the DDA line from (cx, cy) towards (cx + dx, cy + dy):
+// p_k = (cx + sgn dx floor((2k|dx| + m) / 2m), cy + sgn dy floor((2k|dy| + m) / 2m)),
+// k = 0..m, m = max(|dx|, |dy|).
+struct Line {
+    int cx, cy, sx, sy, adx, ady, m;
+    __device__ __forceinline__ void at(int k, int &x, int &y) const
     {
-        const int px = cx + isgn(dx) * ((2 * k * adx + m) / (2 * m));
-        const int py = cy + isgn(dy) * ((2 * k * ady + m) / (2 * m));
-        return py * Wp + px;
+        x = cx + sx * ((2 * k * adx + m) / (2 * m));
+        y = cy + sy * ((2 * k * ady + m) / (2 * m));
     }
 };
 
-__device__ __forceinline__ Path make_path(int c, int d, int Wp)
+__device__ __forceinline__ Line make_line(uint32_t cxy, uint32_t dxy)
 {
-    Path p;
-    p.cy = c / Wp;
-    p.cx = c - p.cy * Wp;
-    const int ty = d / Wp, tx = d - ty * Wp;
-    p.dx = tx - p.cx;
-    p.dy = ty - p.cy;
-    p.adx = abs(p.dx);
-    p.ady = abs(p.dy);
-    p.m = max(p.adx, p.ady);
-    return p;
+    Line L;
+    L.cx = (int)(cxy & 0xFFFFu);
+    L.cy = (int)(cxy >> 16);
+    const int dx = (int)(dxy & 0xFFFFu) - L.cx, dy = (int)(dxy >> 16) - L.cy;
+    L.sx = isgn(dx);
+    L.sy = isgn(dy);
+    L.adx = abs(dx);
+    L.ady = abs(dy);
+    L.m = max(L.adx, L.ady);
+    return L;
 }
 
-__global__ __launch_bounds__(MOVE_THREADS) void move_kernel(const SlotDev *__restrict__ table,
-                                                            const int32_t *__restrict__ slots)
+// Barrier of the G workgroups of one scenario: arrivals are counted on the
+// slot's C_BAR word (zeroed by the planning kernel), the k-th barrier waits
+// for k*G arrivals.  A wait longer than SPIN_LIMIT polls marks the scenario
+// as failed (C_ERR) instead of hanging.
+__device__ bool group_sync(const SlotDev &s, int G, int &epoch)
 {
-    const SlotDev &s = table[slots[blockIdx.x]];
-    __shared__ int sh_cnt;
-    __shared__ int sh_n;
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    __shared__ int sh_ok;
+    __threadfence();
+    __syncthreads();
+    ++epoch;
+    if (G > 1) {
+        if (threadIdx.x == 0) {
+            atomicAdd(&s.ctr[C_BAR], 1);
+            const int target = epoch * G;
+            uint32_t spins = 0;
+            int ok = 1;
+            while (ld_agent(&s.ctr[C_BAR]) < target) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > SPIN_LIMIT) { ok = 0; atomicOr(&s.ctr[C_ERR], 1); break; }
+            }
+            sh_ok = ok;
+        }
+        __syncthreads();
+        __threadfence();
+        return sh_ok != 0;
+    }
+    return true;
+}
+
+// Reservation phase for movers [lo, hi) of the current list.
+__device__ __forceinline__ void reserve_range(const SlotDev &s, const Mover *cur, int lo, int hi,
+                                              unsigned long long tagw)
+{
+    const int Wp = s.Wp;
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const Mover mv = cur[i];
+        const Line L = make_line(mv.cxy, mv.dxy);
+        const unsigned long long key = mv.key | tagw;
+        for (int k = 0; k <= L.m; ++k) {
+            int x, y;
+            L.at(k, x, y);
+            atomicMax(&s.res[y * Wp + x], key);
+        }
+    }
+}
+
+// Check-and-commit phase: a mover that holds every cell of its line walks it
+// (stopping before a wall, an occupied cell, or a diagonal step past a wall
+// corner; leaving at an exit); the others go to the next round's list.
+__device__ __forceinline__ void commit_range(const SlotDev &s, const Mover *cur, Mover *nxt,
+                                             int *cnt, int lo, int hi, unsigned long long tagw)
+{
+    const int Wp = s.Wp;
+    const int lane = __lane_id();
+    for (int base = lo; base < hi; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        bool loser = false;
+        Mover mv{};
+        if (i < hi) {
+            mv = cur[i];
+            const Line L = make_line(mv.cxy, mv.dxy);
+            const unsigned long long key = mv.key | tagw;
+            bool holds = true;
+            for (int k = 0; k <= L.m; ++k) {
+                int x, y;
+                L.at(k, x, y);
+                holds = holds && ld_res(&s.res[y * Wp + x]) == key;
+            }
+            if (!holds) {
+                loser = true;
+            } else {
+                const int id = (int)(~(uint32_t)mv.key & ID_MASK);
+                const int c = L.cy * Wp + L.cx;
+                int at = c, px = L.cx, py = L.cy;
+                bool gone = false;
+                for (int k = 1; k <= L.m; ++k) {
+                    int qx, qy;
+                    L.at(k, qx, qy);
+                    const int q = qy * Wp + qx;
+                    const uint8_t tq = s.type[q];
+                    if (tq == CELL_WALL) break;
+                    if (ld_agent(&s.occ[q]) != -1) break;
+                    if (qx != px && qy != py) {
+                        if (s.type[py * Wp + qx] == CELL_WALL) break;
+                        if (s.type[qy * Wp + px] == CELL_WALL) break;
+                    }
+                    if (tq == CELL_EXIT) { gone = true; break; }
+                    at = q; px = qx; py = qy;
+                }
+                if (gone) {
+                    st_agent(&s.occ[c], -1);
+                    s.pos[id] = -1;
+                    s.desired[id] = -1;
+                    atomicAdd(&s.ctr[C_EXITED], 1);
+                    atomicSub(&s.ctr[C_NACTIVE], 1);
+                } else if (at != c) {
+                    st_agent(&s.occ[c], -1);
+                    st_agent(&s.occ[at], id);
+                    s.pos[id] = at;
+                }
+            }
+        }
+        // losers to the next list, one atomic per wavefront
+        const unsigned long long mask = __ballot(loser);
+        if (mask) {
+            const int leader = __builtin_ctzll(mask);
+            int b = 0;
+            if (lane == leader) b = atomicAdd(cnt, __popcll(mask));
+            b = __shfl(b, leader);
+            if (loser) nxt[b + __popcll(mask & ((1ull << lane) - 1ull))] = mv;
+        }
+    }
+}
+
+// mitems[i] = slot | g << 12 | (G - 1) << 22: workgroup g of the G that move
+// the slot's agents.
+__global__ __launch_bounds__(MOVE_THREADS) void move_kernel(const SlotDev *__restrict__ table,
+                                                            const uint32_t *__restrict__ mitems)
+{
+    const uint32_t it = mitems[blockIdx.x];
+    const SlotDev &s = table[it & 0xFFFu];
+    int g = (int)((it >> 12) & 0x3FFu);
+    int G = (int)(it >> 22) + 1;
+    const int tid = threadIdx.x;
     const int step = s.ctr[C_STEP];
     if (step >= s.ctr[C_LIMIT]) return;
     const int Wp = s.Wp;
-    int n = s.ctr[C_PEND];
+    const int n0 = s.ctr[C_PEND];
+    int epoch = 0;
 
-    // priority word per mover: [~x0:32][~id:20] (larger = earlier)
-    for (int i = tid; i < n; i += nthr) {
-        const int id = s.pend[i];
-        const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_ORDER,
-                                         s.seed_lo, s.seed_hi);
-        s.keys_a[i] = ((unsigned long long)(~x0) << ID_BITS) |
-                      (unsigned long long)(~(uint32_t)id & ID_MASK);
+    // movers of this step with their priority words [~x0:32][~id:20] (larger = earlier)
+    {
+        const int lo = (int)((long)n0 * g / G), hi = (int)((long)n0 * (g + 1) / G);
+        for (int i = lo + tid; i < hi; i += blockDim.x) {
+            const int id = s.pend[i];
+            const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_ORDER,
+                                             s.seed_lo, s.seed_hi);
+            const int c = s.pos[id], d = s.desired[id];
+            const int cy = c / Wp, dy = d / Wp;
+            Mover mv;
+            mv.key = ((unsigned long long)(~x0) << ID_BITS) | (unsigned long long)(~(uint32_t)id & ID_MASK);
+            mv.cxy = (uint32_t)(c - cy * Wp) | ((uint32_t)cy << 16);
+            mv.dxy = (uint32_t)(d - dy * Wp) | ((uint32_t)dy << 16);
+            s.mv_a[i] = mv;
+        }
     }
-    uint32_t tag = (uint32_t)s.ctr[C_TAG];
-    int rounds = 0;
-    unsigned long long *cur = s.keys_a, *nxt = s.keys_b;
-    __threadfence();
-    __syncthreads();
+    if (!group_sync(s, G, epoch)) return;
 
+    uint32_t tag = (uint32_t)s.ctr[C_TAG];
+    int rounds = 0, n = n0;
+    Mover *cur = s.mv_a, *nxt = s.mv_b;
     while (n > 0) {
+        if (G > 1 && n <= MOVE_SOLO_N) {
+            if (g != 0) return;       // workgroup 0 finishes the rounds alone
+            G = 1;
+            g = 0;
+        }
+        int *cnt = &s.ctr[(rounds & 1) ? C_CNT1 : C_CNT0];
         ++rounds;
         if (tag >= TAG_LIMIT) {
             // tags are exhausted: wipe the reservation words, restart at 1
-            const int cells = s.Wp * s.Hp;
-            for (int i = tid; i < cells; i += nthr)
+            const long cells = (long)s.Wp * s.Hp;
+            const long lo = cells * g / G, hi = cells * (g + 1) / G;
+            for (long i = lo + tid; i < hi; i += blockDim.x)
                 __hip_atomic_store(&s.res[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tag = 0;
-            __threadfence();
-            __syncthreads();
+            if (!group_sync(s, G, epoch)) return;
         }
         ++tag;
-        if (tid == 0) sh_cnt = 0;
         const unsigned long long tagw = (unsigned long long)tag << TAG_SHIFT;
-
-        // reserve every cell of the path, the start cell included
-        for (int i = tid; i < n; i += nthr) {
-            const unsigned long long key = cur[i] | tagw;
-            const int id = (int)(~(uint32_t)cur[i] & ID_MASK);
-            const Path p = make_path(s.pos[id], s.desired[id], Wp);
-            for (int k = 0; k <= p.m; ++k) atomicMax(&s.res[p.cell(k, Wp)], key);
-        }
-        __threadfence();
-        __syncthreads();
-
-        // agents holding all their cells move; the others wait for the next round
-        for (int i = tid; i < n; i += nthr) {
-            const unsigned long long key = cur[i] | tagw;
-            const int id = (int)(~(uint32_t)cur[i] & ID_MASK);
-            const int c = s.pos[id];
-            const Path p = make_path(c, s.desired[id], Wp);
-            bool holds = true;
-            for (int k = 0; k <= p.m; ++k) holds = holds && load_res(&s.res[p.cell(k, Wp)]) == key;
-            if (!holds) {
-                nxt[atomicAdd(&sh_cnt, 1)] = cur[i];
-                continue;
-            }
-            int at = c, px = p.cx, py = p.cy;
-            bool gone = false;
-            for (int k = 1; k <= p.m; ++k) {
-                const int q = p.cell(k, Wp);
-                const int qy = q / Wp, qx = q - qy * Wp;
-                if (s.type[q] == CELL_WALL) break;
-                if (load_occ(&s.occ[q]) != -1) break;
-                if (qx != px && qy != py) {
-                    if (s.type[py * Wp + qx] == CELL_WALL) break;
-                    if (s.type[qy * Wp + px] == CELL_WALL) break;
-                }
-                if (s.type[q] == CELL_EXIT) { gone = true; break; }
-                at = q; px = qx; py = qy;
-            }
-            if (gone) {
-                store_occ(&s.occ[c], -1);
-                s.pos[id] = -1;
-                s.desired[id] = -1;
-                atomicAdd(&s.ctr[C_EXITED], 1);
-                atomicSub(&s.ctr[C_NACTIVE], 1);
-            } else if (at != c) {
-                store_occ(&s.occ[c], -1);
-                store_occ(&s.occ[at], id);
-                s.pos[id] = at;
-            }
-        }
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) sh_n = sh_cnt;
-        __syncthreads();
-        n = sh_n;
-        unsigned long long *t = cur; cur = nxt; nxt = t;
+        if (g == 0 && tid == 0) st_agent(cnt, 0);
+        const int lo = (int)((long)n * g / G), hi = (int)((long)n * (g + 1) / G);
+        reserve_range(s, cur, lo, hi, tagw);
+        if (!group_sync(s, G, epoch)) return;
+        commit_range(s, cur, nxt, cnt, lo, hi, tagw);
+        if (!group_sync(s, G, epoch)) return;
+        n = ld_agent(cnt);
+        Mover *t = cur; cur = nxt; nxt = t;
     }
-    __syncthreads();
-    if (tid == 0) {
+    if (g == 0 && tid == 0) {
         s.ctr[C_TAG] = (int)tag;
         s.ctr[C_ROUNDS] = rounds;
         s.ctr[C_PEND] = 0;
@@ -548,13 +633,28 @@ extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *i
     return hipGetLastError();
 }
 
-extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const int32_t *slots, int n_slots,
+extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,
                                      hipStream_t stream)
 {
-    if (n_slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fk::move_kernel, dim3(n_slots), dim3(fk::MOVE_THREADS), 0, stream, table,
-                       slots);
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fk::move_kernel, dim3(n_items), dim3(fk::MOVE_THREADS), 0, stream, table,
+                       mitems);
     return hipGetLastError();
+}
+
+// Workgroups of move_kernel that one device holds at once.
+extern "C" hipError_t fk_move_capacity(int *blocks)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fk::move_kernel,
+                                                                fk::MOVE_THREADS, 0);
+    if (e != hipSuccess) return e;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *blocks = per_cu * cus;
+    return hipSuccess;
 }
 
 extern "C" hipError_t fk_launch_reset(const fk::SlotDev *table, const int32_t *slots, int n_slots,

@@ -55,7 +55,9 @@ struct Slot {
     size_t bytes = 0;
     uint32_t *items = nullptr;   // device: plan work items of this slot alone
     int32_t *self = nullptr;     // device: [slot index]
+    uint32_t *mitems = nullptr;  // device: motion work items of this slot alone
     int n_items = 0;
+    int group = 1;               // motion workgroups when stepped alone
     int n_fb_tiles = 0;
     int host_steps = 0;          // steps launched (== device step once the stream drains)
     bool planned = false;        // a plan was launched after the last motion phase
@@ -66,7 +68,8 @@ struct Batch {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     uint32_t *items = nullptr;
-    int32_t *slots = nullptr;
+    uint32_t *mitems = nullptr;
+    int n_mitems = 0;
     void *block = nullptr;
     size_t bytes = 0;
     std::vector<int32_t> members;
@@ -102,6 +105,7 @@ struct fast_ctx {
     fast_free_fn free_fn = nullptr;
     void *user = nullptr;
     fk::SlotDev *table = nullptr;    // device, FAST_MAX_SLOTS entries
+    int move_capacity = 0;           // motion workgroups the device holds at once
     std::vector<Slot> slots;
     std::map<std::vector<int32_t>, Batch> batches;
     std::recursive_mutex mu;         // guards everything above
@@ -165,6 +169,41 @@ void choose_tile(int W, int H, int v, int *tx, int *ty)
 }
 
 bool valid_tile_dim(int t) { return t == 8 || t == 16 || t == 32 || t == 64; }
+
+// Motion workgroups for a scenario of n agents: one per MOVE_AGENTS_PER_WG
+// agents, at most MOVE_GROUP_MAX.
+int motion_group(int n)
+{
+    const int g = (n + fk::MOVE_AGENTS_PER_WG - 1) / fk::MOVE_AGENTS_PER_WG;
+    return std::max(1, std::min(g, fk::MOVE_GROUP_MAX));
+}
+
+uint32_t motion_item(int32_t slot, int g, int G)
+{
+    return (uint32_t)slot | ((uint32_t)g << 12) | ((uint32_t)(G - 1) << 22);
+}
+
+// Group sizes for a batch: the workgroups of scenarios that use a group
+// barrier must all fit on the device at once, with room to spare; larger
+// groups are shrunk until they do.
+std::vector<int> batch_groups(const fast_ctx *c, const std::vector<int32_t> &hs)
+{
+    std::vector<int> G(hs.size());
+    long total = 0;
+    for (size_t i = 0; i < hs.size(); ++i) {
+        G[i] = motion_group(c->slots[hs[i]].n_agents);
+        if (G[i] > 1) total += G[i];
+    }
+    const long cap = std::max(2, c->move_capacity / 2);
+    while (total > cap) {
+        total = 0;
+        for (size_t i = 0; i < hs.size(); ++i) {
+            if (G[i] > 1) G[i] = std::max(1, G[i] / 2);
+            if (G[i] > 1) total += G[i];
+        }
+    }
+    return G;
+}
 
 fast_status check_desc(const fast_scenario_desc *d)
 {
@@ -240,9 +279,10 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     const size_t o_S = take(cells * 8), o_res = take(cells * 8), o_G = take(cells * 4),
                  o_occ = take(cells * 4), o_type = take(cells), o_tm = take(tm * 4),
                  o_fb = take(ntiles), o_pos = take(n * 4), o_des = take(n * 4),
-                 o_pend = take(n * 4), o_ka = take(n * 8), o_kb = take(n * 8),
-                 o_ctr = take(fk::C_NCTR * 4), o_stat = take(fk::S_NSTAT * 8),
-                 o_items = take(ntiles * 4), o_self = take(4);
+                 o_pend = take(n * 4), o_ka = take(n * sizeof(fk::Mover)),
+                 o_kb = take(n * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
+                 o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
+                 o_mitems = take(fk::MOVE_GROUP_MAX * 4);
     void *block = nullptr;
     st = dev_alloc(c, off, &block);
     if (st) return st;
@@ -263,8 +303,8 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     sd.pos = (int32_t *)(base + o_pos);
     sd.desired = (int32_t *)(base + o_des);
     sd.pend = (int32_t *)(base + o_pend);
-    sd.keys_a = (unsigned long long *)(base + o_ka);
-    sd.keys_b = (unsigned long long *)(base + o_kb);
+    sd.mv_a = (fk::Mover *)(base + o_ka);
+    sd.mv_b = (fk::Mover *)(base + o_kb);
     sd.ctr = (int32_t *)(base + o_ctr);
     sd.stat = (unsigned long long *)(base + o_stat);
 
@@ -274,6 +314,10 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     std::vector<uint32_t> items(ntiles);
     for (size_t i = 0; i < ntiles; ++i) items[i] = ((uint32_t)h << 20) | (uint32_t)i;
     const int32_t self = h;
+    int group = motion_group(b.n);
+    if (group > std::max(2, c->move_capacity / 2)) group = std::max(1, c->move_capacity / 2);
+    std::vector<uint32_t> mitems((size_t)group);
+    for (int g = 0; g < group; ++g) mitems[g] = motion_item(h, g, group);
 
     hipError_t e = hipSuccess;
     auto cp = [&](size_t o, const void *src, size_t bytes) {
@@ -292,6 +336,7 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     if (e == hipSuccess) e = hipMemset(base + o_stat, 0, fk::S_NSTAT * 8);
     cp(o_items, items.data(), ntiles * 4);
     cp(o_self, &self, 4);
+    cp(o_mitems, mitems.data(), mitems.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         dev_free(c, block, off);
@@ -306,6 +351,8 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     s.bytes = off;
     s.items = (uint32_t *)(base + o_items);
     s.self = (int32_t *)(base + o_self);
+    s.mitems = (uint32_t *)(base + o_mitems);
+    s.group = group;
     s.n_items = (int)ntiles;
     s.n_fb_tiles = b.n_fb;
     s.n_agents = b.n;
@@ -331,6 +378,8 @@ fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_
     const int n = s->n_agents;
     std::vector<int32_t> pos((size_t)std::max(n, 1)), des((size_t)std::max(n, 1)), ctr(fk::C_NCTR);
     HIP_TRY(hipMemcpy(ctr.data(), s->dev.ctr, fk::C_NCTR * 4, hipMemcpyDeviceToHost));
+    if (ctr[fk::C_ERR])
+        return fail(FAST_E_DEVICE, "a motion-phase group barrier timed out: the scenario state is invalid");
     if (n) {
         HIP_TRY(hipMemcpy(pos.data(), s->dev.pos, (size_t)n * 4, hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(des.data(), s->dev.desired, (size_t)n * 4, hipMemcpyDeviceToHost));
@@ -368,22 +417,27 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
         const Slot &s = c->slots[h];
         for (int i = 0; i < s.n_items; ++i) items.push_back(((uint32_t)h << 20) | (uint32_t)i);
     }
+    const std::vector<int> G = batch_groups(c, order);
+    std::vector<uint32_t> mitems;
+    for (size_t i = 0; i < order.size(); ++i)
+        for (int g = 0; g < G[i]; ++g) mitems.push_back(motion_item(order[i], g, G[i]));
     Batch b;
     b.members = hs;
     const size_t ib = align_up(items.size() * 4, 256);
-    b.bytes = ib + order.size() * 4;
+    b.bytes = ib + mitems.size() * 4;
     fast_status st = dev_alloc(c, b.bytes, &b.block);
     if (st) return st;
     b.items = (uint32_t *)b.block;
-    b.slots = (int32_t *)((char *)b.block + ib);
+    b.mitems = (uint32_t *)((char *)b.block + ib);
+    b.n_mitems = (int)mitems.size();
     HIP_TRY(hipMemcpy(b.items, items.data(), items.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b.slots, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b.mitems, mitems.data(), mitems.size() * 4, hipMemcpyHostToDevice));
 
     // capture one time step: one planning launch over every tile, one motion
     // launch with a workgroup per scenario
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = fk_launch_plan(c->table, b.items, (int)items.size(), 0, c->stream);
-    hipError_t e2 = fk_launch_move(c->table, b.slots, (int)order.size(), c->stream);
+    hipError_t e2 = fk_launch_move(c->table, b.mitems, b.n_mitems, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b.graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         if (b.graph) (void)hipGraphDestroy(b.graph);
@@ -587,6 +641,7 @@ fast_status fast_ctx_create(int device, void *hip_stream, size_t hbm_budget, fas
         HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
     }
+    HIP_TRY(fk_move_capacity(&c->move_capacity));
     hipError_t e = hipMalloc(&c->table, sizeof(fk::SlotDev) * FAST_MAX_SLOTS);
     if (e != hipSuccess) {
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -651,7 +706,7 @@ fast_status fast_move_step(fast_ctx *c, int32_t h)
     Slot *s = get_slot(c, h);
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     if (!s->planned) return fail(FAST_E_STATE, "scenario %d: motion without a plan of this step", h);
-    HIP_TRY(fk_launch_move(c->table, s->self, 1, c->stream));
+    HIP_TRY(fk_launch_move(c->table, s->mitems, s->group, c->stream));
     s->planned = false;
     s->host_steps += 1;
     return FAST_OK;
@@ -689,6 +744,8 @@ fast_status fast_get_stats(fast_ctx *c, int32_t h, fast_stats *out)
     unsigned long long stat[fk::S_NSTAT];
     HIP_TRY(hipMemcpy(ctr, s->dev.ctr, sizeof ctr, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(stat, s->dev.stat, sizeof stat, hipMemcpyDeviceToHost));
+    if (ctr[fk::C_ERR])
+        return fail(FAST_E_DEVICE, "a motion-phase group barrier timed out: the scenario state is invalid");
     std::memset(out, 0, sizeof *out);
     out->step = ctr[fk::C_STEP];
     out->n_agents = s->n_agents;
@@ -703,6 +760,7 @@ fast_status fast_get_stats(fast_ctx *c, int32_t h, fast_stats *out)
     out->n_fallback_tiles = s->n_fb_tiles;
     out->guard_band = s->dev.eps;
     out->device_bytes = (int64_t)s->bytes;
+    out->planned = (int64_t)stat[fk::S_PLANNED];
     return FAST_OK;
 }
 

@@ -43,6 +43,7 @@ class Stats(ctypes.Structure):
         ("last_rounds", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
         ("n_tiles", ctypes.c_int32), ("n_fallback_tiles", ctypes.c_int32),
         ("guard_band", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+        ("planned", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
