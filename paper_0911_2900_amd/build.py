@@ -11,6 +11,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfast.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CLANGXX = os.environ.get("CLANGXX", "/opt/rocm/llvm/bin/clang++")   # host-only C++ sources
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function",
@@ -39,7 +40,8 @@ def build(verbose: bool = False) -> str:
         if src.endswith(".hip"):
             cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, "-c", path, "-o", obj]
         else:
-            cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
+            cmd = [CLANGXX, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON,
+                   "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         _run(cmd)

@@ -8,7 +8,8 @@
 //   cell (x, y) of the scenario lives at index (y + v) * Wp + (x + v).
 // Per cell:  type u8 (static), G f32 (static exp table, see below),
 //            S f64 (static floor field, read only by the FP64 re-resolve),
-//            occ i32 (agent id or -1), res u64 (motion reservations).
+//            occ i32 (agent id or -1), res0/res1 u64 (motion reservations of
+//            even / odd rounds).
 // Per agent: pos i32 (padded cell, -1 once gone), desired i32, a pending id
 //            and two reservation-key lists for the motion rounds.
 // Per tile:  m i32 (power-of-two scale of the exp table), fallback u8.
@@ -33,10 +34,9 @@ constexpr int MAX_V = 5;
 constexpr int MAX_TILE_CELLS = 1024;   // tx * ty
 constexpr int MAX_STAGE = 2048;        // (tx + 2v)(ty + 2v) over the allowed tiles
 constexpr int PLAN_THREADS = 256;
-constexpr int MOVE_THREADS = 256;
+constexpr int MOVE_THREADS = 1024;
 constexpr int MOVE_GROUP_MAX = 64;        // workgroups per scenario in the motion phase
 constexpr int MOVE_AGENTS_PER_WG = 1024;  // group size = ceil(agents / this), capped
-constexpr int MOVE_SOLO_N = 2048;         // rounds with fewer movers run in one workgroup
 constexpr uint32_t SPIN_LIMIT = 1u << 22; // bound on a group-barrier wait (never hangs)
 
 // Motion reservation words: [tag:12][~x0:32][~id:20]; the largest word on a
@@ -55,9 +55,8 @@ enum : int {
     C_TAG = 4,       // last reservation tag used
     C_ROUNDS = 5,    // reservation rounds of the last motion phase
     C_LIMIT = 6,     // kernels act while step < limit
-    C_CNT0 = 7,      // movers left after an even / odd reservation round
-    C_CNT1 = 8,
-    C_BAR = 9,       // group-barrier arrivals of the running motion phase
+    C_BAR = 12,      // 2 x uint64 (C_BAR..C_BAR+3): group-barrier words of even / odd
+                     // rounds, [arrivals:32][movers left:32], zeroed by the plan kernel
     C_ERR = 10,      // nonzero: a group barrier timed out, the state is invalid
     C_NCTR = 16
 };
@@ -87,7 +86,8 @@ struct SlotDev {
     const int32_t *tile_m;   // (ntx+2)*(nty+2), a ring of zeros around
     const uint8_t *tile_fb;  // ntx*nty
     int32_t *occ;            // Wp*Hp
-    unsigned long long *res; // Wp*Hp
+    unsigned long long *res0;// Wp*Hp, reservations of even rounds
+    unsigned long long *res1;// Wp*Hp, reservations of odd rounds
     int32_t *pos;            // n_agents
     int32_t *desired;        // n_agents
     int32_t *pend;           // n_agents

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fast.h"
+#include "fast.h"
 #include "fast_dev.h"
 
 namespace fh {

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(PLAN_THREADS) void plan_kernel(const SlotDev *__res
     const int step = s.ctr[C_STEP];
     if (step >= s.ctr[C_LIMIT]) return;
     const int tile_y = tile / s.ntx, tile_x = tile - tile_y * s.ntx;
-    if (tile == 0 && threadIdx.x == 0) s.ctr[C_BAR] = 0;     // fresh barrier for the motion phase
+    if (tile == 0 && threadIdx.x < 4) s.ctr[C_BAR + threadIdx.x] = 0;   // fresh motion barriers
     switch (s.v) {
         case 1: plan_tile<1, DEBUG>(s, tile_x, tile_y, step, sh); break;
         case 2: plan_tile<2, DEBUG>(s, tile_x, tile_y, step, sh); break;
@@ -376,9 +376,13 @@ __global__ __launch_bounds__(PLAN_THREADS) void plan_kernel(const SlotDev *__res
 }
 
 // ---------------------------------------------------------------------------
-// Motion kernel: deterministic reservations.  A scenario's movers are split
-// over a group of G workgroups that meet at a group barrier between phases;
-// once few movers remain, workgroup 0 finishes the rounds alone.
+// Motion kernel: deterministic reservations.  The movers of a scenario are
+// split over a group of G workgroups; each keeps its share in a private list.
+// Round r reserves into res[r & 1] with tag r (tags grow, so stale words of
+// earlier rounds always lose), so the checks of round r and the reservations
+// of round r + 1 never touch the same array and one group barrier per round
+// suffices:
+//     reserve r+1 (own losers) | count | barrier | check r+1, commit, ...
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int isgn(int a) { return (a > 0) - (a < 0); }
 
@@ -397,7 +401,7 @@ __device__ __forceinline__ unsigned long long ld_res(const unsigned long long *p
 
 // Cells of the DDA line from (cx, cy) towards (cx + dx, cy + dy):
 // p_k = (cx + sgn dx floor((2k|dx| + m) / 2m), cy + sgn dy floor((2k|dy| + m) / 2m)),
-// k = 0..m, m = max(|dx|, |dy|).
+// k = 0..m, m = max(|dx|, |dy|) <= v.
 struct Line {
     int cx, cy, sx, sy, adx, ady, m;
     __device__ __forceinline__ void at(int k, int &x, int &y) const
@@ -421,117 +425,192 @@ __device__ __forceinline__ Line make_line(uint32_t cxy, uint32_t dxy)
     return L;
 }
 
-// Barrier of the G workgroups of one scenario: arrivals are counted on the
-// slot's C_BAR word (zeroed by the planning kernel), the k-th barrier waits
-// for k*G arrivals.  A wait longer than SPIN_LIMIT polls marks the scenario
-// as failed (C_ERR) instead of hanging.
-__device__ bool group_sync(const SlotDev &s, int G, int &epoch)
+// Barrier of the G workgroups of one scenario that also sums their mover
+// counts.  Round r uses the 64-bit word bar[r & 1] = [arrivals:32][count:32]
+// (both zeroed by the planning kernel): each workgroup adds (1 << 32) | n and
+// waits until the arrivals reach (r / 2 + 1) * G.  A word is touched again only
+// two barriers later, after every workgroup has read it, so the count part
+// minus its value at the previous barrier of the same parity is this round's
+// total.  All data shared between the workgroups moves through agent-scope
+// atomics; the fences of thread 0 order them around the arrival.  A wait
+// longer than SPIN_LIMIT polls marks the scenario as failed (C_ERR) instead of
+// hanging; the function then returns -1.
+__device__ int group_sync_count(const SlotDev &s, int G, int r, int n, unsigned long long &seen0,
+                                unsigned long long &seen1)
 {
-    __shared__ int sh_ok;
-    __threadfence();
+    __shared__ int sh_total;
     __syncthreads();
-    ++epoch;
-    if (G > 1) {
-        if (threadIdx.x == 0) {
-            atomicAdd(&s.ctr[C_BAR], 1);
-            const int target = epoch * G;
-            uint32_t spins = 0;
-            int ok = 1;
-            while (ld_agent(&s.ctr[C_BAR]) < target) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > SPIN_LIMIT) { ok = 0; atomicOr(&s.ctr[C_ERR], 1); break; }
-            }
-            sh_ok = ok;
-        }
-        __syncthreads();
+    if (G == 1) return n;
+    if (threadIdx.x == 0) {
+        unsigned long long *bar = (unsigned long long *)&s.ctr[C_BAR] + (r & 1);
+        unsigned long long &seen = (r & 1) ? seen1 : seen0;
         __threadfence();
-        return sh_ok != 0;
+        atomicAdd(bar, (1ull << 32) | (unsigned long long)(uint32_t)n);
+        const unsigned long long target = (unsigned long long)(r / 2 + 1) * (unsigned long long)G;
+        uint32_t spins = 0;
+        unsigned long long w;
+        int total = -1;
+        for (;;) {
+            w = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((w >> 32) >= target) { total = (int)((uint32_t)w - (uint32_t)seen); seen = w; break; }
+            if (++spins > SPIN_LIMIT) { atomicOr(&s.ctr[C_ERR], 1); break; }
+        }
+        __threadfence();
+        sh_total = total;
     }
-    return true;
+    __syncthreads();
+    return sh_total;
 }
 
-// Reservation phase for movers [lo, hi) of the current list.
-__device__ __forceinline__ void reserve_range(const SlotDev &s, const Mover *cur, int lo, int hi,
-                                              unsigned long long tagw)
+template <int V>
+__device__ __forceinline__ void reserve_list(const SlotDev &s, unsigned long long *res,
+                                             const Mover *list, int n, unsigned long long tagw)
 {
     const int Wp = s.Wp;
-    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const Mover mv = list[i];
+        const Line L = make_line(mv.cxy, mv.dxy);
+        const unsigned long long key = mv.key | tagw;
+#pragma unroll
+        for (int k = 0; k <= V; ++k) {
+            if (k <= L.m) {
+                int x, y;
+                L.at(k, x, y);
+                atomicMax(&res[y * Wp + x], key);
+            }
+        }
+    }
+}
+
+// Check-and-commit for the workgroup's list: a mover holding every cell of
+// its line walks it (stopping before a wall, an occupied cell, or a diagonal
+// step past a wall corner; leaving at an exit); the others are appended to
+// `nxt`.  Returns the number appended.
+template <int V>
+__device__ int commit_list(const SlotDev &s, const unsigned long long *res, const Mover *cur,
+                           Mover *nxt, int n, unsigned long long tagw)
+{
+    __shared__ int sh_cnt;
+    const int Wp = s.Wp;
+    if (threadIdx.x == 0) sh_cnt = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const Mover mv = cur[i];
         const Line L = make_line(mv.cxy, mv.dxy);
         const unsigned long long key = mv.key | tagw;
-        for (int k = 0; k <= L.m; ++k) {
-            int x, y;
-            L.at(k, x, y);
-            atomicMax(&s.res[y * Wp + x], key);
+        int cell[V + 1];
+        unsigned long long w[V + 1];
+        int o[V + 1];
+#pragma unroll
+        for (int k = 0; k <= V; ++k) {
+            int x = L.cx, y = L.cy;
+            if (k <= L.m) L.at(k, x, y);
+            cell[k] = y * Wp + x;
+            w[k] = k <= L.m ? ld_res(&res[cell[k]]) : key;
+            o[k] = (k >= 1 && k <= L.m) ? ld_agent(&s.occ[cell[k]]) : -1;
+        }
+        bool holds = true;
+#pragma unroll
+        for (int k = 0; k <= V; ++k) holds &= (w[k] == key);
+        if (!holds) {
+            nxt[atomicAdd(&sh_cnt, 1)] = mv;
+            continue;
+        }
+        const int id = (int)(~(uint32_t)mv.key & ID_MASK);
+        const int c = cell[0];
+        int at = c, px = L.cx, py = L.cy;
+        bool gone = false, stop = false;
+#pragma unroll
+        for (int k = 1; k <= V; ++k) {
+            if (k > L.m || stop) break;
+            int qx, qy;
+            L.at(k, qx, qy);
+            const int q = cell[k];
+            const uint8_t tq = s.type[q];
+            if (tq == CELL_WALL || o[k] != -1) { stop = true; break; }
+            if (qx != px && qy != py &&
+                (s.type[py * Wp + qx] == CELL_WALL || s.type[qy * Wp + px] == CELL_WALL)) {
+                stop = true;
+                break;
+            }
+            if (tq == CELL_EXIT) { gone = true; break; }
+            at = q; px = qx; py = qy;
+        }
+        if (gone) {
+            st_agent(&s.occ[c], -1);
+            s.pos[id] = -1;
+            s.desired[id] = -1;
+            atomicAdd(&s.ctr[C_EXITED], 1);
+            atomicSub(&s.ctr[C_NACTIVE], 1);
+        } else if (at != c) {
+            st_agent(&s.occ[c], -1);
+            st_agent(&s.occ[at], id);
+            s.pos[id] = at;
         }
     }
+    __syncthreads();
+    return sh_cnt;
 }
 
-// Check-and-commit phase: a mover that holds every cell of its line walks it
-// (stopping before a wall, an occupied cell, or a diagonal step past a wall
-// corner; leaving at an exit); the others go to the next round's list.
-__device__ __forceinline__ void commit_range(const SlotDev &s, const Mover *cur, Mover *nxt,
-                                             int *cnt, int lo, int hi, unsigned long long tagw)
+template <int V>
+__device__ void move_group(const SlotDev &s, int g, int G, int step)
 {
+    const int tid = threadIdx.x;
     const int Wp = s.Wp;
-    const int lane = __lane_id();
-    for (int base = lo; base < hi; base += blockDim.x) {
-        const int i = base + threadIdx.x;
-        bool loser = false;
-        Mover mv{};
-        if (i < hi) {
-            mv = cur[i];
-            const Line L = make_line(mv.cxy, mv.dxy);
-            const unsigned long long key = mv.key | tagw;
-            bool holds = true;
-            for (int k = 0; k <= L.m; ++k) {
-                int x, y;
-                L.at(k, x, y);
-                holds = holds && ld_res(&s.res[y * Wp + x]) == key;
-            }
-            if (!holds) {
-                loser = true;
-            } else {
-                const int id = (int)(~(uint32_t)mv.key & ID_MASK);
-                const int c = L.cy * Wp + L.cx;
-                int at = c, px = L.cx, py = L.cy;
-                bool gone = false;
-                for (int k = 1; k <= L.m; ++k) {
-                    int qx, qy;
-                    L.at(k, qx, qy);
-                    const int q = qy * Wp + qx;
-                    const uint8_t tq = s.type[q];
-                    if (tq == CELL_WALL) break;
-                    if (ld_agent(&s.occ[q]) != -1) break;
-                    if (qx != px && qy != py) {
-                        if (s.type[py * Wp + qx] == CELL_WALL) break;
-                        if (s.type[qy * Wp + px] == CELL_WALL) break;
-                    }
-                    if (tq == CELL_EXIT) { gone = true; break; }
-                    at = q; px = qx; py = qy;
-                }
-                if (gone) {
-                    st_agent(&s.occ[c], -1);
-                    s.pos[id] = -1;
-                    s.desired[id] = -1;
-                    atomicAdd(&s.ctr[C_EXITED], 1);
-                    atomicSub(&s.ctr[C_NACTIVE], 1);
-                } else if (at != c) {
-                    st_agent(&s.occ[c], -1);
-                    st_agent(&s.occ[at], id);
-                    s.pos[id] = at;
-                }
-            }
+    const int n0 = s.ctr[C_PEND];
+    const int lo = (int)((long)n0 * g / G), hi = (int)((long)n0 * (g + 1) / G);
+    Mover *cur = s.mv_a + lo, *nxt = s.mv_b + lo;
+    unsigned long long seen0 = 0, seen1 = 0;
+    uint32_t tag = (uint32_t)s.ctr[C_TAG];
+
+    // this workgroup's movers with priority words [~x0:32][~id:20] (larger = earlier)
+    int n = hi - lo;
+    for (int i = tid; i < n; i += blockDim.x) {
+        const int id = s.pend[lo + i];
+        const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_ORDER,
+                                         s.seed_lo, s.seed_hi);
+        const int c = s.pos[id], d = s.desired[id];
+        const int cy = c / Wp, dy = d / Wp;
+        Mover mv;
+        mv.key = ((unsigned long long)(~x0) << ID_BITS) | (unsigned long long)(~(uint32_t)id & ID_MASK);
+        mv.cxy = (uint32_t)(c - cy * Wp) | ((uint32_t)cy << 16);
+        mv.dxy = (uint32_t)(d - dy * Wp) | ((uint32_t)dy << 16);
+        cur[i] = mv;
+    }
+    __syncthreads();
+
+    int total = n0, rounds = 0, bar_r = 0;
+    for (int r = 0; total > 0; ++r) {
+        unsigned long long *res = (r & 1) ? s.res1 : s.res0;
+        if (r > 0) {
+            // round r's movers are the losers of round r - 1 (this workgroup's share)
+            n = commit_list<V>(s, (r & 1) ? s.res0 : s.res1, cur, nxt, n,
+                               (unsigned long long)tag << TAG_SHIFT);
+            Mover *t = cur; cur = nxt; nxt = t;
         }
-        // losers to the next list, one atomic per wavefront
-        const unsigned long long mask = __ballot(loser);
-        if (mask) {
-            const int leader = __builtin_ctzll(mask);
-            int b = 0;
-            if (lane == leader) b = atomicAdd(cnt, __popcll(mask));
-            b = __shfl(b, leader);
-            if (loser) nxt[b + __popcll(mask & ((1ull << lane) - 1ull))] = mv;
+        if (tag >= TAG_LIMIT) {
+            // tags are exhausted: once every check of the last round is done,
+            // wipe both reservation arrays and restart the tags at 1
+            if (group_sync_count(s, G, bar_r++, 0, seen0, seen1) < 0) return;
+            const long cells = (long)s.Wp * s.Hp;
+            for (long i = cells * g / G + tid; i < cells * (g + 1) / G; i += blockDim.x) {
+                __hip_atomic_store(&s.res0[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&s.res1[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            tag = 0;
+            if (group_sync_count(s, G, bar_r++, 0, seen0, seen1) < 0) return;
         }
+        ++tag;
+        reserve_list<V>(s, res, cur, n, (unsigned long long)tag << TAG_SHIFT);
+        total = group_sync_count(s, G, bar_r++, n, seen0, seen1);
+        if (total < 0) return;
+        rounds += total > 0 ? 1 : 0;
+    }
+    if (g == 0 && tid == 0) {
+        s.ctr[C_TAG] = (int)tag;
+        s.ctr[C_ROUNDS] = rounds;
+        s.ctr[C_PEND] = 0;
+        s.ctr[C_STEP] = step + 1;
     }
 }
 
@@ -542,69 +621,17 @@ __global__ __launch_bounds__(MOVE_THREADS) void move_kernel(const SlotDev *__res
 {
     const uint32_t it = mitems[blockIdx.x];
     const SlotDev &s = table[it & 0xFFFu];
-    int g = (int)((it >> 12) & 0x3FFu);
-    int G = (int)(it >> 22) + 1;
-    const int tid = threadIdx.x;
+    const int g = (int)((it >> 12) & 0x3FFu);
+    const int G = (int)(it >> 22) + 1;
     const int step = s.ctr[C_STEP];
     if (step >= s.ctr[C_LIMIT]) return;
-    const int Wp = s.Wp;
-    const int n0 = s.ctr[C_PEND];
-    int epoch = 0;
-
-    // movers of this step with their priority words [~x0:32][~id:20] (larger = earlier)
-    {
-        const int lo = (int)((long)n0 * g / G), hi = (int)((long)n0 * (g + 1) / G);
-        for (int i = lo + tid; i < hi; i += blockDim.x) {
-            const int id = s.pend[i];
-            const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_ORDER,
-                                             s.seed_lo, s.seed_hi);
-            const int c = s.pos[id], d = s.desired[id];
-            const int cy = c / Wp, dy = d / Wp;
-            Mover mv;
-            mv.key = ((unsigned long long)(~x0) << ID_BITS) | (unsigned long long)(~(uint32_t)id & ID_MASK);
-            mv.cxy = (uint32_t)(c - cy * Wp) | ((uint32_t)cy << 16);
-            mv.dxy = (uint32_t)(d - dy * Wp) | ((uint32_t)dy << 16);
-            s.mv_a[i] = mv;
-        }
-    }
-    if (!group_sync(s, G, epoch)) return;
-
-    uint32_t tag = (uint32_t)s.ctr[C_TAG];
-    int rounds = 0, n = n0;
-    Mover *cur = s.mv_a, *nxt = s.mv_b;
-    while (n > 0) {
-        if (G > 1 && n <= MOVE_SOLO_N) {
-            if (g != 0) return;       // workgroup 0 finishes the rounds alone
-            G = 1;
-            g = 0;
-        }
-        int *cnt = &s.ctr[(rounds & 1) ? C_CNT1 : C_CNT0];
-        ++rounds;
-        if (tag >= TAG_LIMIT) {
-            // tags are exhausted: wipe the reservation words, restart at 1
-            const long cells = (long)s.Wp * s.Hp;
-            const long lo = cells * g / G, hi = cells * (g + 1) / G;
-            for (long i = lo + tid; i < hi; i += blockDim.x)
-                __hip_atomic_store(&s.res[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            tag = 0;
-            if (!group_sync(s, G, epoch)) return;
-        }
-        ++tag;
-        const unsigned long long tagw = (unsigned long long)tag << TAG_SHIFT;
-        if (g == 0 && tid == 0) st_agent(cnt, 0);
-        const int lo = (int)((long)n * g / G), hi = (int)((long)n * (g + 1) / G);
-        reserve_range(s, cur, lo, hi, tagw);
-        if (!group_sync(s, G, epoch)) return;
-        commit_range(s, cur, nxt, cnt, lo, hi, tagw);
-        if (!group_sync(s, G, epoch)) return;
-        n = ld_agent(cnt);
-        Mover *t = cur; cur = nxt; nxt = t;
-    }
-    if (g == 0 && tid == 0) {
-        s.ctr[C_TAG] = (int)tag;
-        s.ctr[C_ROUNDS] = rounds;
-        s.ctr[C_PEND] = 0;
-        s.ctr[C_STEP] = step + 1;
+    switch (s.v) {
+        case 1: move_group<1>(s, g, G, step); break;
+        case 2: move_group<2>(s, g, G, step); break;
+        case 3: move_group<3>(s, g, G, step); break;
+        case 4: move_group<4>(s, g, G, step); break;
+        case 5: move_group<5>(s, g, G, step); break;
+        default: break;
     }
 }
 

@@ -276,7 +276,7 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     // carve one block: 256-byte aligned sub-buffers
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-    const size_t o_S = take(cells * 8), o_res = take(cells * 8), o_G = take(cells * 4),
+    const size_t o_S = take(cells * 8), o_res = take(cells * 16), o_G = take(cells * 4),
                  o_occ = take(cells * 4), o_type = take(cells), o_tm = take(tm * 4),
                  o_fb = take(ntiles), o_pos = take(n * 4), o_des = take(n * 4),
                  o_pend = take(n * 4), o_ka = take(n * sizeof(fk::Mover)),
@@ -294,7 +294,9 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     sd.seed_lo = (uint32_t)d->seed; sd.seed_hi = (uint32_t)(d->seed >> 32);
     sd.scn = d->scenario_id; sd.eps = b.eps; sd.k_s = d->k_s;
     sd.S = (const double *)(base + o_S);
-    sd.res = (unsigned long long *)(base + o_res);
+    sd.res0 = (unsigned long long *)(base + o_res);
+    sd.res1 = (unsigned long long *)(base + o_res + cells * 8);
+
     sd.G = (const float *)(base + o_G);
     sd.occ = (int32_t *)(base + o_occ);
     sd.type = (const uint8_t *)(base + o_type);
@@ -324,7 +326,7 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
         if (e == hipSuccess && bytes) e = hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice);
     };
     cp(o_S, b.S.data(), cells * 8);
-    if (e == hipSuccess) e = hipMemset(base + o_res, 0, cells * 8);
+    if (e == hipSuccess) e = hipMemset(base + o_res, 0, cells * 16);
     cp(o_G, b.G.data(), cells * 4);
     cp(o_occ, b.occ.data(), cells * 4);
     cp(o_type, b.type.data(), cells);
