@@ -43,17 +43,16 @@ def log(*a):
 
 
 def window_cells(cell_type: np.ndarray, xy: np.ndarray, v: int) -> int:
-    """Cells inside the reach disc of at least one agent (the planning
-    phase's algorithmic footprint)."""
+    """Cells of the grid inside the reach disc of at least one agent (the
+    planning phase's algorithmic footprint)."""
+    from scipy.ndimage import binary_dilation
+
     H, W = cell_type.shape
-    mask = np.zeros((H + 2 * v, W + 2 * v), dtype=bool)
-    occ = np.zeros_like(mask)
-    occ[xy[:, 1] + v, xy[:, 0] + v] = True
-    for dy in range(-v, v + 1):
-        for dx in range(-v, v + 1):
-            if dx * dx + dy * dy <= v * v:
-                mask |= np.roll(np.roll(occ, dy, 0), dx, 1)
-    return int(mask[v:v + H, v:v + W].sum())
+    occ = np.zeros((H, W), dtype=bool)
+    occ[xy[:, 1], xy[:, 0]] = True
+    yy, xx = np.mgrid[-v:v + 1, -v:v + 1]
+    disc = xx * xx + yy * yy <= v * v
+    return int(binary_dilation(occ, structure=disc).sum())
 
 
 def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4):
@@ -142,6 +141,47 @@ def bench_ensemble(ctx, torch, warmup: int, steps: int, plain_steps: int):
     }
 
 
+def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int):
+    """Planning kernel of many scenarios in one launch (fast_plan_batch), the
+    throughput regime: events around each launch, motion between them."""
+    t0 = time.perf_counter()
+    hs = [ctx.init_from(m) for m in scenarios]
+    init_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        ctx.plan_batch(hs)
+        ctx.move_batch(hs)
+    cells = 0
+    for m, h in zip(scenarios, hs):
+        st = ctx.state(h)
+        cells += window_cells(m.cell_type, st["xy"][st["alive"].astype(bool)], m.v)
+    planned0 = sum(ctx.stats(h)["planned"] for h in hs)
+    stream = ctx.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        ctx.plan_batch(hs)
+        ev[k][1].record(stream)
+        ctx.move_batch(hs)
+    torch.cuda.synchronize()
+    plan_ms = [a.elapsed_time(b) for a, b in ev]
+    planned = sum(ctx.stats(h)["planned"] for h in hs) - planned0
+    for h in hs:
+        ctx.destroy(h)
+    avg_ms = float(np.mean(plan_ms))
+    bytes_per_launch = 5.0 * cells + 12.0 * planned / steps
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    return {
+        "workload": name, "scenarios": len(scenarios), "agents": int(sum(m.n_agents for m in scenarios)),
+        "planning_agent_updates_per_s": planned / (sum(plan_ms) / 1e3),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "plan_kernel",
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_ms * 1e3},
+        "init_s": init_s,
+    }
+
+
 def cpu_baseline(budget_s: float = 15.0, max_steps: int = 396, v: int = 4):
     """The oracle as it stands: its OpenMP planning loop (paper Sec. 2
     schedule) on every host thread, sequential motion, on the room workload."""
@@ -179,6 +219,13 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=60)
     ap.add_argument("--plain-steps", type=int, default=4)
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--large-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes 5 times (the reference "
+                         "kernel for scaling the HBM traffic counters) and exit")
+    ap.add_argument("--room-replicas", type=int, default=0,
+                    help="also time the planning launch over this many copies of the room")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -193,6 +240,16 @@ def main():
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(1)
+    if args.copy_calibration:
+        n = args.copy_calibration * 1024 * 1024
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {n} bytes 5 times")
+        return
     ctx = fast.Context(device=0)
     log(f"room: warmup {args.warmup}, timed {args.steps} steps")
     r = bench_room(ctx, torch, args.warmup, args.steps)
@@ -203,6 +260,23 @@ def main():
     achieved = bytes_per_launch / (avg_plan_ms / 1e3) / 1e9
     log(f"room: planning {value:.4g} agent-updates/s, plan {avg_plan_ms * 1e3:.2f} us/step, "
         f"whole step {r['total_ms'] / args.steps * 1e3:.1f} us, stats {r['stats']}")
+
+    large = None
+    if not args.no_large:
+        from paper_0911_2900_amd import scenarios as sc
+        log("large: 16 x 1000x1000, 200,000 agents each ...")
+        large = bench_batch_plan(ctx, torch, sc.large(16),
+                                 "16 scenarios of 1000x1000 cells, 10 % pillars, 4 exits, "
+                                 "200,000 agents each, v_m=4, one planning launch", 2,
+                                 args.large_steps)
+        log(f"large: {large}")
+    replicas = None
+    if args.room_replicas:
+        from paper_0911_2900_amd import scenarios as sc
+        rooms = [sc.room(v=4, scn=k) for k in range(args.room_replicas)]
+        replicas = bench_batch_plan(ctx, torch, rooms, f"{args.room_replicas} x room 400x400, "
+                                    "40,000 agents, v_m=4, one planning launch", 2, args.large_steps)
+        log(f"replicas: {replicas}")
 
     ens = None
     if not args.no_ensemble:
@@ -245,6 +319,8 @@ def main():
             "avg_launch_us": avg_plan_ms * 1e3,
         },
         "ensemble": ens,
+        "large": large,
+        "room_replicas": replicas,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in
                                                  ("value", "unit", "cores", "kind", "sample")},
     }

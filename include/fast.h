@@ -156,6 +156,14 @@ fast_status fast_move_step(fast_ctx *ctx, int32_t handle);
  * scenario keeps its own step counter.  n >= 1, steps >= 0. */
 fast_status fast_run(fast_ctx *ctx, const int32_t *handles, int32_t n, int32_t steps);
 
+/* One planning phase of each of the n scenarios in a single launch over all
+ * their tiles (the batched form of fast_plan_step). */
+fast_status fast_plan_batch(fast_ctx *ctx, const int32_t *handles, int32_t n);
+
+/* One motion phase of each of the n scenarios in a single launch (the batched
+ * form of fast_move_step); each must have been planned for this step. */
+fast_status fast_move_batch(fast_ctx *ctx, const int32_t *handles, int32_t n);
+
 /* Copies the state back (synchronises the stream).  Any pointer may be NULL.
  * xy: 2*n_agents (x, y), (-1, -1) for agents that left; alive: n_agents;
  * desired: n_agents cells y*width + x of the last plan (-1 when gone). */

@@ -190,7 +190,9 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
     // padded layout
     b.ntx = (W + tx - 1) / tx;
     b.nty = (H + ty - 1) / ty;
-    b.Wp = b.ntx * tx + 2 * v;
+    // rows padded to a multiple of 32 cells, with room for the planning
+    // kernel's 4-cell vector loads past the last tile's window
+    b.Wp = (b.ntx * tx + 2 * v + 3 + 31) / 32 * 32;
     b.Hp = b.nty * ty + 2 * v;
     const int64_t np = (int64_t)b.Wp * b.Hp;
     b.type.assign((size_t)np, fk::CELL_WALL);

@@ -4,15 +4,19 @@
 // Layout of one scenario (a "slot") in HBM.  The grid is padded by v cells of
 // wall on every side and rounded up to whole planning tiles, so that a tile's
 // (tx + 2v) x (ty + 2v) window never needs a bounds check:
-//   padded width  Wp = ntx * tx + 2v,  padded height Hp = nty * ty + 2v,
+//   padded width  Wp = ntx * tx + 2v rounded up past 4-cell vector reads to a
+//   multiple of 32 cells,  padded height Hp = nty * ty + 2v,
 //   cell (x, y) of the scenario lives at index (y + v) * Wp + (x + v).
 // Per cell:  type u8 (static), G f32 (static exp table, see below),
 //            S f64 (static floor field, read only by the FP64 re-resolve),
 //            occ i32 (agent id or -1), res0/res1 u64 (motion reservations of
 //            even / odd rounds).
-// Per agent: pos i32 (padded cell, -1 once gone), desired i32, a pending id
-//            and two reservation-key lists for the motion rounds.
-// Per tile:  m i32 (power-of-two scale of the exp table), fallback u8.
+// Per tile:  m i32 (power-of-two scale of the exp table), fallback u8, and the
+//            movers planned on the tile: a count and up to tx*ty records
+//            (id, start, target) written by the planning kernel, read by the
+//            motion kernel; the motion rounds keep two mover lists of the same
+//            size.  Positions live only in occ (the host rebuilds per-agent
+//            arrays from occ and the records when asked).
 //
 // Exp table: G(t) = fl32(exp(m_T(t) ln 2 - k_S S(t))) where T(t) is the tile
 // holding t.  A tile T staging a halo cell t of tile T' rescales it by
@@ -32,7 +36,7 @@ enum : int { CELL_FREE = 0, CELL_WALL = 1, CELL_EXIT = 2 };
 
 constexpr int MAX_V = 5;
 constexpr int MAX_TILE_CELLS = 1024;   // tx * ty
-constexpr int MAX_STAGE = 2048;        // (tx + 2v)(ty + 2v) over the allowed tiles
+constexpr int MAX_STAGE = 2112;        // round4(tx + 2v) * (ty + 2v) over the allowed tiles
 constexpr int PLAN_THREADS = 256;
 constexpr int MOVE_THREADS = 1024;
 constexpr int MOVE_GROUP_MAX = 64;        // workgroups per scenario in the motion phase
@@ -51,7 +55,6 @@ enum : int {
     C_STEP = 0,      // steps completed
     C_NACTIVE = 1,   // agents still present
     C_EXITED = 2,    // agents that left
-    C_PEND = 3,      // movers appended by the last plan
     C_TAG = 4,       // last reservation tag used
     C_ROUNDS = 5,    // reservation rounds of the last motion phase
     C_LIMIT = 6,     // kernels act while step < limit
@@ -66,6 +69,11 @@ enum : int {
 struct Mover {
     unsigned long long key;
     uint32_t cxy, dxy;
+};
+
+// A mover as planned: agent id and packed start / target cells.
+struct MoveRec {
+    uint32_t id, cxy, dxy;
 };
 // uint64 statistics per slot
 enum : int { S_FLAGGED = 0, S_FALLBACK = 1, S_PLANNED = 2, S_NSTAT = 4 };
@@ -88,10 +96,9 @@ struct SlotDev {
     int32_t *occ;            // Wp*Hp
     unsigned long long *res0;// Wp*Hp, reservations of even rounds
     unsigned long long *res1;// Wp*Hp, reservations of odd rounds
-    int32_t *pos;            // n_agents
-    int32_t *desired;        // n_agents
-    int32_t *pend;           // n_agents
-    Mover *mv_a, *mv_b;      // n_agents each: movers of the current / next round
+    int32_t *seg_cnt;        // ntx*nty: movers planned per tile
+    MoveRec *seg;            // ntx*nty*tx*ty: their records, tile by tile
+    Mover *mv_a, *mv_b;      // ntx*nty*tx*ty each: movers of the current / next round
     int32_t *ctr;            // C_NCTR
     unsigned long long *stat;// S_NSTAT
     float *dbg_w;            // optional debug outputs (null in normal runs)

@@ -41,5 +41,3 @@ extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *i
 extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,
                                      hipStream_t stream);
 extern "C" hipError_t fk_move_capacity(int *blocks);
-extern "C" hipError_t fk_launch_reset(const fk::SlotDev *table, const int32_t *slots, int n_slots,
-                                      hipStream_t stream);

@@ -7,7 +7,8 @@
 //                 by scanning the tile's occupancy; one lane per agent forms
 //                 the weights, the CDF over the reach disc, and the Philox
 //                 draw in FP32; draws inside the guard band are re-resolved
-//                 in FP64 by a whole wavefront.
+//                 in FP64 by a whole wavefront.  The tile's movers are written
+//                 as (id, start, target) records to the tile's own segment.
 //   move_kernel   the motion phase with the model's sequential semantics
 //                 (Sec. 1), run as deterministic reservations: one workgroup
 //                 per scenario; every round each pending agent reserves its
@@ -17,8 +18,6 @@
 //                 only moves once every earlier agent sharing a cell with it
 //                 has moved, so the result equals moving them one by one in
 //                 priority order.
-//   reset_kernel  clears the per-step mover count (used when a plan is
-//                 issued again without a motion phase in between).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,11 +63,14 @@ __device__ __forceinline__ float row_sum(const float *Em, int l, int LX, float e
     return Tree<2 * a + 1, 0>::sum(x);
 }
 
+// Row sums one row at a time: the scheduling barrier keeps the loads of a row
+// from being hoisted above the previous row's sum, which bounds the live
+// registers to one row's values (occupancy hides the LDS latency instead).
 template <int V, int... R>
 __device__ __forceinline__ void all_rows(std::integer_sequence<int, R...>, float *Rs,
                                          const float *Em, int l, int LX, float ec)
 {
-    ((Rs[R] = row_sum<V, R>(Em, l, LX, ec)), ...);
+    ((Rs[R] = row_sum<V, R>(Em, l, LX, ec), __builtin_amdgcn_sched_barrier(0)), ...);
 }
 
 // ---------------------------------------------------------------------------
@@ -85,13 +87,17 @@ __device__ __forceinline__ bool reach_ok(const SlotDev &s, int gc, int t, int dx
     return o < 0 || t == gc;
 }
 
+// (The loops stay rolled: this path is rare, and unrolled FP64 exp code would
+// raise the register count of the whole planning kernel.)
 template <int V, bool DEBUG>
 __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
 {
     const double Sc = s.S[gc];
     const double ks = s.k_s;
     double C = 0.0;
+#pragma unroll 1
     for (int dy = -V; dy <= V; ++dy)
+#pragma unroll 1
         for (int dx = -V; dx <= V; ++dx) {
             const int t = gc + dy * s.Wp + dx;
             if (reach_ok<V>(s, gc, t, dx, dy)) {
@@ -104,7 +110,9 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
         }
     const double tau = (double)u32 * C;
     double C2 = 0.0;
+#pragma unroll 1
     for (int dy = -V; dy <= V; ++dy)
+#pragma unroll 1
         for (int dx = -V; dx <= V; ++dx) {
             const int t = gc + dy * s.Wp + dx;
             if (reach_ok<V>(s, gc, t, dx, dy)) {
@@ -119,7 +127,7 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
 // j + 64; the prefix sum is still taken sequentially, slot by slot, in raster
 // order, so the result is bit-identical to resolve64_lane.
 template <int V>
-__device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane)
+__device__ __forceinline__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane)
 {
     constexpr int SIDE = 2 * V + 1;
     constexpr int NS = SIDE * SIDE;           // <= 121
@@ -159,33 +167,37 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane)
 // Planning kernel.
 // ---------------------------------------------------------------------------
 struct PlanShared {
-    float Em[MAX_STAGE];                // masked exp table window
-    int32_t a_id[MAX_TILE_CELLS];       // agents found on the tile
-    int32_t a_g[MAX_TILE_CELLS];        // their padded cell
-    int16_t a_l[MAX_TILE_CELLS];        // their LDS cell
+    alignas(16) float Em[MAX_STAGE];    // masked exp table window, pitch P = round4(tx + 2v)
+    int32_t a_pk[MAX_TILE_CELLS];       // agents of the tile: id << 12 | LDS cell
     float a_ec[MAX_TILE_CELLS];         // e_c of their own cell
-    int16_t f_k[MAX_TILE_CELLS];        // flagged agents (index into a_*)
-    float f_u[MAX_TILE_CELLS];
+    uint32_t flags[MAX_TILE_CELLS / 32];// draws to re-resolve in FP64
     int32_t m_nb[9];
-    int n_agents, n_flag;
+    int n_agents, n_flag, n_mov;
 };
 
-// Appends movers (target != own cell) to the slot's pending list with one
+// Appends movers (target != own cell) to the tile's record segment, one LDS
 // atomic per wavefront.
-__device__ __forceinline__ void append_movers(const SlotDev &s, bool mover, int id)
+__device__ __forceinline__ void emit_movers(MoveRec *seg, PlanShared &sh, bool mover, MoveRec rec)
 {
     const unsigned long long mask = __ballot(mover);
     if (mask == 0) return;
     const int lane = __lane_id();
     const int leader = __builtin_ctzll(mask);
     int base = 0;
-    if (lane == leader) base = atomicAdd(&s.ctr[C_PEND], __popcll(mask));
+    if (lane == leader) base = atomicAdd(&sh.n_mov, __popcll(mask));
     base = __shfl(base, leader);
-    if (mover) {
-        const unsigned long long below = mask & ((1ull << lane) - 1ull);
-        s.pend[base + __popcll(below)] = id;
-    }
+    if (mover) seg[base + __popcll(mask & ((1ull << lane) - 1ull))] = rec;
 }
+
+__device__ __forceinline__ uint32_t pack_xy(int x, int y) { return (uint32_t)x | ((uint32_t)y << 16); }
+
+__device__ __forceinline__ int lanes_below(unsigned long long mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+constexpr int STAGE_ITERS = (MAX_STAGE / 4 + PLAN_THREADS - 1) / PLAN_THREADS;   // 3
 
 template <int V, bool DEBUG>
 __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, PlanShared &sh)
@@ -193,62 +205,116 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
     constexpr int SIDE = 2 * V + 1;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
+    const int lane = __lane_id();
     const int LX = s.tx + 2 * V, LY = s.ty + 2 * V;
-    const int ns = LX * LY;
-    const int gx0 = tile_x * s.tx, gy0 = tile_y * s.ty;     // padded origin of the window
+    const int P = (LX + 3) & ~3;                              // LDS pitch and load width
+    const int cpr = P >> 2;                                   // 4-cell chunks per row
+    const int nchunk = cpr * LY;
+    const int gx0 = tile_x * s.tx, gy0 = tile_y * s.ty;       // padded origin of the window
     const int tstride = s.ntx + 2;
     const bool fallback = s.tile_fb[tile_y * s.ntx + tile_x] != 0;
 
     if (tid < 9) sh.m_nb[tid] = s.tile_m[(tile_y + tid / 3) * tstride + tile_x + tid % 3];
-    if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; }
-    __syncthreads();
-    const int mT = sh.m_nb[4];
+    if (tid < MAX_TILE_CELLS / 32) sh.flags[tid] = 0u;
+    if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; sh.n_mov = 0; }
+    const int tile = tile_y * s.ntx + tile_x;
+    MoveRec *seg = s.seg + (long)tile * (s.tx * s.ty);
 
-    // --- stage the window: Em = 2^(m_T - m_T') G where free, 0 where occupied
-    const float invLX = 1.0f / (float)LX;
-    for (int i = tid; i < ns; i += nthr) {
-        const int ly = (int)(((float)i + 0.5f) * invLX);
-        const int lx = i - ly * LX;
-        const int g = (gy0 + ly) * s.Wp + gx0 + lx;
-        const int o = s.occ[g];
-        const float G = s.G[g];
-        const int nbx = (lx >= V) + (lx >= V + s.tx);
+    // --- stage the window.  All of a thread's 16-byte loads are issued first.
+    int4 o4[STAGE_ITERS];
+    float4 g4[STAGE_ITERS];
+    const float inv_cpr = 1.0f / (float)cpr;
+#pragma unroll
+    for (int j = 0; j < STAGE_ITERS; ++j) {
+        const int ch = tid + j * nthr;
+        o4[j] = make_int4(-1, -1, -1, -1);
+        g4[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ch < nchunk) {
+            const int ly = (int)(((float)ch + 0.5f) * inv_cpr);
+            const int lx = (ch - ly * cpr) * 4;
+            const int g = (gy0 + ly) * s.Wp + gx0 + lx;
+            o4[j] = *(const int4 *)(s.occ + g);
+            g4[j] = *(const float4 *)(s.G + g);
+        }
+    }
+    __syncthreads();                                          // m_nb, counters ready
+    const int mT = sh.m_nb[4];
+#pragma unroll
+    for (int j = 0; j < STAGE_ITERS; ++j) {
+        const int ch = tid + j * nthr;
+        const bool live = ch < nchunk;
+        const int ly = (int)(((float)ch + 0.5f) * inv_cpr);
+        const int lx0 = (ch - ly * cpr) * 4;
         const int nby = (ly >= V) + (ly >= V + s.ty);
-        const float e = ldexpf(G, mT - sh.m_nb[nby * 3 + nbx]);
-        sh.Em[i] = o < 0 ? e : 0.0f;
-        if (nbx == 1 && nby == 1 && o >= 0) {
-            const int k = atomicAdd(&sh.n_agents, 1);
-            sh.a_id[k] = o;
-            sh.a_g[k] = g;
-            sh.a_l[k] = (int16_t)i;
-            sh.a_ec[k] = e;
+        const int ov[4] = {o4[j].x, o4[j].y, o4[j].z, o4[j].w};
+        const float gv[4] = {g4[j].x, g4[j].y, g4[j].z, g4[j].w};
+        float e[4];
+        bool ag[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int lx = lx0 + k;
+            const int nbx = (lx >= V) + (lx >= V + s.tx);
+            e[k] = ldexpf(gv[k], mT - sh.m_nb[nby * 3 + nbx]);
+            ag[k] = live && nbx == 1 && nby == 1 && ov[k] >= 0;
+        }
+        if (live)
+            *(float4 *)&sh.Em[ly * P + lx0] = make_float4(ov[0] < 0 ? e[0] : 0.f, ov[1] < 0 ? e[1] : 0.f,
+                                                          ov[2] < 0 ? e[2] : 0.f, ov[3] < 0 ? e[3] : 0.f);
+        // compact the agents found: one LDS atomic per wavefront
+        unsigned long long m[4];
+        int tot = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { m[k] = __ballot(ag[k]); tot += __popcll(m[k]); }
+        if (tot) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&sh.n_agents, tot);
+            base = __shfl(base, 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (ag[k]) {
+                    const int slot = base + lanes_below(m[k]);
+                    sh.a_pk[slot] = (ov[k] << 12) | (ly * P + lx0 + k);
+                    sh.a_ec[slot] = e[k];
+                }
+                base += __popcll(m[k]);
+            }
         }
     }
     __syncthreads();
     const int na = sh.n_agents;
     const uint32_t kseed0 = s.seed_lo, kseed1 = s.seed_hi;
-    if (tid == 0 && na > 0) atomicAdd(&s.stat[S_PLANNED], (unsigned long long)na);
+    const float inv_P = 1.0f / (float)P;
 
     if (fallback) {
         // every draw of this tile in FP64, one lane per agent
-        for (int k = tid; k < na; k += nthr) {
-            const int id = sh.a_id[k], gc = sh.a_g[k];
-            const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
-                                             kseed0, kseed1);
-            const float u = (float)(x0 >> 8) * 0x1p-24f;
-            const int t = resolve64_lane<V, DEBUG>(s, gc, id, u);
-            s.desired[id] = t;
-            if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
-            if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
-        }
         for (int base = 0; base < na; base += nthr) {
             const int k = base + tid;
             bool mover = false;
-            int id = 0;
-            if (k < na) { id = sh.a_id[k]; mover = s.desired[id] != sh.a_g[k]; }
-            append_movers(s, mover, id);
+            MoveRec rec{};
+            if (k < na) {
+                const int id = sh.a_pk[k] >> 12;
+                const int l = sh.a_pk[k] & 0xFFF;
+                const int ly = (int)(((float)l + 0.5f) * inv_P);
+                const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
+                const int gc = cy * s.Wp + cx;
+                const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
+                                                 kseed0, kseed1);
+                const float u = (float)(x0 >> 8) * 0x1p-24f;
+                const int t = resolve64_lane<V, DEBUG>(s, gc, id, u);
+                mover = t != gc;
+                const int d = t - gc;                       // |dx|, |dy| <= V < Wp / 2
+                const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
+                rec = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
+                if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
+            }
+            emit_movers(seg, sh, mover, rec);
         }
-        if (tid == 0 && na > 0) atomicAdd(&s.stat[S_FALLBACK], (unsigned long long)na);
+        __syncthreads();
+        if (tid == 0) {
+            s.seg_cnt[tile] = sh.n_mov;
+            if (na > 0) atomicAdd(&s.stat[S_FALLBACK], (unsigned long long)na);
+        }
         return;
     }
 
@@ -256,38 +322,39 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
     for (int base = 0; base < na; base += nthr) {
         const int k = base + tid;
         bool mover = false;
-        int id = 0;
+        MoveRec rec{};
         if (k < na) {
-            id = sh.a_id[k];
-            const int gc = sh.a_g[k];
-            const int l = sh.a_l[k];
+            const int id = sh.a_pk[k] >> 12;
+            const int l = sh.a_pk[k] & 0xFFF;
             const float ec = sh.a_ec[k];
+            const int ly = (int)(((float)l + 0.5f) * inv_P);
+            const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
 
             float Rs[SIDE];
-            all_rows<V>(std::make_integer_sequence<int, SIDE>{}, Rs, sh.Em, l, LX, ec);
-            float P[SIDE + 1];
-            P[0] = 0.0f;
+            all_rows<V>(std::make_integer_sequence<int, SIDE>{}, Rs, sh.Em, l, P, ec);
+            float Pr[SIDE + 1];
+            Pr[0] = 0.0f;
 #pragma unroll
-            for (int r = 0; r < SIDE; ++r) P[r + 1] = P[r] + Rs[r];
-            const float Wsum = P[SIDE];
+            for (int r = 0; r < SIDE; ++r) Pr[r + 1] = Pr[r] + Rs[r];
+            const float Wsum = Pr[SIDE];
 
             const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
                                              kseed0, kseed1);
             const float u = (float)(x0 >> 8) * 0x1p-24f;
             const float tau = u * Wsum;
 
-            // row: the last r with P_r <= tau
+            // row: the last r with Pr_r <= tau
             int rs = 0, as = half_width(V, -V);
             float Ps = 0.0f;
 #pragma unroll
             for (int r = 1; r < SIDE; ++r) {
-                const bool le = P[r] <= tau;
+                const bool le = Pr[r] <= tau;
                 rs = le ? r : rs;
-                Ps = le ? P[r] : Ps;
+                Ps = le ? Pr[r] : Ps;
                 as = le ? half_width(V, r - V) : as;
             }
             // slot within the row: count of in-row boundaries <= tau
-            const int rowbase = l + (rs - V) * LX - as;
+            const int rowbase = l + (rs - V) * P - as;
             float Q = 0.0f;
             float margin = fabsf(tau - Ps);
             int ks = 0;
@@ -303,7 +370,6 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
                 }
             }
             const bool flag = (margin <= s.eps * Wsum) || (ks > 2 * as);
-            const int tgt = gc + (rs - V) * s.Wp + (ks - as);
 
             if (DEBUG) {
                 if (s.dbg_w) {
@@ -312,7 +378,7 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
                         for (int dx = -V; dx <= V; ++dx) {
                             float wv = 0.0f;
                             if (dx * dx + dy * dy <= V * V)
-                                wv = (dx == 0 && dy == 0) ? 1.0f : sh.Em[l + dy * LX + dx] / ec;
+                                wv = (dx == 0 && dy == 0) ? 1.0f : sh.Em[l + dy * P + dx] / ec;
                             wd[(dy + V) * SIDE + dx + V] = wv;
                         }
                 }
@@ -320,36 +386,48 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
                 if (s.dbg_margin) s.dbg_margin[id] = margin / Wsum;
             }
             if (flag) {
-                const int f = atomicAdd(&sh.n_flag, 1);
-                sh.f_k[f] = (int16_t)k;
-                sh.f_u[f] = u;
+                atomicOr(&sh.flags[k >> 5], 1u << (k & 31));
+                atomicAdd(&sh.n_flag, 1);
             } else {
-                s.desired[id] = tgt;
-                mover = tgt != gc;
+                const int ddx = ks - as, ddy = rs - V;
+                mover = ddx != 0 || ddy != 0;
+                rec = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
             }
         }
-        append_movers(s, mover, id);
+        emit_movers(seg, sh, mover, rec);
     }
     __syncthreads();
 
     // --- FP64 re-resolve of the flagged draws, one wavefront per draw
     const int nf = sh.n_flag;
-    if (nf == 0) return;
-    const int lane = __lane_id();
     const int wave = tid >> 6, nwaves = nthr >> 6;
-    for (int f = wave; f < nf; f += nwaves) {
-        const int k = sh.f_k[f];
-        const int id = sh.a_id[k], gc = sh.a_g[k];
-        const int t = resolve64_wave<V>(s, gc, sh.f_u[f], lane);
-        if (lane == 0) {
-            s.desired[id] = t;
-            if (t != gc) {
-                const int p = atomicAdd(&s.ctr[C_PEND], 1);
-                s.pend[p] = id;
+    for (int w = wave; w < (na + 31) / 32; w += nwaves) {
+        uint32_t bits = sh.flags[w];
+        while (bits) {
+            const int k = w * 32 + __builtin_ctz(bits);
+            bits &= bits - 1u;
+            const int id = sh.a_pk[k] >> 12;
+            const int l = sh.a_pk[k] & 0xFFF;
+            const int ly = (int)(((float)l + 0.5f) * inv_P);
+            const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
+            const int gc = cy * s.Wp + cx;
+            const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
+                                             kseed0, kseed1);
+            const float u = (float)(x0 >> 8) * 0x1p-24f;
+            const int t = resolve64_wave<V>(s, gc, u, lane);
+            if (lane == 0 && t != gc) {
+                const int d = t - gc;
+                const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
+                seg[atomicAdd(&sh.n_mov, 1)] =
+                    MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
             }
         }
     }
-    if (tid == 0) atomicAdd(&s.stat[S_FLAGGED], (unsigned long long)nf);
+    __syncthreads();
+    if (tid == 0) {
+        s.seg_cnt[tile] = sh.n_mov;
+        if (nf) atomicAdd(&s.stat[S_FLAGGED], (unsigned long long)nf);
+    }
 }
 
 // items[i] = (slot << 20) | tile index (row-major over the slot's tiles)
@@ -538,14 +616,11 @@ __device__ int commit_list(const SlotDev &s, const unsigned long long *res, cons
         }
         if (gone) {
             st_agent(&s.occ[c], -1);
-            s.pos[id] = -1;
-            s.desired[id] = -1;
             atomicAdd(&s.ctr[C_EXITED], 1);
             atomicSub(&s.ctr[C_NACTIVE], 1);
         } else if (at != c) {
             st_agent(&s.occ[c], -1);
             st_agent(&s.occ[at], id);
-            s.pos[id] = at;
         }
     }
     __syncthreads();
@@ -555,31 +630,51 @@ __device__ int commit_list(const SlotDev &s, const unsigned long long *res, cons
 template <int V>
 __device__ void move_group(const SlotDev &s, int g, int G, int step)
 {
+    __shared__ int sh_scan[MOVE_THREADS];
     const int tid = threadIdx.x;
-    const int Wp = s.Wp;
-    const int n0 = s.ctr[C_PEND];
-    const int lo = (int)((long)n0 * g / G), hi = (int)((long)n0 * (g + 1) / G);
-    Mover *cur = s.mv_a + lo, *nxt = s.mv_b + lo;
+    const int T = s.ntx * s.nty, TC = s.tx * s.ty;
+    const int t_lo = (int)((long)T * g / G), t_hi = (int)((long)T * (g + 1) / G);
+    Mover *cur = s.mv_a + (long)t_lo * TC, *nxt = s.mv_b + (long)t_lo * TC;
     unsigned long long seen0 = 0, seen1 = 0;
     uint32_t tag = (uint32_t)s.ctr[C_TAG];
+    if (g == 0 && tid == 0)   // agents planned this step, for the throughput counters
+        atomicAdd(&s.stat[S_PLANNED], (unsigned long long)s.ctr[C_NACTIVE]);
 
-    // this workgroup's movers with priority words [~x0:32][~id:20] (larger = earlier)
-    int n = hi - lo;
-    for (int i = tid; i < n; i += blockDim.x) {
-        const int id = s.pend[lo + i];
-        const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_ORDER,
-                                         s.seed_lo, s.seed_hi);
-        const int c = s.pos[id], d = s.desired[id];
-        const int cy = c / Wp, dy = d / Wp;
-        Mover mv;
-        mv.key = ((unsigned long long)(~x0) << ID_BITS) | (unsigned long long)(~(uint32_t)id & ID_MASK);
-        mv.cxy = (uint32_t)(c - cy * Wp) | ((uint32_t)cy << 16);
-        mv.dxy = (uint32_t)(d - dy * Wp) | ((uint32_t)dy << 16);
-        cur[i] = mv;
+    // gather this workgroup's movers (the records of tiles [t_lo, t_hi)) with
+    // their priority words [~x0:32][~id:20] (larger = earlier)
+    int n = 0;
+    for (int tc = t_lo; tc < t_hi; tc += MOVE_THREADS) {
+        const int nt = min(MOVE_THREADS, t_hi - tc);
+        sh_scan[tid] = tid < nt ? s.seg_cnt[tc + tid] : 0;
+        __syncthreads();
+        for (int off = 1; off < MOVE_THREADS; off <<= 1) {
+            const int add = tid >= off ? sh_scan[tid - off] : 0;
+            __syncthreads();
+            sh_scan[tid] += add;
+            __syncthreads();
+        }
+        const int chunk = sh_scan[MOVE_THREADS - 1];
+        for (int i = tid; i < chunk; i += blockDim.x) {
+            int a = 0, b = nt - 1;                   // first tile whose inclusive count exceeds i
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (sh_scan[mid] > i) b = mid; else a = mid + 1;
+            }
+            const int k = i - (a ? sh_scan[a - 1] : 0);
+            const MoveRec rec = s.seg[(long)(tc + a) * TC + k];
+            const uint32_t x0 = philox_word0(rec.id, (uint32_t)step, s.scn, STREAM_ORDER,
+                                             s.seed_lo, s.seed_hi);
+            Mover mv;
+            mv.key = ((unsigned long long)(~x0) << ID_BITS) | (unsigned long long)(~rec.id & ID_MASK);
+            mv.cxy = rec.cxy;
+            mv.dxy = rec.dxy;
+            cur[n + i] = mv;
+        }
+        n += chunk;
+        __syncthreads();
     }
-    __syncthreads();
 
-    int total = n0, rounds = 0, bar_r = 0;
+    int total = 1, rounds = 0, bar_r = 0;          // round 0's total comes from its barrier
     for (int r = 0; total > 0; ++r) {
         unsigned long long *res = (r & 1) ? s.res1 : s.res0;
         if (r > 0) {
@@ -609,7 +704,6 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
     if (g == 0 && tid == 0) {
         s.ctr[C_TAG] = (int)tag;
         s.ctr[C_ROUNDS] = rounds;
-        s.ctr[C_PEND] = 0;
         s.ctr[C_STEP] = step + 1;
     }
 }
@@ -633,13 +727,6 @@ __global__ __launch_bounds__(MOVE_THREADS) void move_kernel(const SlotDev *__res
         case 5: move_group<5>(s, g, G, step); break;
         default: break;
     }
-}
-
-__global__ void reset_kernel(const SlotDev *__restrict__ table, const int32_t *__restrict__ slots,
-                             int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) table[slots[i]].ctr[C_PEND] = 0;
 }
 
 }  // namespace fk
@@ -684,11 +771,3 @@ extern "C" hipError_t fk_move_capacity(int *blocks)
     return hipSuccess;
 }
 
-extern "C" hipError_t fk_launch_reset(const fk::SlotDev *table, const int32_t *slots, int n_slots,
-                                      hipStream_t stream)
-{
-    if (n_slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fk::reset_kernel, dim3((n_slots + 255) / 256), dim3(256), 0, stream, table,
-                       slots, n_slots);
-    return hipGetLastError();
-}

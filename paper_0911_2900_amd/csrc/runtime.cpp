@@ -69,7 +69,8 @@ struct Batch {
     hipGraph_t graph = nullptr;
     uint32_t *items = nullptr;
     uint32_t *mitems = nullptr;
-    int n_mitems = 0;
+    int32_t *slots = nullptr;
+    int n_items = 0, n_mitems = 0, n_slots = 0;
     void *block = nullptr;
     size_t bytes = 0;
     std::vector<int32_t> members;
@@ -270,17 +271,17 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     }
 
     const size_t cells = (size_t)b.Wp * b.Hp;
-    const size_t n = (size_t)std::max(b.n, 1);
     const size_t ntiles = (size_t)b.ntx * b.nty;
+    const size_t tcells = ntiles * (size_t)b.tx * b.ty;   // record / mover capacity
     const size_t tm = (size_t)(b.ntx + 2) * (b.nty + 2);
     // carve one block: 256-byte aligned sub-buffers
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
     const size_t o_S = take(cells * 8), o_res = take(cells * 16), o_G = take(cells * 4),
                  o_occ = take(cells * 4), o_type = take(cells), o_tm = take(tm * 4),
-                 o_fb = take(ntiles), o_pos = take(n * 4), o_des = take(n * 4),
-                 o_pend = take(n * 4), o_ka = take(n * sizeof(fk::Mover)),
-                 o_kb = take(n * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
+                 o_fb = take(ntiles), o_scnt = take(ntiles * 4),
+                 o_seg = take(tcells * sizeof(fk::MoveRec)), o_ka = take(tcells * sizeof(fk::Mover)),
+                 o_kb = take(tcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
                  o_mitems = take(fk::MOVE_GROUP_MAX * 4);
     void *block = nullptr;
@@ -302,9 +303,8 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     sd.type = (const uint8_t *)(base + o_type);
     sd.tile_m = (const int32_t *)(base + o_tm);
     sd.tile_fb = (const uint8_t *)(base + o_fb);
-    sd.pos = (int32_t *)(base + o_pos);
-    sd.desired = (int32_t *)(base + o_des);
-    sd.pend = (int32_t *)(base + o_pend);
+    sd.seg_cnt = (int32_t *)(base + o_scnt);
+    sd.seg = (fk::MoveRec *)(base + o_seg);
     sd.mv_a = (fk::Mover *)(base + o_ka);
     sd.mv_b = (fk::Mover *)(base + o_kb);
     sd.ctr = (int32_t *)(base + o_ctr);
@@ -332,8 +332,7 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     cp(o_type, b.type.data(), cells);
     cp(o_tm, b.tile_m.data(), tm * 4);
     cp(o_fb, b.tile_fb.data(), ntiles);
-    cp(o_pos, b.pos.data(), (size_t)b.n * 4);
-    cp(o_des, b.pos.data(), (size_t)b.n * 4);          // desired = own cell until planned
+    if (e == hipSuccess) e = hipMemset(base + o_scnt, 0, ntiles * 4);   // no movers planned yet
     cp(o_ctr, ctr.data(), fk::C_NCTR * 4);
     if (e == hipSuccess) e = hipMemset(base + o_stat, 0, fk::S_NSTAT * 8);
     cp(o_items, items.data(), ntiles * 4);
@@ -373,20 +372,41 @@ fast_status destroy_slot(fast_ctx *c, int32_t h)
     return FAST_OK;
 }
 
+// Per-agent state rebuilt from the occupancy grid (positions) and the tiles'
+// mover records of the last plan (targets; agents without one stay put).
 fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_t *desired,
                        int32_t *step, int32_t *n_active)
 {
     HIP_TRY(hipStreamSynchronize(c->stream));
+    const fk::SlotDev &d = s->dev;
     const int n = s->n_agents;
-    std::vector<int32_t> pos((size_t)std::max(n, 1)), des((size_t)std::max(n, 1)), ctr(fk::C_NCTR);
-    HIP_TRY(hipMemcpy(ctr.data(), s->dev.ctr, fk::C_NCTR * 4, hipMemcpyDeviceToHost));
+    std::vector<int32_t> ctr(fk::C_NCTR);
+    HIP_TRY(hipMemcpy(ctr.data(), d.ctr, fk::C_NCTR * 4, hipMemcpyDeviceToHost));
     if (ctr[fk::C_ERR])
         return fail(FAST_E_DEVICE, "a motion-phase group barrier timed out: the scenario state is invalid");
-    if (n) {
-        HIP_TRY(hipMemcpy(pos.data(), s->dev.pos, (size_t)n * 4, hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(des.data(), s->dev.desired, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (step) *step = ctr[fk::C_STEP];
+    if (n_active) *n_active = ctr[fk::C_NACTIVE];
+    if (!xy && !alive && !desired) return FAST_OK;
+    const size_t cells = (size_t)d.Wp * d.Hp;
+    std::vector<int32_t> occ(cells), pos((size_t)std::max(n, 1), -1);
+    HIP_TRY(hipMemcpy(occ.data(), d.occ, cells * 4, hipMemcpyDeviceToHost));
+    for (size_t g = 0; g < cells; ++g)
+        if (occ[g] >= 0 && occ[g] < n) pos[occ[g]] = (int32_t)g;
+    const int Wp = d.Wp, v = d.v, W = d.W;
+    std::vector<int32_t> tgt;
+    if (desired) {
+        const size_t ntiles = (size_t)d.ntx * d.nty, tc = (size_t)d.tx * d.ty;
+        std::vector<int32_t> cnt(ntiles);
+        std::vector<fk::MoveRec> rec(ntiles * tc);
+        HIP_TRY(hipMemcpy(cnt.data(), d.seg_cnt, ntiles * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(rec.data(), d.seg, rec.size() * sizeof(fk::MoveRec), hipMemcpyDeviceToHost));
+        tgt = pos;                                          // no record: the agent stays
+        for (size_t t = 0; t < ntiles; ++t)
+            for (int k = 0; k < cnt[t]; ++k) {
+                const fk::MoveRec &r = rec[t * tc + k];
+                if ((int)r.id < n) tgt[r.id] = (int32_t)((r.dxy >> 16) * Wp + (r.dxy & 0xFFFFu));
+            }
     }
-    const int Wp = s->dev.Wp, v = s->dev.v, W = s->dev.W;
     for (int i = 0; i < n; ++i) {
         const int p = pos[i];
         if (xy) {
@@ -395,12 +415,10 @@ fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_
         }
         if (alive) alive[i] = p >= 0 ? 1 : 0;
         if (desired) {
-            const int q = des[i];
+            const int q = tgt[i];
             desired[i] = (p < 0 || q < 0) ? -1 : (q / Wp - v) * W + (q % Wp - v);
         }
     }
-    if (step) *step = ctr[fk::C_STEP];
-    if (n_active) *n_active = ctr[fk::C_NACTIVE];
     return FAST_OK;
 }
 
@@ -425,36 +443,58 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
         for (int g = 0; g < G[i]; ++g) mitems.push_back(motion_item(order[i], g, G[i]));
     Batch b;
     b.members = hs;
-    const size_t ib = align_up(items.size() * 4, 256);
-    b.bytes = ib + mitems.size() * 4;
+    const size_t ib = align_up(items.size() * 4, 256), mb = align_up(mitems.size() * 4, 256);
+    b.bytes = ib + mb + order.size() * 4;
     fast_status st = dev_alloc(c, b.bytes, &b.block);
     if (st) return st;
     b.items = (uint32_t *)b.block;
     b.mitems = (uint32_t *)((char *)b.block + ib);
+    b.slots = (int32_t *)((char *)b.block + ib + mb);
+    b.n_items = (int)items.size();
     b.n_mitems = (int)mitems.size();
+    b.n_slots = (int)order.size();
     HIP_TRY(hipMemcpy(b.items, items.data(), items.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(b.mitems, mitems.data(), mitems.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b.slots, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+    auto res = c->batches.emplace(hs, b);
+    *out = &res.first->second;
+    return FAST_OK;
+}
 
-    // capture one time step: one planning launch over every tile, one motion
-    // launch with a workgroup per scenario
+// One time step of a batch captured as a HIP graph: one planning launch over
+// every tile of every member, one motion launch over their workgroup groups.
+fast_status batch_graph(fast_ctx *c, Batch *b)
+{
+    if (b->exec) return FAST_OK;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = fk_launch_plan(c->table, b.items, (int)items.size(), 0, c->stream);
-    hipError_t e2 = fk_launch_move(c->table, b.mitems, b.n_mitems, c->stream);
-    hipError_t e3 = hipStreamEndCapture(c->stream, &b.graph);
+    hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, 0, c->stream);
+    hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
+    hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-        if (b.graph) (void)hipGraphDestroy(b.graph);
-        dev_free(c, b.block, b.bytes);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
         return fail(FAST_E_DEVICE, "graph capture failed: %s / %s / %s", hipGetErrorString(e1),
                     hipGetErrorString(e2), hipGetErrorString(e3));
     }
-    hipError_t e4 = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+    hipError_t e4 = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e4 != hipSuccess) {
-        (void)hipGraphDestroy(b.graph);
-        dev_free(c, b.block, b.bytes);
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+        b->exec = nullptr;
         return fail(FAST_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e4));
     }
-    auto res = c->batches.emplace(hs, b);
-    *out = &res.first->second;
+    return FAST_OK;
+}
+
+fast_status check_handles(fast_ctx *c, const int32_t *hs, int32_t n, std::vector<int32_t> &out)
+{
+    if (!hs || n < 1) return fail(FAST_E_INVALID, "empty handle list");
+    out.assign(hs, hs + n);
+    std::sort(out.begin(), out.end());
+    if (std::adjacent_find(out.begin(), out.end()) != out.end())
+        return fail(FAST_E_INVALID, "a handle appears twice");
+    for (int32_t h : out)
+        if (!get_slot(c, h)) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     return FAST_OK;
 }
 
@@ -468,6 +508,8 @@ fast_status run_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     if (steps == 0) return FAST_OK;
     Batch *b = nullptr;
     fast_status st = get_batch(c, hs, &b);
+    if (st) return st;
+    st = batch_graph(c, b);
     if (st) return st;
     for (int k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(b->exec, c->stream));
     for (int32_t h : hs) c->slots[h].host_steps += steps;
@@ -695,7 +737,6 @@ fast_status fast_plan_step(fast_ctx *c, int32_t h)
     std::lock_guard<std::recursive_mutex> g(c->mu);
     Slot *s = get_slot(c, h);
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
-    if (s->planned) HIP_TRY(fk_launch_reset(c->table, s->self, 1, c->stream));
     HIP_TRY(fk_launch_plan(c->table, s->items, s->n_items, 0, c->stream));
     s->planned = true;
     return FAST_OK;
@@ -716,13 +757,48 @@ fast_status fast_move_step(fast_ctx *c, int32_t h)
 
 fast_status fast_run(fast_ctx *c, const int32_t *hs, int32_t n, int32_t steps)
 {
-    if (!c || !hs || n < 1 || steps < 0) return fail(FAST_E_INVALID, "bad arguments to fast_run");
+    if (!c || steps < 0) return fail(FAST_E_INVALID, "bad arguments to fast_run");
     std::lock_guard<std::recursive_mutex> g(c->mu);
-    std::vector<int32_t> v(hs, hs + n);
-    std::sort(v.begin(), v.end());
-    if (std::adjacent_find(v.begin(), v.end()) != v.end())
-        return fail(FAST_E_INVALID, "a handle appears twice");
+    std::vector<int32_t> v;
+    fast_status st = check_handles(c, hs, n, v);
+    if (st) return st;
     return run_batch(c, v, steps);
+}
+
+fast_status fast_plan_batch(fast_ctx *c, const int32_t *hs, int32_t n)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    std::vector<int32_t> v;
+    fast_status st = check_handles(c, hs, n, v);
+    if (st) return st;
+    Batch *b = nullptr;
+    st = get_batch(c, v, &b);
+    if (st) return st;
+    HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, 0, c->stream));
+    for (int32_t h : v) c->slots[h].planned = true;
+    return FAST_OK;
+}
+
+fast_status fast_move_batch(fast_ctx *c, const int32_t *hs, int32_t n)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    std::vector<int32_t> v;
+    fast_status st = check_handles(c, hs, n, v);
+    if (st) return st;
+    for (int32_t h : v)
+        if (!c->slots[h].planned)
+            return fail(FAST_E_STATE, "scenario %d: motion without a plan of this step", h);
+    Batch *b = nullptr;
+    st = get_batch(c, v, &b);
+    if (st) return st;
+    HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
+    for (int32_t h : v) {
+        c->slots[h].planned = false;
+        c->slots[h].host_steps += 1;
+    }
+    return FAST_OK;
 }
 
 fast_status fast_get_state(fast_ctx *c, int32_t h, int32_t *xy, uint8_t *alive, int32_t *desired,
@@ -785,7 +861,6 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     sd.dbg_margin = (float *)((char *)block + bw + bf);
     hipError_t e = hipMemsetAsync(block, 0, bw + bf + bm, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && s->planned) e = fk_launch_reset(c->table, s->self, 1, c->stream);
     if (e == hipSuccess) e = fk_launch_plan(c->table, s->items, s->n_items, 1, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->table + h, &s->dev, sizeof sd, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

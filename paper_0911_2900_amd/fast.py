@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
         "fast_plan_step": [P, I32],
         "fast_move_step": [P, I32],
         "fast_run": [P, P, I32, I32],
+        "fast_plan_batch": [P, P, I32],
+        "fast_move_batch": [P, P, I32],
         "fast_get_state": [P, I32, P, P, P, P, P],
         "fast_get_stats": [P, I32, P],
         "fast_debug_plan": [P, I32, P, P, P],
@@ -209,6 +211,14 @@ class Context:
 
     def move(self, h: int):
         _check(lib().fast_move_step(self.ctx, h))
+
+    def plan_batch(self, handles):
+        hs = np.ascontiguousarray(np.asarray(list(handles), dtype=np.int32))
+        _check(lib().fast_plan_batch(self.ctx, _ptr(hs), len(hs)))
+
+    def move_batch(self, handles):
+        hs = np.ascontiguousarray(np.asarray(list(handles), dtype=np.int32))
+        _check(lib().fast_move_batch(self.ctx, _ptr(hs), len(hs)))
 
     def run(self, handles, steps: int):
         hs = np.ascontiguousarray(np.asarray(list(handles), dtype=np.int32))
