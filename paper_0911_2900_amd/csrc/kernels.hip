@@ -633,19 +633,24 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
     __shared__ int sh_scan[MOVE_THREADS];
     const int tid = threadIdx.x;
     const int T = s.ntx * s.nty, TC = s.tx * s.ty;
-    const int t_lo = (int)((long)T * g / G), t_hi = (int)((long)T * (g + 1) / G);
-    Mover *cur = s.mv_a + (long)t_lo * TC, *nxt = s.mv_b + (long)t_lo * TC;
+    // workgroup g takes tiles g, g + G, g + 2G, ...: every region of the grid
+    // (the congested exit above all) is spread over the whole group, so the
+    // rounds stay balanced; its mover lists own tiles' worth of room
+    const int q = T / G, rm = T % G;
+    const int nt_g = q + (g < rm ? 1 : 0);
+    const long base_g = ((long)g * q + min(g, rm)) * TC;
+    Mover *cur = s.mv_a + base_g, *nxt = s.mv_b + base_g;
     unsigned long long seen0 = 0, seen1 = 0;
     uint32_t tag = (uint32_t)s.ctr[C_TAG];
     if (g == 0 && tid == 0)   // agents planned this step, for the throughput counters
         atomicAdd(&s.stat[S_PLANNED], (unsigned long long)s.ctr[C_NACTIVE]);
 
-    // gather this workgroup's movers (the records of tiles [t_lo, t_hi)) with
-    // their priority words [~x0:32][~id:20] (larger = earlier)
+    // gather this workgroup's movers (the records of its tiles) with their
+    // priority words [~x0:32][~id:20] (larger = earlier)
     int n = 0;
-    for (int tc = t_lo; tc < t_hi; tc += MOVE_THREADS) {
-        const int nt = min(MOVE_THREADS, t_hi - tc);
-        sh_scan[tid] = tid < nt ? s.seg_cnt[tc + tid] : 0;
+    for (int j0 = 0; j0 < nt_g; j0 += MOVE_THREADS) {
+        const int nt = min(MOVE_THREADS, nt_g - j0);
+        sh_scan[tid] = tid < nt ? s.seg_cnt[g + (long)(j0 + tid) * G] : 0;
         __syncthreads();
         for (int off = 1; off < MOVE_THREADS; off <<= 1) {
             const int add = tid >= off ? sh_scan[tid - off] : 0;
@@ -661,7 +666,7 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
                 if (sh_scan[mid] > i) b = mid; else a = mid + 1;
             }
             const int k = i - (a ? sh_scan[a - 1] : 0);
-            const MoveRec rec = s.seg[(long)(tc + a) * TC + k];
+            const MoveRec rec = s.seg[(g + (long)(j0 + a) * G) * TC + k];
             const uint32_t x0 = philox_word0(rec.id, (uint32_t)step, s.scn, STREAM_ORDER,
                                              s.seed_lo, s.seed_hi);
             Mover mv;
