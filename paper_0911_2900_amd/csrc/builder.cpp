@@ -190,10 +190,12 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
     // padded layout
     b.ntx = (W + tx - 1) / tx;
     b.nty = (H + ty - 1) / ty;
-    // rows padded to a multiple of 32 cells, with room for the planning
-    // kernel's 4-cell vector loads past the last tile's window
-    b.Wp = (b.ntx * tx + 2 * v + 3 + 31) / 32 * 32;
-    b.Hp = b.nty * ty + 2 * v;
+    // a wall border of pad = round4(v) cells (the planning kernel stages whole
+    // 4-cell chunks, each inside one tile column), rows padded to 32 cells
+    const int pad = (v + 3) / 4 * 4;
+    b.pad = pad;
+    b.Wp = (b.ntx * tx + 2 * pad + 31) / 32 * 32;
+    b.Hp = b.nty * ty + 2 * pad;
     const int64_t np = (int64_t)b.Wp * b.Hp;
     b.type.assign((size_t)np, fk::CELL_WALL);
     b.S.assign((size_t)np, INFINITY);
@@ -201,14 +203,14 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
     b.occ.assign((size_t)np, -1);
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
-            const int64_t g = (int64_t)(y + v) * b.Wp + (x + v);
+            const int64_t g = (int64_t)(y + pad) * b.Wp + (x + pad);
             b.type[g] = type[(int64_t)y * W + x];
             b.S[g] = S[(int64_t)y * W + x];
         }
     b.n = d.n_agents;
     b.pos.resize((size_t)b.n);
     for (int i = 0; i < b.n; ++i) {
-        const int64_t g = (int64_t)(xy[2 * i + 1] + v) * b.Wp + (xy[2 * i] + v);
+        const int64_t g = (int64_t)(xy[2 * i + 1] + pad) * b.Wp + (xy[2 * i] + pad);
         b.pos[i] = (int32_t)g;
         b.occ[g] = i;
     }
@@ -221,16 +223,16 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
     for (int j = 0; j < b.nty; ++j)
         for (int i = 0; i < b.ntx; ++i) {
             double lo = INFINITY, hi = -INFINITY;
-            for (int y = j * ty; y < j * ty + ty + 2 * v; ++y)
-                for (int x = i * tx; x < i * tx + tx + 2 * v; ++x) {
+            for (int y = j * ty + pad - v; y < j * ty + pad + ty + v; ++y)
+                for (int x = i * tx + pad - v; x < i * tx + pad + tx + v; ++x) {
                     const double s = b.S[(int64_t)y * b.Wp + x];
                     if (std::isfinite(s)) { lo = std::min(lo, s); hi = std::max(hi, s); }
                 }
             int32_t m = 0;
             if (lo <= hi) m = (int32_t)std::llround(ks * 0.5 * (lo + hi) / kLn2);
             b.tile_m[(size_t)(j + 1) * ts + i + 1] = m;
-            for (int y = j * ty + v; y < j * ty + ty + v; ++y)
-                for (int x = i * tx + v; x < i * tx + tx + v; ++x) mcell[(int64_t)y * b.Wp + x] = m;
+            for (int y = j * ty + pad; y < j * ty + ty + pad; ++y)
+                for (int x = i * tx + pad; x < i * tx + tx + pad; ++x) mcell[(int64_t)y * b.Wp + x] = m;
         }
     // table entries in the scale of their own tile
     std::vector<char> cell_ok((size_t)np, 1);
@@ -248,8 +250,8 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
         for (int i = 0; i < b.ntx; ++i) {
             const int32_t m = b.tile_m[(size_t)(j + 1) * ts + i + 1];
             bool ok = true;
-            for (int y = j * ty; ok && y < j * ty + ty + 2 * v; ++y)
-                for (int x = i * tx; x < i * tx + tx + 2 * v; ++x) {
+            for (int y = j * ty + pad - v; ok && y < j * ty + pad + ty + v; ++y)
+                for (int x = i * tx + pad - v; x < i * tx + pad + tx + v; ++x) {
                     const int64_t g = (int64_t)y * b.Wp + x;
                     const double s = b.S[g];
                     if (!std::isfinite(s)) continue;

@@ -1,12 +1,13 @@
 // fast_dev.h -- data layout shared by libfast's host runtime and its gfx950
 // kernels: the per-scenario slot descriptor, counters, and Philox4x32-10.
 //
-// Layout of one scenario (a "slot") in HBM.  The grid is padded by v cells of
-// wall on every side and rounded up to whole planning tiles, so that a tile's
-// (tx + 2v) x (ty + 2v) window never needs a bounds check:
-//   padded width  Wp = ntx * tx + 2v rounded up past 4-cell vector reads to a
-//   multiple of 32 cells,  padded height Hp = nty * ty + 2v,
-//   cell (x, y) of the scenario lives at index (y + v) * Wp + (x + v).
+// Layout of one scenario (a "slot") in HBM.  The grid is padded by
+// pad = round4(v) cells of wall on every side and rounded up to whole planning
+// tiles, so that a tile's staged window -- tx + 2 pad columns (whole 4-cell
+// chunks, each inside one tile column) by ty + 2v rows -- needs no bounds check:
+//   padded width  Wp = ntx * tx + 2 pad rounded up to a multiple of 32 cells,
+//   padded height Hp = nty * ty + 2 pad,
+//   cell (x, y) of the scenario lives at index (y + pad) * Wp + (x + pad).
 // Per cell:  type u8 (static), G f32 (static exp table, see below),
 //            S f64 (static floor field, read only by the FP64 re-resolve),
 //            occ i32 (agent id or -1), res0/res1 u64 (motion reservations of
@@ -36,7 +37,7 @@ enum : int { CELL_FREE = 0, CELL_WALL = 1, CELL_EXIT = 2 };
 
 constexpr int MAX_V = 5;
 constexpr int MAX_TILE_CELLS = 1024;   // tx * ty
-constexpr int MAX_STAGE = 2112;        // round4(tx + 2v) * (ty + 2v) over the allowed tiles
+constexpr int MAX_STAGE = 2368;        // (tx + 2 pad) * (ty + 2v) over the allowed tiles
 constexpr int PLAN_THREADS = 256;
 constexpr int MOVE_THREADS = 1024;
 constexpr int MOVE_GROUP_MAX = 64;        // workgroups per scenario in the motion phase
@@ -81,7 +82,8 @@ enum : int { S_FLAGGED = 0, S_FALLBACK = 1, S_PLANNED = 2, S_NSTAT = 4 };
 struct SlotDev {
     int32_t W, H;            // scenario size
     int32_t Wp, Hp;          // padded size
-    int32_t v;               // v_m; also the pad width
+    int32_t v;               // v_m
+    int32_t pad;             // wall border, round4(v)
     int32_t tx, ty;          // planning tile
     int32_t ntx, nty;        // tiles per row / column
     int32_t n_agents;

@@ -15,7 +15,7 @@ namespace fh {
 
 // A scenario laid out for the device (see fast_dev.h for the layout).
 struct Built {
-    int W = 0, H = 0, v = 0, tx = 0, ty = 0, ntx = 0, nty = 0, Wp = 0, Hp = 0;
+    int W = 0, H = 0, v = 0, pad = 0, tx = 0, ty = 0, ntx = 0, nty = 0, Wp = 0, Hp = 0;
     std::vector<uint8_t> type;     // padded
     std::vector<float> G;          // padded exp table
     std::vector<double> S;         // padded floor field

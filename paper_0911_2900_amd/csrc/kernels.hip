@@ -197,8 +197,6 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-constexpr int STAGE_ITERS = (MAX_STAGE / 4 + PLAN_THREADS - 1) / PLAN_THREADS;   // 3
-
 template <int V, bool DEBUG>
 __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, PlanShared &sh)
 {
@@ -206,11 +204,17 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int lane = __lane_id();
-    const int LX = s.tx + 2 * V, LY = s.ty + 2 * V;
-    const int P = (LX + 3) & ~3;                              // LDS pitch and load width
+    const int Hc = s.pad;                                    // column halo, a multiple of 4 >= V
+    const int LY = s.ty + 2 * V;
+    const int P = s.tx + 2 * Hc;                              // LDS pitch = staged width
     const int cpr = P >> 2;                                   // 4-cell chunks per row
-    const int nchunk = cpr * LY;
-    const int gx0 = tile_x * s.tx, gy0 = tile_y * s.ty;       // padded origin of the window
+    const int hc4 = Hc >> 2;
+    const int cw = s.tx >> 2;                                 // interior chunks per row (power of 2)
+    const int cw_log = __builtin_ctz(cw);
+    const int n_in = cw * s.ty;                               // interior chunks (<= nthr)
+    const int n_top = V * cpr;                                // halo chunks: V rows above / below,
+    const int n_halo = 2 * n_top + s.ty * 2 * hc4;            // then hc4 chunks left and right
+    const int gx0 = tile_x * s.tx, gy0 = tile_y * s.ty + Hc - V;   // padded origin of the window
     const int tstride = s.ntx + 2;
     const bool fallback = s.tile_fb[tile_y * s.ntx + tile_x] != 0;
 
@@ -220,61 +224,87 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
     const int tile = tile_y * s.ntx + tile_x;
     MoveRec *seg = s.seg + (long)tile * (s.tx * s.ty);
 
-    // --- stage the window.  All of a thread's 16-byte loads are issued first.
-    int4 o4[STAGE_ITERS];
-    float4 g4[STAGE_ITERS];
-    const float inv_cpr = 1.0f / (float)cpr;
+    // --- stage the window: one interior chunk and up to two halo chunks per
+    // thread, 16-byte loads of occupancy and exp table, all issued first
+    const int ci = tid;
+    const int ly_in = V + (ci >> cw_log), cc_in = hc4 + (ci & (cw - 1));
+    int ly_h[2], cc_h[2];
+    const float inv_cpr = 1.0f / (float)cpr, inv_side = 1.0f / (float)(2 * hc4);
 #pragma unroll
-    for (int j = 0; j < STAGE_ITERS; ++j) {
-        const int ch = tid + j * nthr;
-        o4[j] = make_int4(-1, -1, -1, -1);
-        g4[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ch < nchunk) {
-            const int ly = (int)(((float)ch + 0.5f) * inv_cpr);
-            const int lx = (ch - ly * cpr) * 4;
-            const int g = (gy0 + ly) * s.Wp + gx0 + lx;
-            o4[j] = *(const int4 *)(s.occ + g);
-            g4[j] = *(const float4 *)(s.G + g);
+    for (int j = 0; j < 2; ++j) {
+        const int h = tid + j * nthr;
+        int ly, cc;
+        if (h < 2 * n_top) {                                  // rows above, then rows below
+            const int hh = h < n_top ? h : h - n_top;
+            ly = (int)(((float)hh + 0.5f) * inv_cpr);
+            cc = hh - ly * cpr;
+            if (h >= n_top) ly += V + s.ty;
+        } else {                                              // left / right columns
+            const int hh = h - 2 * n_top;
+            const int r = (int)(((float)hh + 0.5f) * inv_side);
+            const int c = hh - r * 2 * hc4;
+            ly = V + r;
+            cc = c < hc4 ? c : c + cw;
         }
+        ly_h[j] = ly;
+        cc_h[j] = cc;
+    }
+    int4 o_in = make_int4(-1, -1, -1, -1), o_h0 = o_in, o_h1 = o_in;
+    float4 g_in = make_float4(0.f, 0.f, 0.f, 0.f), g_h0 = g_in, g_h1 = g_in;
+    if (ci < n_in) {
+        const int g = (gy0 + ly_in) * s.Wp + gx0 + 4 * cc_in;
+        o_in = *(const int4 *)(s.occ + g);
+        g_in = *(const float4 *)(s.G + g);
+    }
+    if (tid < n_halo) {
+        const int g = (gy0 + ly_h[0]) * s.Wp + gx0 + 4 * cc_h[0];
+        o_h0 = *(const int4 *)(s.occ + g);
+        g_h0 = *(const float4 *)(s.G + g);
+    }
+    if (tid + nthr < n_halo) {
+        const int g = (gy0 + ly_h[1]) * s.Wp + gx0 + 4 * cc_h[1];
+        o_h1 = *(const int4 *)(s.occ + g);
+        g_h1 = *(const float4 *)(s.G + g);
     }
     __syncthreads();                                          // m_nb, counters ready
     const int mT = sh.m_nb[4];
-#pragma unroll
-    for (int j = 0; j < STAGE_ITERS; ++j) {
-        const int ch = tid + j * nthr;
-        const bool live = ch < nchunk;
-        const int ly = (int)(((float)ch + 0.5f) * inv_cpr);
-        const int lx0 = (ch - ly * cpr) * 4;
+
+    // halo chunks: rescale to this tile's exponent, mask occupied cells
+    auto stage_halo = [&](int ly, int cc, int4 o, float4 gv) {
         const int nby = (ly >= V) + (ly >= V + s.ty);
-        const int ov[4] = {o4[j].x, o4[j].y, o4[j].z, o4[j].w};
-        const float gv[4] = {g4[j].x, g4[j].y, g4[j].z, g4[j].w};
-        float e[4];
-        bool ag[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int lx = lx0 + k;
-            const int nbx = (lx >= V) + (lx >= V + s.tx);
-            e[k] = ldexpf(gv[k], mT - sh.m_nb[nby * 3 + nbx]);
-            ag[k] = live && nbx == 1 && nby == 1 && ov[k] >= 0;
-        }
+        const int nbx = (cc >= hc4) + (cc >= hc4 + cw);       // a chunk lies inside one tile column
+        const int dm = mT - sh.m_nb[nby * 3 + nbx];
+        *(float4 *)&sh.Em[ly * P + 4 * cc] =
+            make_float4(o.x < 0 ? ldexpf(gv.x, dm) : 0.f, o.y < 0 ? ldexpf(gv.y, dm) : 0.f,
+                        o.z < 0 ? ldexpf(gv.z, dm) : 0.f, o.w < 0 ? ldexpf(gv.w, dm) : 0.f);
+    };
+    if (tid < n_halo) stage_halo(ly_h[0], cc_h[0], o_h0, g_h0);
+    if (tid + nthr < n_halo) stage_halo(ly_h[1], cc_h[1], o_h1, g_h1);
+
+    // interior chunk: already in the tile's scale; its occupied cells are the
+    // tile's agents (one LDS atomic per wavefront to list them)
+    {
+        const bool live = ci < n_in;
+        const int l0 = ly_in * P + 4 * cc_in;
         if (live)
-            *(float4 *)&sh.Em[ly * P + lx0] = make_float4(ov[0] < 0 ? e[0] : 0.f, ov[1] < 0 ? e[1] : 0.f,
-                                                          ov[2] < 0 ? e[2] : 0.f, ov[3] < 0 ? e[3] : 0.f);
-        // compact the agents found: one LDS atomic per wavefront
+            *(float4 *)&sh.Em[l0] = make_float4(o_in.x < 0 ? g_in.x : 0.f, o_in.y < 0 ? g_in.y : 0.f,
+                                                o_in.z < 0 ? g_in.z : 0.f, o_in.w < 0 ? g_in.w : 0.f);
+        const int ov[4] = {o_in.x, o_in.y, o_in.z, o_in.w};
+        const float gv[4] = {g_in.x, g_in.y, g_in.z, g_in.w};
         unsigned long long m[4];
         int tot = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) { m[k] = __ballot(ag[k]); tot += __popcll(m[k]); }
+        for (int k = 0; k < 4; ++k) { m[k] = __ballot(live && ov[k] >= 0); tot += __popcll(m[k]); }
         if (tot) {
             int base = 0;
             if (lane == 0) base = atomicAdd(&sh.n_agents, tot);
             base = __shfl(base, 0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (ag[k]) {
+                if (live && ov[k] >= 0) {
                     const int slot = base + lanes_below(m[k]);
-                    sh.a_pk[slot] = (ov[k] << 12) | (ly * P + lx0 + k);
-                    sh.a_ec[slot] = e[k];
+                    sh.a_pk[slot] = (ov[k] << 12) | (l0 + k);
+                    sh.a_ec[slot] = gv[k];
                 }
                 base += __popcll(m[k]);
             }
@@ -398,28 +428,32 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
     }
     __syncthreads();
 
-    // --- FP64 re-resolve of the flagged draws, one wavefront per draw
+    // --- FP64 re-resolve of the flagged draws, one wavefront per draw.  The
+    // whole section sits behind a workgroup-uniform test so that none of its
+    // setup runs on the common path without flags.
     const int nf = sh.n_flag;
-    const int wave = tid >> 6, nwaves = nthr >> 6;
-    for (int w = wave; w < (na + 31) / 32; w += nwaves) {
-        uint32_t bits = sh.flags[w];
-        while (bits) {
-            const int k = w * 32 + __builtin_ctz(bits);
-            bits &= bits - 1u;
-            const int id = sh.a_pk[k] >> 12;
-            const int l = sh.a_pk[k] & 0xFFF;
-            const int ly = (int)(((float)l + 0.5f) * inv_P);
-            const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
-            const int gc = cy * s.Wp + cx;
-            const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
-                                             kseed0, kseed1);
-            const float u = (float)(x0 >> 8) * 0x1p-24f;
-            const int t = resolve64_wave<V>(s, gc, u, lane);
-            if (lane == 0 && t != gc) {
-                const int d = t - gc;
-                const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
-                seg[atomicAdd(&sh.n_mov, 1)] =
-                    MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+    if (nf != 0) {
+        const int wave = tid >> 6, nwaves = nthr >> 6;
+        for (int w = wave; w < (na + 31) / 32; w += nwaves) {
+            uint32_t bits = sh.flags[w];
+            while (bits) {
+                const int k = w * 32 + __builtin_ctz(bits);
+                bits &= bits - 1u;
+                const int id = sh.a_pk[k] >> 12;
+                const int l = sh.a_pk[k] & 0xFFF;
+                const int ly = (int)(((float)l + 0.5f) * inv_P);
+                const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
+                const int gc = cy * s.Wp + cx;
+                const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
+                                                 kseed0, kseed1);
+                const float u = (float)(x0 >> 8) * 0x1p-24f;
+                const int t = resolve64_wave<V>(s, gc, u, lane);
+                if (lane == 0 && t != gc) {
+                    const int d = t - gc;
+                    const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
+                    seg[atomicAdd(&sh.n_mov, 1)] =
+                        MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                }
             }
         }
     }

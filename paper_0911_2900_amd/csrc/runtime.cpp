@@ -290,7 +290,7 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     char *base = (char *)block;
 
     fk::SlotDev sd{};
-    sd.W = b.W; sd.H = b.H; sd.Wp = b.Wp; sd.Hp = b.Hp; sd.v = b.v;
+    sd.W = b.W; sd.H = b.H; sd.Wp = b.Wp; sd.Hp = b.Hp; sd.v = b.v; sd.pad = b.pad;
     sd.tx = b.tx; sd.ty = b.ty; sd.ntx = b.ntx; sd.nty = b.nty; sd.n_agents = b.n;
     sd.seed_lo = (uint32_t)d->seed; sd.seed_hi = (uint32_t)(d->seed >> 32);
     sd.scn = d->scenario_id; sd.eps = b.eps; sd.k_s = d->k_s;
@@ -392,7 +392,7 @@ fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_
     HIP_TRY(hipMemcpy(occ.data(), d.occ, cells * 4, hipMemcpyDeviceToHost));
     for (size_t g = 0; g < cells; ++g)
         if (occ[g] >= 0 && occ[g] < n) pos[occ[g]] = (int32_t)g;
-    const int Wp = d.Wp, v = d.v, W = d.W;
+    const int Wp = d.Wp, pad = d.pad, W = d.W;
     std::vector<int32_t> tgt;
     if (desired) {
         const size_t ntiles = (size_t)d.ntx * d.nty, tc = (size_t)d.tx * d.ty;
@@ -410,13 +410,13 @@ fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_
     for (int i = 0; i < n; ++i) {
         const int p = pos[i];
         if (xy) {
-            xy[2 * i] = p < 0 ? -1 : p % Wp - v;
-            xy[2 * i + 1] = p < 0 ? -1 : p / Wp - v;
+            xy[2 * i] = p < 0 ? -1 : p % Wp - pad;
+            xy[2 * i + 1] = p < 0 ? -1 : p / Wp - pad;
         }
         if (alive) alive[i] = p >= 0 ? 1 : 0;
         if (desired) {
             const int q = tgt[i];
-            desired[i] = (p < 0 || q < 0) ? -1 : (q / Wp - v) * W + (q % Wp - v);
+            desired[i] = (p < 0 || q < 0) ? -1 : (q / Wp - pad) * W + (q % Wp - pad);
         }
     }
     return FAST_OK;
