@@ -498,6 +498,21 @@ fast_status check_handles(fast_ctx *c, const int32_t *hs, int32_t n, std::vector
     return FAST_OK;
 }
 
+// Steps of a batch as plain launches (one planning and one motion launch per
+// step), for member sets that change too often to be worth a graph.
+fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
+{
+    Batch *b = nullptr;
+    fast_status st = get_batch(c, hs, &b);
+    if (st) return st;
+    for (int k = 0; k < steps; ++k) {
+        HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, 0, c->stream));
+        HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
+    }
+    for (int32_t h : hs) c->slots[h].host_steps += steps;
+    return FAST_OK;
+}
+
 fast_status run_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
 {
     for (int32_t h : hs) {
@@ -576,7 +591,7 @@ void serve_loop(fast_ctx *c)
         chunk = std::max(1, std::min(chunk, 8));
         {
             std::lock_guard<std::recursive_mutex> g(c->mu);
-            if (run_batch(c, hs, chunk)) {
+            if (launch_batch(c, hs, chunk)) {
                 std::lock_guard<std::mutex> lk(c->smu);
                 for (uint64_t t : active) { c->reqs[t]->state = -1; c->reqs[t]->t_done = now_s(); }
                 active.clear();

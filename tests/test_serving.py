@@ -1,0 +1,108 @@
+"""Serving (continuous batching) through the C-ABI: requests that arrive while
+others run are admitted as slots free up, and every request's final state is
+bit-identical to the oracle's run of the same scenario alone."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0911_2900_amd import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fast_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0911_2900_amd import fast
+    return fast
+
+
+def _requests(k0, count, steps):
+    reqs = []
+    for k in range(k0, k0 + count):
+        m = sc.ensemble_member(k, base_seed=4, scn_base=1000)
+        reqs.append((m, steps))
+    return reqs
+
+
+def _oracle_final(m, steps):
+    sim = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents)
+    sim.run(steps)
+    return sim.positions(), sim.alive[: sim.n].astype(bool)
+
+
+def _serve(fast, reqs, budget, max_active, gap_s):
+    ctx = fast.Context(device=0, torch_alloc=False)
+    try:
+        ctx.serve_start(budget=budget, max_active=max_active)
+        tickets = []
+        for m, steps in reqs:
+            tickets.append(ctx.serve_submit(m.cell_type, m.n_agents, m.v, m.k_s, m.seed, m.scn,
+                                            steps=steps))
+            time.sleep(gap_s)                      # later requests arrive while others run
+        deadline = time.time() + 120
+        lat = {}
+        while len(lat) < len(tickets):
+            assert time.time() < deadline, "serving did not finish"
+            for t in tickets:
+                if t not in lat:
+                    done, l = ctx.serve_poll(t)
+                    if done:
+                        lat[t] = l
+            time.sleep(0.002)
+        results = [ctx.serve_result(t) for t in tickets]
+        ctx.serve_stop()
+        return results, [lat[t] for t in tickets]
+    finally:
+        ctx.close()
+
+
+def test_served_results_equal_oracle_alone(fast_mod):
+    reqs = _requests(0, 10, 30)
+    results, lat = _serve(fast_mod, reqs, budget=0, max_active=4, gap_s=0.003)
+    say("latencies", np.round(lat, 4))
+    for (m, steps), r in zip(reqs, results):
+        xy, alive = _oracle_final(m, steps)
+        assert r["step"] == steps
+        assert np.array_equal(r["alive"].astype(bool), alive), m.name
+        assert np.array_equal(r["xy"], xy), m.name
+
+
+def test_small_budget_forces_queueing_and_stays_exact(fast_mod):
+    reqs = _requests(20, 6, 20)
+    probe = fast_mod.Context(device=0, torch_alloc=False)
+    sizes = []
+    for m, _ in reqs:
+        h = probe.init_from(m)
+        sizes.append(probe.stats(h)["device_bytes"])
+        probe.destroy(h)
+    probe.close()
+    # room for the largest request and a little more: admission must queue
+    budget = int(max(sizes) * 1.5) + (1 << 20)
+    assert budget < sum(sizes)
+    results, lat = _serve(fast_mod, reqs, budget=budget, max_active=0, gap_s=0.0)
+    say("latencies (queued)", np.round(lat, 4))
+    assert max(lat) > min(lat)
+    for (m, steps), r in zip(reqs, results):
+        xy, alive = _oracle_final(m, steps)
+        assert np.array_equal(r["xy"], xy), m.name
+
+
+def test_submit_without_start_fails(fast_mod):
+    ctx = fast_mod.Context(device=0)
+    try:
+        m = sc.corridor()
+        with pytest.raises(fast_mod.FastError):
+            ctx.serve_submit(m.cell_type, m.n_agents, m.v)
+    finally:
+        ctx.close()
