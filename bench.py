@@ -99,7 +99,7 @@ def bench_ensemble(ctx, torch, warmup: int, steps: int, plain_steps: int):
 
     ens = sc.ensemble(256)
     t0 = time.perf_counter()
-    hs = [ctx.init_from(m) for m in ens]
+    hs = [ctx.init_from(m, batched=True) for m in ens]
     init_s = time.perf_counter() - t0
     ctx.run(hs, warmup)
     planned0 = sum(ctx.stats(h)["planned"] for h in hs)
@@ -145,8 +145,9 @@ def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int):
     """Planning kernel of many scenarios in one launch (fast_plan_batch), the
     throughput regime: events around each launch, motion between them."""
     t0 = time.perf_counter()
-    hs = [ctx.init_from(m) for m in scenarios]
+    hs = [ctx.init_from(m, batched=True) for m in scenarios]
     init_s = time.perf_counter() - t0
+    tile = [ctx.stats(hs[0])["tile_w"], ctx.stats(hs[0])["tile_h"]]
     for _ in range(warmup):
         ctx.plan_batch(hs)
         ctx.move_batch(hs)
@@ -174,6 +175,7 @@ def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int):
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     return {
         "workload": name, "scenarios": len(scenarios), "agents": int(sum(m.n_agents for m in scenarios)),
+        "tile": tile,
         "planning_agent_updates_per_s": planned / (sum(plan_ms) / 1e3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "plan_kernel",
@@ -308,6 +310,7 @@ def main():
             "workload": "room 400x400 cells, 10-cell exit, 40,000 agents, v_m=4, k_S=1.2, "
                         "k_other=0; steps 0..395 of the 396-step run (warmup first)",
             "agents": 40000, "grid": [400, 400], "v_m": 4, "k_S": 1.2,
+            "tile": [r["stats"]["tile_w"], r["stats"]["tile_h"]],
             "parallelism": "1 GPU",
         },
         "whole_step_agent_updates_per_s": r["planned"] / (r["total_ms"] / 1e3),

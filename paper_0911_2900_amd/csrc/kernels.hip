@@ -124,43 +124,99 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
 }
 
 // The same draw by a whole wavefront: lane j evaluates raster slots j and
-// j + 64; the prefix sum is still taken sequentially, slot by slot, in raster
-// order, so the result is bit-identical to resolve64_lane.
-template <int V>
-__device__ __forceinline__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane)
+// j + 64 of the square window; the prefix sum is still taken sequentially,
+// slot by slot, in raster order, so the result is bit-identical to
+// resolve64_lane (slots outside the reach set add nothing).
+// Reachability is read from the tile's staged window (Em, agent cell l, pitch
+// P): on a fast tile a cell is zero there exactly when it is a wall, padding
+// or occupied, so only the floor field needs global reads.  For v <= 4 the
+// reach disc has at most 49 slots: lane j takes the j-th disc slot in raster
+// order and the sequential sum runs over the disc only (the slots it skips add
+// nothing in the raster-order sum); v = 5 uses the square window.
+constexpr int disc_count(int V)
 {
-    constexpr int SIDE = 2 * V + 1;
-    constexpr int NS = SIDE * SIDE;           // <= 121
+    int n = 0;
+    for (int dy = -V; dy <= V; ++dy) n += 2 * half_width(V, dy) + 1;
+    return n;
+}
+
+// (dx, dy) of the j-th slot of the disc in raster order (j < disc_count(V)).
+template <int V>
+__device__ __forceinline__ void disc_slot(int j, int &dx, int &dy)
+{
+    int start = 0;
+    dy = -V;
+    dx = 0;
+#pragma unroll
+    for (int r = -V; r <= V; ++r) {
+        const int a = half_width(V, r);
+        const bool in = j >= start;
+        dy = in ? r : dy;
+        dx = in ? j - start - a : dx;
+        start += 2 * a + 1;
+    }
+}
+
+template <int V>
+__device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, const float *Em,
+                              int l, int P)
+{
     const double Sc = s.S[gc];
     const double ks = s.k_s;
-    double w[2] = {0.0, 0.0};
+    if constexpr (disc_count(V) <= 64) {
+        constexpr int ND = disc_count(V);
+        double w = 0.0;
+        int dx = 0, dy = 0;
+        disc_slot<V>(lane, dx, dy);
+        if (lane < ND && ((dx == 0 && dy == 0) || Em[l + dy * P + dx] != 0.0f))
+            w = exp(ks * (Sc - s.S[gc + dy * s.Wp + dx]));
+        double C = 0.0, myC = 0.0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int j = lane + 64 * h;
-        if (j < NS) {
-            const int dy = j / SIDE - V, dx = j % SIDE - V;
-            const int t = gc + dy * s.Wp + dx;
-            if (reach_ok<V>(s, gc, t, dx, dy)) w[h] = exp(ks * (Sc - s.S[t]));
+        for (int j = 0; j < ND; ++j) {
+            const int lo = __builtin_amdgcn_readlane(__double2loint(w), j);
+            const int hi = __builtin_amdgcn_readlane(__double2hiint(w), j);
+            C = C + __hiloint2double(hi, lo);
+            if (lane == j) myC = C;
         }
-    }
-    double C = 0.0, myC0 = 0.0, myC1 = 0.0;
+        const double tau = (double)u32 * C;
+        const unsigned long long m = __ballot(lane < ND && tau < myC);
+        const int jw = m ? __builtin_ctzll(m) : V * 0 + (ND - 1) / 2;   // own cell if unreached
+        int wx, wy;
+        disc_slot<V>(jw, wx, wy);
+        return gc + wy * s.Wp + wx;
+    } else {
+        constexpr int SIDE = 2 * V + 1;
+        constexpr int NS = SIDE * SIDE;           // 121
+        double w[2] = {0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        const double wj = w[j / 64];
-        const int lo = __builtin_amdgcn_readlane(__double2loint(wj), j % 64);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(wj), j % 64);
-        C = C + __hiloint2double(hi, lo);
-        if (j < 64) { if (lane == j) myC0 = C; }
-        else { if (lane == j - 64) myC1 = C; }
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + 64 * h;
+            if (j < NS) {
+                const int dy = j / SIDE - V, dx = j % SIDE - V;
+                const bool own = dx == 0 && dy == 0;
+                if (dx * dx + dy * dy <= V * V && (own || Em[l + dy * P + dx] != 0.0f))
+                    w[h] = exp(ks * (Sc - s.S[gc + dy * s.Wp + dx]));
+            }
+        }
+        double C = 0.0, myC0 = 0.0, myC1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const double wj = w[j / 64];
+            const int lo = __builtin_amdgcn_readlane(__double2loint(wj), j % 64);
+            const int hi = __builtin_amdgcn_readlane(__double2hiint(wj), j % 64);
+            C = C + __hiloint2double(hi, lo);
+            if (j < 64) { if (lane == j) myC0 = C; }
+            else { if (lane == j - 64) myC1 = C; }
+        }
+        const double tau = (double)u32 * C;
+        const unsigned long long m0 = __ballot(lane < NS && tau < myC0);
+        const unsigned long long m1 = __ballot(lane + 64 < NS && tau < myC1);
+        int j;
+        if (m0) j = __builtin_ctzll(m0);
+        else if (m1) j = 64 + __builtin_ctzll(m1);
+        else j = V * SIDE + V;                   // not reached
+        return gc + (j / SIDE - V) * s.Wp + (j % SIDE - V);
     }
-    const double tau = (double)u32 * C;
-    const unsigned long long m0 = __ballot(lane < NS && tau < myC0);
-    const unsigned long long m1 = __ballot(lane + 64 < NS && tau < myC1);
-    int j;
-    if (m0) j = __builtin_ctzll(m0);
-    else if (m1) j = 64 + __builtin_ctzll(m1);
-    else j = V * SIDE + V;                       // not reached
-    return gc + (j / SIDE - V) * s.Wp + (j % SIDE - V);
 }
 
 // ---------------------------------------------------------------------------
@@ -170,7 +226,6 @@ struct PlanShared {
     alignas(16) float Em[MAX_STAGE];    // masked exp table window, pitch P = round4(tx + 2v)
     int32_t a_pk[MAX_TILE_CELLS];       // agents of the tile: id << 12 | LDS cell
     float a_ec[MAX_TILE_CELLS];         // e_c of their own cell
-    uint32_t flags[MAX_TILE_CELLS / 32];// draws to re-resolve in FP64
     int32_t m_nb[9];
     int n_agents, n_flag, n_mov;
 };
@@ -198,7 +253,7 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
 }
 
 template <int V, bool DEBUG>
-__device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, PlanShared &sh)
+__device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
 {
     constexpr int SIDE = 2 * V + 1;
     const int tid = threadIdx.x;
@@ -214,14 +269,13 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
     const int n_in = cw * s.ty;                               // interior chunks (<= nthr)
     const int n_top = V * cpr;                                // halo chunks: V rows above / below,
     const int n_halo = 2 * n_top + s.ty * 2 * hc4;            // then hc4 chunks left and right
+    const int tile_y = tile / s.ntx, tile_x = tile - tile_y * s.ntx;
     const int gx0 = tile_x * s.tx, gy0 = tile_y * s.ty + Hc - V;   // padded origin of the window
     const int tstride = s.ntx + 2;
     const bool fallback = s.tile_fb[tile_y * s.ntx + tile_x] != 0;
 
     if (tid < 9) sh.m_nb[tid] = s.tile_m[(tile_y + tid / 3) * tstride + tile_x + tid % 3];
-    if (tid < MAX_TILE_CELLS / 32) sh.flags[tid] = 0u;
     if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; sh.n_mov = 0; }
-    const int tile = tile_y * s.ntx + tile_x;
     MoveRec *seg = s.seg + (long)tile * (s.tx * s.ty);
 
     // --- stage the window: one interior chunk and up to two halo chunks per
@@ -266,6 +320,10 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
         o_h1 = *(const int4 *)(s.occ + g);
         g_h1 = *(const float4 *)(s.G + g);
     }
+    // the step counter is read while the staging loads are in flight
+    const int step = s.ctr[C_STEP];
+    if (step >= s.ctr[C_LIMIT]) return;                       // scenario finished: nothing to do
+    if (tile == 0 && tid < 4) s.ctr[C_BAR + tid] = 0;          // fresh motion barriers
     __syncthreads();                                          // m_nb, counters ready
     const int mT = sh.m_nb[4];
 
@@ -296,17 +354,20 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
 #pragma unroll
         for (int k = 0; k < 4; ++k) { m[k] = __ballot(live && ov[k] >= 0); tot += __popcll(m[k]); }
         if (tot) {
+            // lane-major order: the list follows the cells in raster order, so
+            // a wavefront's agents gather from consecutive LDS banks
             int base = 0;
             if (lane == 0) base = atomicAdd(&sh.n_agents, tot);
-            base = __shfl(base, 0);
+            int idx = __shfl(base, 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) idx += lanes_below(m[k]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (live && ov[k] >= 0) {
-                    const int slot = base + lanes_below(m[k]);
-                    sh.a_pk[slot] = (ov[k] << 12) | (l0 + k);
-                    sh.a_ec[slot] = gv[k];
+                    sh.a_pk[idx] = (ov[k] << 12) | (l0 + k);
+                    sh.a_ec[idx] = gv[k];
+                    ++idx;
                 }
-                base += __popcll(m[k]);
             }
         }
     }
@@ -351,7 +412,7 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
     // --- one lane per agent, FP32 from the LDS table
     for (int base = 0; base < na; base += nthr) {
         const int k = base + tid;
-        bool mover = false;
+        bool mover = false, flagged = false;
         MoveRec rec{};
         if (k < na) {
             const int id = sh.a_pk[k] >> 12;
@@ -415,76 +476,83 @@ __device__ void plan_tile(const SlotDev &s, int tile_x, int tile_y, int step, Pl
                 if (s.dbg_flag) s.dbg_flag[id] = flag ? 1 : 0;
                 if (s.dbg_margin) s.dbg_margin[id] = margin / Wsum;
             }
-            if (flag) {
-                atomicOr(&sh.flags[k >> 5], 1u << (k & 31));
-                atomicAdd(&sh.n_flag, 1);
-            } else {
+            if (!flag) {
                 const int ddx = ks - as, ddy = rs - V;
                 mover = ddx != 0 || ddy != 0;
                 rec = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
             }
+            flagged = flag;
         }
         emit_movers(seg, sh, mover, rec);
-    }
-    __syncthreads();
 
-    // --- FP64 re-resolve of the flagged draws, one wavefront per draw.  The
-    // whole section sits behind a workgroup-uniform test so that none of its
-    // setup runs on the common path without flags.
-    const int nf = sh.n_flag;
-    if (nf != 0) {
-        const int wave = tid >> 6, nwaves = nthr >> 6;
-        for (int w = wave; w < (na + 31) / 32; w += nwaves) {
-            uint32_t bits = sh.flags[w];
-            while (bits) {
-                const int k = w * 32 + __builtin_ctz(bits);
-                bits &= bits - 1u;
-                const int id = sh.a_pk[k] >> 12;
-                const int l = sh.a_pk[k] & 0xFFF;
+        // FP64 re-resolve of this wavefront's flagged draws, one draw at a
+        // time by the whole wavefront, without waiting for the other waves
+        unsigned long long fm = __ballot(flagged);
+        if (fm) {
+            if (lane == 0) atomicAdd(&sh.n_flag, __popcll(fm));
+            while (fm) {
+                const int src = __builtin_ctzll(fm);
+                fm &= fm - 1ull;
+                const int kk = base + (tid & ~63) + src;
+                const int fid = sh.a_pk[kk] >> 12;
+                const int l = sh.a_pk[kk] & 0xFFF;
                 const int ly = (int)(((float)l + 0.5f) * inv_P);
                 const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
                 const int gc = cy * s.Wp + cx;
-                const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
+                const uint32_t x0 = philox_word0((uint32_t)fid, (uint32_t)step, s.scn, STREAM_PLAN,
                                                  kseed0, kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const int t = resolve64_wave<V>(s, gc, u, lane);
+                const int t = resolve64_wave<V>(s, gc, u, lane, sh.Em, l, P);
                 if (lane == 0 && t != gc) {
                     const int d = t - gc;
                     const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
                     seg[atomicAdd(&sh.n_mov, 1)] =
-                        MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                        MoveRec{(uint32_t)fid, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
                 }
             }
         }
     }
     __syncthreads();
+    const int nf = sh.n_flag;
     if (tid == 0) {
         s.seg_cnt[tile] = sh.n_mov;
         if (nf) atomicAdd(&s.stat[S_FLAGGED], (unsigned long long)nf);
     }
 }
 
-// items[i] = (slot << 20) | tile index (row-major over the slot's tiles)
 template <bool DEBUG>
-__global__ __launch_bounds__(PLAN_THREADS) void plan_kernel(const SlotDev *__restrict__ table,
+__device__ __forceinline__ void plan_dispatch(const SlotDev &s, int tile, PlanShared &sh)
+{
+    switch (s.v) {
+        case 1: plan_tile<1, DEBUG>(s, tile, sh); break;
+        case 2: plan_tile<2, DEBUG>(s, tile, sh); break;
+        case 3: plan_tile<3, DEBUG>(s, tile, sh); break;
+        case 4: plan_tile<4, DEBUG>(s, tile, sh); break;
+        case 5: plan_tile<5, DEBUG>(s, tile, sh); break;
+        default: break;
+    }
+}
+
+// Batched form: items[i] = (slot << 20) | tile index (row-major over the
+// slot's tiles); descriptors come from the device table.
+template <bool DEBUG>
+__global__ __launch_bounds__(PLAN_THREADS) __attribute__((amdgpu_waves_per_eu(7)))
+void plan_kernel(const SlotDev *__restrict__ table,
                                                             const uint32_t *__restrict__ items)
 {
     __shared__ PlanShared sh;
     const uint32_t it = items[blockIdx.x];
-    const SlotDev &s = table[it >> 20];
-    const int tile = (int)(it & 0xFFFFFu);
-    const int step = s.ctr[C_STEP];
-    if (step >= s.ctr[C_LIMIT]) return;
-    const int tile_y = tile / s.ntx, tile_x = tile - tile_y * s.ntx;
-    if (tile == 0 && threadIdx.x < 4) s.ctr[C_BAR + threadIdx.x] = 0;   // fresh motion barriers
-    switch (s.v) {
-        case 1: plan_tile<1, DEBUG>(s, tile_x, tile_y, step, sh); break;
-        case 2: plan_tile<2, DEBUG>(s, tile_x, tile_y, step, sh); break;
-        case 3: plan_tile<3, DEBUG>(s, tile_x, tile_y, step, sh); break;
-        case 4: plan_tile<4, DEBUG>(s, tile_x, tile_y, step, sh); break;
-        case 5: plan_tile<5, DEBUG>(s, tile_x, tile_y, step, sh); break;
-        default: break;
-    }
+    plan_dispatch<DEBUG>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
+}
+
+// One scenario: its descriptor arrives by value with the kernel arguments and
+// workgroup i plans tile i, which saves two dependent memory round trips.
+template <bool DEBUG>
+__global__ __launch_bounds__(PLAN_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
+void plan_kernel_one(const SlotDev s)
+{
+    __shared__ PlanShared sh;
+    plan_dispatch<DEBUG>(s, (int)blockIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -773,6 +841,19 @@ __global__ __launch_bounds__(MOVE_THREADS) void move_kernel(const SlotDev *__res
 // ---------------------------------------------------------------------------
 // Launchers used by the host runtime.
 // ---------------------------------------------------------------------------
+extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, int debug,
+                                         hipStream_t stream)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    if (debug)
+        hipLaunchKernelGGL(fk::plan_kernel_one<true>, dim3(n_tiles), dim3(fk::PLAN_THREADS), 0, stream,
+                           *slot);
+    else
+        hipLaunchKernelGGL(fk::plan_kernel_one<false>, dim3(n_tiles), dim3(fk::PLAN_THREADS), 0,
+                           stream, *slot);
+    return hipGetLastError();
+}
+
 extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
                                      int debug, hipStream_t stream)
 {

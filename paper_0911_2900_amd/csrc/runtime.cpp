@@ -752,7 +752,7 @@ fast_status fast_plan_step(fast_ctx *c, int32_t h)
     std::lock_guard<std::recursive_mutex> g(c->mu);
     Slot *s = get_slot(c, h);
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
-    HIP_TRY(fk_launch_plan(c->table, s->items, s->n_items, 0, c->stream));
+    HIP_TRY(fk_launch_plan_one(&s->dev, s->n_items, 0, c->stream));
     s->planned = true;
     return FAST_OK;
 }
@@ -875,9 +875,7 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     sd.dbg_flag = (uint8_t *)((char *)block + bw);
     sd.dbg_margin = (float *)((char *)block + bw + bf);
     hipError_t e = hipMemsetAsync(block, 0, bw + bf + bm, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = fk_launch_plan(c->table, s->items, s->n_items, 1, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->table + h, &s->dev, sizeof sd, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = fk_launch_plan_one(&sd, s->n_items, 1, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) {
         s->planned = true;

@@ -188,7 +188,14 @@ class Context:
 
     # -- scenarios ---------------------------------------------------------
     def init_scenario(self, cell_type, n_agents=0, v=4, k_s=1.2, seed=1, scn=0, agent_xy=None,
-                      tile=None) -> int:
+                      tile="auto", batched=False) -> int:
+        """tile: (tx, ty); "auto" = the autotuner's table (planned alone, or in
+        a batched launch when `batched`), None = the library's own rule."""
+        if isinstance(tile, str):
+            from . import autotune
+            ct = np.asarray(cell_type)
+            n = len(agent_xy) if agent_xy is not None else int(n_agents)
+            tile = autotune.choose_tile(int(v), int(ct.shape[1]), int(ct.shape[0]), n, batched)
         d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_xy, tile)
         h = ctypes.c_int32(-1)
         _check(lib().fast_init_scenario(self.ctx, ctypes.byref(d), ctypes.byref(h)))
@@ -196,10 +203,10 @@ class Context:
         self.v[h.value] = int(v)
         return h.value
 
-    def init_from(self, sc, tile=None) -> int:
+    def init_from(self, sc, tile="auto", batched=False) -> int:
         """From a paper_0911_2900_amd.scenarios.Scenario."""
         return self.init_scenario(sc.cell_type, sc.n_agents, sc.v, sc.k_s, sc.seed, sc.scn,
-                                  tile=tile)
+                                  tile=tile, batched=batched)
 
     def destroy(self, h: int):
         _check(lib().fast_destroy_scenario(self.ctx, h))
