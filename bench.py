@@ -184,6 +184,82 @@ def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int):
     }
 
 
+def bench_serving(fast, n_req: int, rate: float, steps: int = 396, plain_sample: int = 16,
+                  small_budget_mb: int = 64):
+    """Continuous-batching server on Poisson arrivals (mean `rate` requests/s)
+    of scenarios drawn from the ensemble distribution (scenario ids 1000 + k),
+    `steps` steps each: an open-loop run whose budget admits everything, an
+    open-loop run on a quarter of the requests with a small forced budget so
+    admission binds, and a closed-loop run (all submitted at once) on half of
+    them for the saturation rate; next to the same requests run one at a time
+    with plain single-scenario launches (on a sample)."""
+    from paper_0911_2900_amd import scenarios as sc
+
+    t0 = time.perf_counter()
+    reqs = [sc.ensemble_member(k, base_seed=4, scn_base=1000) for k in range(n_req)]
+    gen_s = time.perf_counter() - t0
+    gaps = np.random.default_rng([4, 1]).exponential(1.0 / rate, n_req)
+
+    def run(members, budget, closed):
+        ctx = fast.Context(device=0, torch_alloc=False)
+        try:
+            ctx.serve_start(budget=budget)
+            arrive = np.zeros(len(members)) if closed else np.cumsum(gaps[: len(members)])
+            tickets = []
+            t_start = time.perf_counter()
+            for m, ta in zip(members, arrive):
+                dt = t_start + ta - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(ctx.serve_submit(m.cell_type, m.n_agents, m.v, m.k_s, m.seed,
+                                                m.scn, steps=steps))
+            ctx.serve_stop()                  # returns once every request has finished
+            wall = time.perf_counter() - t_start
+            lat = np.array([ctx.serve_poll(t)[1] for t in tickets])
+        finally:
+            ctx.close()
+        return {"requests": len(members), "wall_s": wall,
+                "scenarios_per_s": len(members) / wall,
+                "agent_steps_per_s": sum(m.n_agents for m in members) * steps / wall,
+                "latency_p50_s": float(np.percentile(lat, 50)),
+                "latency_p99_s": float(np.percentile(lat, 99)),
+                "latency_max_s": float(lat.max())}
+
+    log(f"serving: open loop, {n_req} requests at {rate}/s ...")
+    open_loop = run(reqs, 0, False)
+    log(f"serving: {open_loop}")
+    nb = max(1, n_req // 4)
+    log(f"serving: open loop, {nb} requests, {small_budget_mb} MB budget ...")
+    small = run(reqs[:nb], small_budget_mb << 20, False)
+    log(f"serving: {small}")
+    nc = max(1, n_req // 2)
+    log(f"serving: closed loop, {nc} requests ...")
+    closed = run(reqs[:nc], 0, True)
+    log(f"serving: {closed}")
+    # the plain single-scenario loop, one request after another
+    ctx = fast.Context(device=0, torch_alloc=False)
+    t_p = time.perf_counter()
+    for m in reqs[:plain_sample]:
+        h = ctx.init_from(m, tile="auto")
+        for _ in range(steps):
+            ctx.plan(h)
+            ctx.move(h)
+        ctx.state(h)
+        ctx.destroy(h)
+    plain_s = time.perf_counter() - t_p
+    ctx.close()
+    plain_rate = plain_sample / plain_s
+    return {
+        "workload": f"Poisson arrivals, mean {rate:g}/s, of ensemble-distribution scenarios "
+                    f"(ids 1000+k), {steps} steps each",
+        "open_loop": open_loop, "small_budget": dict(small, budget_mb=small_budget_mb),
+        "closed_loop": closed,
+        "plain_one_at_a_time_scenarios_per_s": plain_rate, "plain_sample": plain_sample,
+        "closed_over_plain": closed["scenarios_per_s"] / plain_rate,
+        "request_generation_s": gen_s,
+    }
+
+
 def cpu_baseline(budget_s: float = 15.0, max_steps: int = 396, v: int = 4):
     """The oracle as it stands: its OpenMP planning loop (paper Sec. 2
     schedule) on every host thread, sequential motion, on the room workload."""
@@ -229,6 +305,9 @@ def main():
     ap.add_argument("--room-replicas", type=int, default=0,
                     help="also time the planning launch over this many copies of the room")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests in the open-loop serving run (0 = no serving run)")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -287,6 +366,10 @@ def main():
         log(f"ensemble: {ens}")
     ctx.close()
 
+    serving = None
+    if args.serve_requests:
+        serving = bench_serving(fast, args.serve_requests, args.serve_rate)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline ...")
@@ -324,6 +407,7 @@ def main():
         "ensemble": ens,
         "large": large,
         "room_replicas": replicas,
+        "serving": serving,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in
                                                  ("value", "unit", "cores", "kind", "sample")},
     }

@@ -184,11 +184,14 @@ fast_status fast_debug_plan(fast_ctx *ctx, int32_t handle, float *w32, uint8_t *
 
 /* ---- Serving: continuous batching of scenario requests ------------------ */
 
-/* Starts the serving loop on a host thread of the context: requests are
- * admitted as slots while the device bytes stay within `budget` (0 = the
- * context's budget) and at most `max_active` scenarios run at once; each
- * batch step covers all admitted scenarios; finished ones are retired and
- * their results copied back. */
+/* Starts serving on host threads of the context.  Builder threads (half the
+ * host's hardware threads, 1..8) do each request's host setup as soon as it
+ * is submitted; the server thread admits built requests in submission order
+ * as slots while the device bytes stay within `budget` (0 = the context's
+ * budget) and at most `max_active` (0 = no cap) scenarios run at once, steps
+ * all admitted scenarios together with batched launches of up to 8 steps,
+ * retires finished ones and copies their results back.  A request that fits
+ * no budget even alone is rejected.  FAST_E_STATE if already serving. */
 fast_status fast_serve_start(fast_ctx *ctx, size_t budget, int32_t max_active);
 
 /* Queues a request for `steps` time steps of the scenario; returns a ticket.
@@ -204,7 +207,7 @@ fast_status fast_serve_poll(fast_ctx *ctx, uint64_t ticket, int32_t *done, doubl
 fast_status fast_serve_result(fast_ctx *ctx, uint64_t ticket, int32_t *xy, uint8_t *alive,
                               int32_t *step, int32_t *n_active);
 
-/* Stops admitting, finishes running requests, joins the thread. */
+/* Finishes every submitted request, then joins the serving threads. */
 fast_status fast_serve_stop(fast_ctx *ctx);
 
 /* ---- Host-only helpers (no device work) --------------------------------- */

@@ -47,31 +47,36 @@ struct Tree<1, O> {
     static __device__ __forceinline__ float sum(const float *x) { return x[O]; }
 };
 
-// Row r (dy = r - V) of the disc around the agent's LDS cell l: sum of the
-// masked exp values, the agent's own cell taking e_c.
-template <int V, int R>
-__device__ __forceinline__ float row_sum(const float *Em, int l, int LX, float ec)
+// Row R (dy = R - V) of the reach disc: its 2a+1 masked exp values, read
+// from Eb = the agent's window origin (row -V, column -V) with pitch P; the
+// agent's own cell takes e_c.
+template <int V, int P, int R>
+__device__ __forceinline__ void load_row(const float *Eb, float ec, float (&x)[2 * V + 1])
 {
-    constexpr int dy = R - V;
-    constexpr int a = half_width(V, dy);
-    float x[2 * a + 1];
+    constexpr int a = half_width(V, R - V);
 #pragma unroll
     for (int k = 0; k <= 2 * a; ++k) {
-        if (dy == 0 && k == a) x[k] = ec;
-        else x[k] = Em[l + dy * LX + (k - a)];
+        if (R == V && k == a) x[k] = ec;
+        else x[k] = Eb[R * P + (V - a) + k];
     }
-    return Tree<2 * a + 1, 0>::sum(x);
 }
 
-// Row sums one row at a time: the scheduling barrier keeps the loads of a row
-// from being hoisted above the previous row's sum, which bounds the live
-// registers to one row's values (occupancy hides the LDS latency instead).
-template <int V, int... R>
-__device__ __forceinline__ void all_rows(std::integer_sequence<int, R...>, float *Rs,
-                                         const float *Em, int l, int LX, float ec)
-{
-    ((Rs[R] = row_sum<V, R>(Em, l, LX, ec), __builtin_amdgcn_sched_barrier(0)), ...);
-}
+// Row sums, software-pipelined by one row: the loads of row R+1 are issued
+// before row R is summed, and the scheduling barrier keeps later rows from
+// being hoisted, so at most two rows of values are live.
+template <int V, int P, int R>
+struct RowPipe {
+    static __device__ __forceinline__ void run(const float *Eb, float ec, float *Rs,
+                                               const float (&cur)[2 * V + 1])
+    {
+        constexpr int a = half_width(V, R - V);
+        float nxt[2 * V + 1];
+        if constexpr (R + 1 < 2 * V + 1) load_row<V, P, R + 1>(Eb, ec, nxt);
+        Rs[R] = Tree<2 * a + 1, 0>::sum(cur);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (R + 1 < 2 * V + 1) RowPipe<V, P, R + 1>::run(Eb, ec, Rs, nxt);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // FP64 draw, the test oracle's arithmetic: weights exp(k_S (S(c) - S(t))) over
@@ -252,50 +257,62 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-template <int V, bool DEBUG>
+// Philox word 0 for the planning draw.  The empty asm marks the key as
+// rewritten on every call, so the ten round keys are formed by scalar adds at
+// the point of use instead of being kept live across the agent loop (twenty
+// scalar registers the kernel cannot spare).
+__device__ __forceinline__ uint32_t plan_draw_word(uint32_t id, uint32_t step, uint32_t scn,
+                                                   uint32_t k0, uint32_t k1)
+{
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    return philox_word0(id, step, scn, STREAM_PLAN, k0, k1);
+}
+
+// V = v_max, TX = tile width (a power of two, 8..64): both fix the LDS pitch,
+// so every window offset of the agent loop is a compile-time constant.
+template <int V, int TX, bool DEBUG>
 __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
 {
     constexpr int SIDE = 2 * V + 1;
+    constexpr int Hc = (V + 3) & ~3;                          // column halo, a multiple of 4 >= V
+    constexpr int P = TX + 2 * Hc;                            // LDS pitch = staged width
+    constexpr int cpr = P >> 2;                               // 4-cell chunks per row
+    constexpr int hc4 = Hc >> 2;
+    constexpr int cw = TX >> 2;                               // interior chunks per row
+    constexpr int cw_log = __builtin_ctz(cw);
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int lane = __lane_id();
-    const int Hc = s.pad;                                    // column halo, a multiple of 4 >= V
     const int LY = s.ty + 2 * V;
-    const int P = s.tx + 2 * Hc;                              // LDS pitch = staged width
-    const int cpr = P >> 2;                                   // 4-cell chunks per row
-    const int hc4 = Hc >> 2;
-    const int cw = s.tx >> 2;                                 // interior chunks per row (power of 2)
-    const int cw_log = __builtin_ctz(cw);
     const int n_in = cw * s.ty;                               // interior chunks (<= nthr)
     const int n_top = V * cpr;                                // halo chunks: V rows above / below,
     const int n_halo = 2 * n_top + s.ty * 2 * hc4;            // then hc4 chunks left and right
     const int tile_y = tile / s.ntx, tile_x = tile - tile_y * s.ntx;
-    const int gx0 = tile_x * s.tx, gy0 = tile_y * s.ty + Hc - V;   // padded origin of the window
+    const int gx0 = tile_x * TX, gy0 = tile_y * s.ty + Hc - V;     // padded origin of the window
     const int tstride = s.ntx + 2;
     const bool fallback = s.tile_fb[tile_y * s.ntx + tile_x] != 0;
 
     if (tid < 9) sh.m_nb[tid] = s.tile_m[(tile_y + tid / 3) * tstride + tile_x + tid % 3];
     if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; sh.n_mov = 0; }
-    MoveRec *seg = s.seg + (long)tile * (s.tx * s.ty);
+    MoveRec *seg = s.seg + (long)tile * (TX * s.ty);
 
     // --- stage the window: one interior chunk and up to two halo chunks per
     // thread, 16-byte loads of occupancy and exp table, all issued first
     const int ci = tid;
     const int ly_in = V + (ci >> cw_log), cc_in = hc4 + (ci & (cw - 1));
     int ly_h[2], cc_h[2];
-    const float inv_cpr = 1.0f / (float)cpr, inv_side = 1.0f / (float)(2 * hc4);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int h = tid + j * nthr;
         int ly, cc;
         if (h < 2 * n_top) {                                  // rows above, then rows below
             const int hh = h < n_top ? h : h - n_top;
-            ly = (int)(((float)hh + 0.5f) * inv_cpr);
+            ly = (int)((unsigned)hh / cpr);
             cc = hh - ly * cpr;
             if (h >= n_top) ly += V + s.ty;
         } else {                                              // left / right columns
             const int hh = h - 2 * n_top;
-            const int r = (int)(((float)hh + 0.5f) * inv_side);
+            const int r = (int)((unsigned)hh / (2 * hc4));
             const int c = hh - r * 2 * hc4;
             ly = V + r;
             cc = c < hc4 ? c : c + cw;
@@ -374,7 +391,8 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
     __syncthreads();
     const int na = sh.n_agents;
     const uint32_t kseed0 = s.seed_lo, kseed1 = s.seed_hi;
-    const float inv_P = 1.0f / (float)P;
+    const uint32_t scn = s.scn;          // held in registers: the loops below store to memory
+    const float eps = s.eps;
 
     if (fallback) {
         // every draw of this tile in FP64, one lane per agent
@@ -385,11 +403,11 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
             if (k < na) {
                 const int id = sh.a_pk[k] >> 12;
                 const int l = sh.a_pk[k] & 0xFFF;
-                const int ly = (int)(((float)l + 0.5f) * inv_P);
+                const int ly = (int)((unsigned)l / P);
                 const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
                 const int gc = cy * s.Wp + cx;
-                const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
-                                                 kseed0, kseed1);
+                const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0,
+                                                   kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
                 const int t = resolve64_lane<V, DEBUG>(s, gc, id, u);
                 mover = t != gc;
@@ -418,19 +436,24 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
             const int id = sh.a_pk[k] >> 12;
             const int l = sh.a_pk[k] & 0xFFF;
             const float ec = sh.a_ec[k];
-            const int ly = (int)(((float)l + 0.5f) * inv_P);
+            const int ly = (int)((unsigned)l / P);
             const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
 
-            float Rs[SIDE];
-            all_rows<V>(std::make_integer_sequence<int, SIDE>{}, Rs, sh.Em, l, P, ec);
+            const float *Eb = sh.Em + (l - V * P - V);      // window origin (dy, dx) = (-V, -V)
+            float Rs[SIDE], row0[SIDE];
+            load_row<V, P, 0>(Eb, ec, row0);
+            __builtin_amdgcn_sched_barrier(0);
+            // the draw's counter-based word overlaps the first row's LDS reads
+            const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0, kseed1);
+            __builtin_amdgcn_sched_barrier(0);
+            RowPipe<V, P, 0>::run(Eb, ec, Rs, row0);
             float Pr[SIDE + 1];
             Pr[0] = 0.0f;
+            Pr[1] = Rs[0];
 #pragma unroll
-            for (int r = 0; r < SIDE; ++r) Pr[r + 1] = Pr[r] + Rs[r];
+            for (int r = 1; r < SIDE; ++r) Pr[r + 1] = Pr[r] + Rs[r];
             const float Wsum = Pr[SIDE];
 
-            const uint32_t x0 = philox_word0((uint32_t)id, (uint32_t)step, s.scn, STREAM_PLAN,
-                                             kseed0, kseed1);
             const float u = (float)(x0 >> 8) * 0x1p-24f;
             const float tau = u * Wsum;
 
@@ -444,15 +467,20 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
                 Ps = le ? Pr[r] : Ps;
                 as = le ? half_width(V, r - V) : as;
             }
-            // slot within the row: count of in-row boundaries <= tau
-            const int rowbase = l + (rs - V) * P - as;
+            // slot within the row: count of in-row boundaries <= tau.  The
+            // row's cells are read at once (slots past 2a stay inside the
+            // LDS block and are not used).
+            const float *rb = Eb + rs * P + (V - as);
+            float rv[SIDE];
+#pragma unroll
+            for (int d = 0; d < SIDE; ++d) rv[d] = rb[d];
             float Q = 0.0f;
             float margin = fabsf(tau - Ps);
             int ks = 0;
 #pragma unroll
             for (int d = 0; d < SIDE; ++d) {
                 if (d <= 2 * as) {
-                    const float val = (rs == V && d == as) ? ec : sh.Em[rowbase + d];
+                    const float val = (rs == V && d == as) ? ec : rv[d];
                     Q = Q + val;
                     const float C = Ps + Q;
                     const float diff = tau - C;
@@ -460,7 +488,7 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
                     margin = fminf(margin, fabsf(diff));
                 }
             }
-            const bool flag = (margin <= s.eps * Wsum) || (ks > 2 * as);
+            const bool flag = (margin <= eps * Wsum) || (ks > 2 * as);
 
             if (DEBUG) {
                 if (s.dbg_w) {
@@ -496,11 +524,11 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
                 const int kk = base + (tid & ~63) + src;
                 const int fid = sh.a_pk[kk] >> 12;
                 const int l = sh.a_pk[kk] & 0xFFF;
-                const int ly = (int)(((float)l + 0.5f) * inv_P);
+                const int ly = (int)((unsigned)l / P);
                 const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
                 const int gc = cy * s.Wp + cx;
-                const uint32_t x0 = philox_word0((uint32_t)fid, (uint32_t)step, s.scn, STREAM_PLAN,
-                                                 kseed0, kseed1);
+                const uint32_t x0 = plan_draw_word((uint32_t)fid, (uint32_t)step, scn, kseed0,
+                                                   kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
                 const int t = resolve64_wave<V>(s, gc, u, lane, sh.Em, l, P);
                 if (lane == 0 && t != gc) {
@@ -520,15 +548,27 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
     }
 }
 
+template <int V, bool DEBUG>
+__device__ __forceinline__ void plan_dispatch_tx(const SlotDev &s, int tile, PlanShared &sh)
+{
+    switch (s.tx) {
+        case 8: plan_tile<V, 8, DEBUG>(s, tile, sh); break;
+        case 16: plan_tile<V, 16, DEBUG>(s, tile, sh); break;
+        case 32: plan_tile<V, 32, DEBUG>(s, tile, sh); break;
+        case 64: plan_tile<V, 64, DEBUG>(s, tile, sh); break;
+        default: break;
+    }
+}
+
 template <bool DEBUG>
 __device__ __forceinline__ void plan_dispatch(const SlotDev &s, int tile, PlanShared &sh)
 {
     switch (s.v) {
-        case 1: plan_tile<1, DEBUG>(s, tile, sh); break;
-        case 2: plan_tile<2, DEBUG>(s, tile, sh); break;
-        case 3: plan_tile<3, DEBUG>(s, tile, sh); break;
-        case 4: plan_tile<4, DEBUG>(s, tile, sh); break;
-        case 5: plan_tile<5, DEBUG>(s, tile, sh); break;
+        case 1: plan_dispatch_tx<1, DEBUG>(s, tile, sh); break;
+        case 2: plan_dispatch_tx<2, DEBUG>(s, tile, sh); break;
+        case 3: plan_dispatch_tx<3, DEBUG>(s, tile, sh); break;
+        case 4: plan_dispatch_tx<4, DEBUG>(s, tile, sh); break;
+        case 5: plan_dispatch_tx<5, DEBUG>(s, tile, sh); break;
         default: break;
     }
 }

@@ -84,6 +84,8 @@ struct Request {
     int steps = 0;
     double t_submit = 0, t_done = 0;
     int state = 0;               // 0 queued, 1 running, 2 done, -1 rejected
+    int built_state = 0;         // host build: 0 pending, 1 ready, -1 failed
+    std::unique_ptr<fh::Built> built;
     int32_t handle = -1;
     std::vector<int32_t> out_xy;
     std::vector<uint8_t> out_alive;
@@ -113,13 +115,16 @@ struct fast_ctx {
 
     // serving
     std::thread server;
+    std::vector<std::thread> builders;
     std::mutex smu;
-    std::condition_variable scv;
+    std::condition_variable scv;     // server: a request is built, or stop
+    std::condition_variable bcv;     // builders: a request is queued, or stop
     bool serving = false, stopping = false;
     size_t serve_budget = 0;
     int serve_max_active = 0;
     uint64_t next_ticket = 1;
-    std::deque<uint64_t> queue;
+    std::deque<uint64_t> queue;       // admission order
+    std::deque<uint64_t> build_queue; // awaiting their host build
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
 };
 
@@ -248,18 +253,25 @@ void drop_batches_with(fast_ctx *c, int32_t h)
 
 // Builds a scenario into a free slot; `limit` is the step at which its kernels
 // stop acting (INT_MAX for scenarios stepped by the caller).
-fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32_t *handle)
+// Host half of scenario setup: floor field, placement, exp table and tile
+// metadata.  Touches no device state, so the server runs it on builder threads.
+fast_status build_host(const fast_scenario_desc *d, fh::Built &b)
 {
     fast_status st = check_desc(d);
     if (st) return st;
     int tx = d->tile_w, ty = d->tile_h;
     if (!tx) choose_tile(d->width, d->height, d->v_max, &tx, &ty);
-
-    fh::Built b;
     std::string err;
     st = fh::build_scenario(*d, tx, ty, b, err);
     if (st) return fail(st, "%s", err.c_str());
+    return FAST_OK;
+}
 
+// Device half: one allocation for the slot, upload, descriptor table entry.
+fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Built &b, int limit,
+                        int32_t *handle)
+{
+    fast_status st = FAST_OK;
     int32_t h = -1;
     for (int32_t i = 0; i < (int32_t)c->slots.size(); ++i)
         if (!c->slots[i].live) { h = i; break; }
@@ -359,6 +371,14 @@ fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32
     s.n_agents = b.n;
     *handle = h;
     return FAST_OK;
+}
+
+fast_status init_slot(fast_ctx *c, const fast_scenario_desc *d, int limit, int32_t *handle)
+{
+    fh::Built b;
+    fast_status st = build_host(d, b);
+    if (st) return st;
+    return upload_slot(c, d, b, limit, handle);
 }
 
 fast_status destroy_slot(fast_ctx *c, int32_t h)
@@ -532,41 +552,79 @@ fast_status run_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
 }
 
 // ---------------------------------------------------------------------------
-// Serving: a host thread admits queued requests as slots while the budget and
-// the active cap allow, advances every active scenario by one batched step
-// per iteration, retires finished ones, and records completion times.
+// Serving.  Builder threads do each request's host setup (floor field,
+// placement, exp table) as soon as it is submitted; the server thread admits
+// built requests in arrival order while the budget and the active cap allow
+// (upload only), advances every active scenario with batched launches of up to
+// 8 steps, retires finished ones, and records completion times.
 // ---------------------------------------------------------------------------
+void build_loop(fast_ctx *c)
+{
+    for (;;) {
+        Request *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(c->smu);
+            c->bcv.wait(lk, [&] { return c->stopping || !c->build_queue.empty(); });
+            if (c->build_queue.empty()) return;                 // stopping, nothing left
+            r = c->reqs[c->build_queue.front()].get();
+            c->build_queue.pop_front();
+        }
+        std::unique_ptr<fh::Built> b(new fh::Built());
+        const fast_status st = build_host(&r->desc, *b);
+        {
+            std::lock_guard<std::mutex> lk(c->smu);
+            if (st) {
+                r->built_state = -1;
+            } else {
+                r->built = std::move(b);
+                r->built_state = 1;
+            }
+        }
+        c->scv.notify_all();
+    }
+}
+
 void serve_loop(fast_ctx *c)
 {
     std::vector<uint64_t> active;
+    auto head_ready = [&] {
+        return !c->queue.empty() && c->reqs[c->queue.front()]->built_state != 0;
+    };
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(c->smu);
             if (active.empty()) {
-                c->scv.wait(lk, [&] { return c->stopping || !c->queue.empty(); });
+                c->scv.wait(lk, [&] { return (c->stopping && c->queue.empty()) || head_ready(); });
                 if (c->stopping && c->queue.empty()) break;
             }
         }
-        // admit
+        // admit, in arrival order
         for (;;) {
             uint64_t t = 0;
             Request *r = nullptr;
             {
                 std::lock_guard<std::mutex> lk(c->smu);
-                if (c->queue.empty()) break;
+                if (!head_ready()) break;
                 if (c->serve_max_active && (int)active.size() >= c->serve_max_active) break;
                 t = c->queue.front();
                 r = c->reqs[t].get();
+                if (r->built_state < 0) {
+                    c->queue.pop_front();
+                    r->state = -1;
+                    r->t_done = now_s();
+                    continue;
+                }
             }
             std::lock_guard<std::recursive_mutex> g(c->mu);
             const size_t saved = c->budget;
             if (c->serve_budget) c->budget = c->serve_budget;
             int32_t h = -1;
-            fast_status st = init_slot(c, &r->desc, r->steps, &h);
+            fast_status st = upload_slot(c, &r->desc, *r->built, r->steps, &h);
             c->budget = saved;
             if (st == FAST_E_BUDGET && !active.empty()) break;      // wait for memory
             std::lock_guard<std::mutex> lk(c->smu);
             c->queue.pop_front();
+            r->built.reset();
             if (st) { r->state = -1; r->t_done = now_s(); continue; }
             r->handle = h;
             r->state = 1;
@@ -899,6 +957,9 @@ fast_status fast_serve_start(fast_ctx *c, size_t budget, int32_t max_active)
     c->stopping = false;
     c->serving = true;
     c->server = std::thread(serve_loop, c);
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nb = (int)std::max(1u, std::min(8u, hw / 2));
+    for (int i = 0; i < nb; ++i) c->builders.emplace_back(build_loop, c);
     return FAST_OK;
 }
 
@@ -923,8 +984,9 @@ fast_status fast_serve_submit(fast_ctx *c, const fast_scenario_desc *d, int32_t 
     r->ticket = c->next_ticket++;
     *ticket = r->ticket;
     c->queue.push_back(r->ticket);
+    c->build_queue.push_back(r->ticket);
     c->reqs[r->ticket] = std::move(r);
-    c->scv.notify_one();
+    c->bcv.notify_one();
     return FAST_OK;
 }
 
@@ -966,7 +1028,11 @@ fast_status fast_serve_stop(fast_ctx *c)
         if (!c->serving) return FAST_OK;
         c->stopping = true;
         c->scv.notify_all();
+        c->bcv.notify_all();
     }
+    for (auto &b : c->builders) b.join();
+    c->builders.clear();
+    c->scv.notify_all();
     if (c->server.joinable()) c->server.join();
     std::lock_guard<std::mutex> lk(c->smu);
     c->serving = false;

@@ -296,3 +296,43 @@ def test_batched_large_grid_sampled(ctx):
     sim.end_step()
     compare_state(ctx, sim, h, where="large step 0")
     ctx.destroy(h)
+
+
+def test_batched_ensemble_16_members_396_steps(ctx):
+    """Sixteen members of the 256-scenario ensemble (uneven grids, agent
+    counts and v_m) run together for the full 396 steps through the
+    graph-replayed batched step; each final state equals the oracle's run of
+    that scenario alone."""
+    picks = np.random.default_rng(16).choice(256, 16, replace=False)
+    members = [sc.ensemble_member(int(k)) for k in picks]
+    hs = [ctx.init_from(m, batched=True) for m in members]
+    ctx.run(hs, 396)
+    for m, h in zip(members, hs):
+        sim = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents)
+        sim.run(396)
+        compare_state(ctx, sim, h, where=m.name)
+        st = ctx.stats(h)
+        assert st["step"] == 396 and st["exited"] == sim.exited
+        ctx.destroy(h)
+    say("ensemble members", sorted(int(k) for k in picks))
+
+
+def test_large_grid_396_steps_bit_exact(ctx):
+    """One 1000 x 1000, 200,000-agent instance for the full 396 steps against
+    the oracle (its planning loop on all host threads), final state and the
+    exit count compared, positions also at steps 99 and 249."""
+    s = sc.large_member(1)
+    sim, h = make_pair(ctx, s)
+    cores = oracle.num_threads()
+    for step in range(396):
+        ctx.plan(h)
+        ctx.move(h)
+        sim.plan_omp(cores)
+        sim.move()
+        sim.end_step()
+        if step in (99, 249):
+            compare_state(ctx, sim, h, where=f"after step {step}")
+            say("large: step", step, "agents left", sim.n_alive())
+    compare_state(ctx, sim, h, where="after 396 steps")
+    assert ctx.stats(h)["exited"] == sim.exited
+    ctx.destroy(h)

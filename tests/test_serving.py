@@ -106,3 +106,28 @@ def test_submit_without_start_fails(fast_mod):
             ctx.serve_submit(m.cell_type, m.n_agents, m.v)
     finally:
         ctx.close()
+
+
+def test_unplaceable_request_is_rejected_and_others_finish(fast_mod):
+    """A request whose agents do not fit the grid fails in its host build; it is
+    reported as rejected and the requests around it still finish exactly."""
+    good = _requests(40, 3, 10)
+    bad = sc.corridor()
+    ctx = fast_mod.Context(device=0, torch_alloc=False)
+    try:
+        ctx.serve_start()
+        t0 = ctx.serve_submit(good[0][0].cell_type, good[0][0].n_agents, good[0][0].v,
+                              good[0][0].k_s, good[0][0].seed, good[0][0].scn, steps=10)
+        tb = ctx.serve_submit(bad.cell_type, 5000, bad.v, steps=10)   # corridor holds < 5000
+        rest = [ctx.serve_submit(m.cell_type, m.n_agents, m.v, m.k_s, m.seed, m.scn, steps=10)
+                for m, _ in good[1:]]
+        ctx.serve_stop()
+        with pytest.raises(fast_mod.FastError):
+            ctx.serve_poll(tb)
+        for t, (m, steps) in zip([t0] + rest, good):
+            done, _ = ctx.serve_poll(t)
+            assert done
+            xy, alive = _oracle_final(m, steps)
+            assert np.array_equal(ctx.serve_result(t)["xy"], xy), m.name
+    finally:
+        ctx.close()
