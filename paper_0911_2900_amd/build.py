@@ -19,7 +19,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["kernels.hip", "builder.cpp", "runtime.cpp"]
+SOURCES = ["plan_batch.hip", "plan_one.hip", "motion.hip", "builder.cpp", "runtime.cpp"]
 
 
 def _run(cmd):
@@ -30,22 +30,31 @@ def _run(cmd):
     return r
 
 
+def _compile_cmd(src: str):
+    path = os.path.join(CSRC, src)
+    obj = os.path.join(BUILD, src + ".o")
+    if src.endswith(".hip"):
+        cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, "-c", path, "-o", obj]
+    else:
+        cmd = [CLANGXX, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON,
+               "-c", path, "-o", obj]
+    return cmd, obj
+
+
 def build(verbose: bool = False) -> str:
-    """Compiles every source (always) and links paper_0911_2900_amd/libfast.so."""
+    """Compiles every source (always, in parallel) and links
+    paper_0911_2900_amd/libfast.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        obj = os.path.join(BUILD, src + ".o")
-        if src.endswith(".hip"):
-            cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, "-c", path, "-o", obj]
-        else:
-            cmd = [CLANGXX, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON,
-                   "-c", path, "-o", obj]
-        if verbose:
+    jobs = [_compile_cmd(src) for src in SOURCES]
+    if verbose:
+        for cmd, _ in jobs:
             print(" ".join(cmd), flush=True)
-        _run(cmd)
-        objs.append(obj)
+    workers = max(1, min(len(jobs), os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        list(pool.map(lambda j: _run(j[0]), jobs))
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)

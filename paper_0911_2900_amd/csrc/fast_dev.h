@@ -41,6 +41,7 @@ constexpr int MAX_STAGE = 2368;        // (tx + 2 pad) * (ty + 2v) over the allo
 constexpr int PLAN_THREADS = 256;
 constexpr int MOVE_THREADS = 1024;
 constexpr int MOVE_GROUP_MAX = 64;        // workgroups per scenario in the motion phase
+constexpr int MOVE_SOLO_MAX = 256;        // movers left at which one workgroup takes over
 constexpr int MOVE_AGENTS_PER_WG = 1024;  // group size = ceil(agents / this), capped
 constexpr uint32_t SPIN_LIMIT = 1u << 22; // bound on a group-barrier wait (never hangs)
 
@@ -62,15 +63,23 @@ enum : int {
     C_BAR = 12,      // 2 x uint64 (C_BAR..C_BAR+3): group-barrier words of even / odd
                      // rounds, [arrivals:32][movers left:32], zeroed by the plan kernel
     C_ERR = 10,      // nonzero: a group barrier timed out, the state is invalid
-    C_NCTR = 16
+    C_SOLO = 16,     // MOVE_GROUP_MAX entries: movers left per workgroup of the group
+    C_NCTR = 16 + 64
 };
 
 // A mover of the running motion phase: priority word and packed coordinates
 // (x | y << 16, padded) of its start and desired cells.
+// key: bits 0..51 the priority word [~x0:32][~id:20] (larger = earlier);
+// bits 52..54 the reach m_eff of the line; bits 55..59 flag the line cells
+// k = 1..5 that hold a higher-priority mover at the start of the phase; bit
+// 60 marks a line that ends on an exit; bit 61 marks a mover whose reach is
+// not known yet (m_eff is then the whole line).
 struct Mover {
     unsigned long long key;
     uint32_t cxy, dxy;
 };
+constexpr unsigned long long KEY_MASK = (1ull << 52) - 1ull;
+constexpr int MEFF_SHIFT = 52, HP_SHIFT = 55, EXIT_BIT = 60, RAW_BIT = 61;
 
 // A mover as planned: agent id and packed start / target cells.
 struct MoveRec {
@@ -90,12 +99,15 @@ struct SlotDev {
     uint32_t seed_lo, seed_hi, scn;
     float eps;               // guard band, relative to W
     double k_s;
+    double near64;           // FP64 re-resolve: scanned prefixes this close to tau (relative
+                             // to W) send the draw to the sequential sum
     const uint8_t *type;     // Wp*Hp
     const float *G;          // Wp*Hp
     const double *S;         // Wp*Hp
     const int32_t *tile_m;   // (ntx+2)*(nty+2), a ring of zeros around
     const uint8_t *tile_fb;  // ntx*nty
     int32_t *occ;            // Wp*Hp
+    unsigned long long *mcell;// Wp*Hp: (step + 1) << 32 | id at the start cell of each mover
     unsigned long long *res0;// Wp*Hp, reservations of even rounds
     unsigned long long *res1;// Wp*Hp, reservations of odd rounds
     int32_t *seg_cnt;        // ntx*nty: movers planned per tile

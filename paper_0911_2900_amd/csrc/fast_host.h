@@ -1,5 +1,6 @@
 // fast_host.h -- host-side pieces of libfast shared by builder.cpp and
-// runtime.cpp: the built scenario and the kernel launchers of kernels.hip.
+// runtime.cpp: the built scenario and the kernel launchers (plan_batch.hip,
+// plan_one.hip, motion.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,7 +38,7 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
 }  // namespace fh
 
 extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
-                                     int debug, hipStream_t stream);
+                                     hipStream_t stream);
 extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, int debug,
                                          hipStream_t stream);
 extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,

@@ -1,0 +1,481 @@
+// motion.hip -- the motion phase with the model's sequential semantics
+// (paper Sec. 1): agents walk their lines one by one in priority order.  It
+// runs as deterministic reservations on a group of workgroups per scenario.
+//
+// What an agent A can meet on its line is decided once per phase: a wall or
+// a cut wall corner ends the line; so does the start cell of a mover of lower
+// priority (it is still there when A's turn comes) and any other occupied
+// cell (an agent that does not move this step, or a committed mover that has
+// arrived: occupants of cells other than start cells never leave); the start
+// cell of a higher-priority mover B stays open (B may leave first).  The line
+// up to that point, cells 0..m_eff, is A's reach.  Start cells are stamped in
+// mcell when the movers are gathered; the reach is formed at a mover's first
+// check, after the first group barrier has made every stamp visible, so its
+// first reservation covers the whole line (a superset of the reach, which
+// can only delay a commit).
+//
+// Every round each pending mover reserves its reach with atomicMax of its
+// priority word.  A mover commits once it holds every reach cell it can still
+// enter: cells 1..j, where cell j + 1 is the first cell (other than a
+// higher-priority mover's start) that has become occupied, necessarily by a
+// committed mover that stays there.  Its own start cell need not be held:
+// a higher-priority mover whose line crosses it stops short of it anyway.
+// A committed mover walks cells 1..j and stops before the first occupied one
+// (a higher-priority mover that stayed) or leaves at an exit.  Two movers
+// commit in the same round only if neither can affect the other's walk, and
+// each mover commits only after every higher-priority mover that can, so the
+// result equals moving them one by one in priority order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fast_dev.h"
+
+namespace fk {
+
+// ---------------------------------------------------------------------------
+// Motion kernel: deterministic reservations.  The movers of a scenario are
+// split over a group of G workgroups; each keeps its share in a private list.
+// Round r reserves into res[r & 1] with tag r (tags grow, so stale words of
+// earlier rounds always lose), so the checks of round r and the reservations
+// of round r + 1 never touch the same array and one group barrier per round
+// suffices:
+//     reserve r+1 (own losers) | count | barrier | check r+1, commit, ...
+// Most movers commit in the first rounds; the long tail of rounds has few
+// movers and its cost is the latency of the group barrier.  Once at most
+// MOVE_SOLO_MAX movers are left, workgroup 0 gathers every workgroup's list
+// and runs the remaining rounds alone, with workgroup barriers only.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int isgn(int a) { return (a > 0) - (a < 0); }
+
+__device__ __forceinline__ int ld_agent(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(int32_t *p, int v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_res(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Cells of the DDA line from (cx, cy) towards (cx + dx, cy + dy):
+// p_k = (cx + sgn dx floor((2k|dx| + m) / 2m), cy + sgn dy floor((2k|dy| + m) / 2m)),
+// k = 0..m, m = max(|dx|, |dy|) <= v.
+// (The quotients have numerators <= 2 v^2 + v = 55 and denominators 2m <= 10:
+// n / 2m is an integer or at least 0.1 below the next one, so the FP32
+// product with 1 / 2m plus 0.05, truncated, is the exact floor.)
+struct Line {
+    int cx, cy, sx, sy, adx, ady, m;
+    float inv2m;
+    __device__ __forceinline__ void at(int k, int &x, int &y) const
+    {
+        x = cx + sx * (int)((float)(2 * k * adx + m) * inv2m + 0.05f);
+        y = cy + sy * (int)((float)(2 * k * ady + m) * inv2m + 0.05f);
+    }
+};
+
+__device__ __forceinline__ Line make_line(uint32_t cxy, uint32_t dxy)
+{
+    Line L;
+    L.cx = (int)(cxy & 0xFFFFu);
+    L.cy = (int)(cxy >> 16);
+    const int dx = (int)(dxy & 0xFFFFu) - L.cx, dy = (int)(dxy >> 16) - L.cy;
+    L.sx = isgn(dx);
+    L.sy = isgn(dy);
+    L.adx = abs(dx);
+    L.ady = abs(dy);
+    L.m = max(L.adx, L.ady);
+    L.inv2m = 0.5f / (float)max(L.m, 1);
+    return L;
+}
+
+// Barrier of the G workgroups of one scenario that also sums their mover
+// counts.  Round r uses the 64-bit word bar[r & 1] = [arrivals:32][count:32]
+// (both zeroed by the planning kernel): each workgroup adds (1 << 32) | n and
+// waits until the arrivals reach (r / 2 + 1) * G.  A word is touched again only
+// two barriers later, after every workgroup has read it, so the count part
+// minus its value at the previous barrier of the same parity is this round's
+// total.  All data shared between the workgroups moves through agent-scope
+// atomics; the fences of thread 0 order them around the arrival.  A wait
+// longer than SPIN_LIMIT polls marks the scenario as failed (C_ERR) instead of
+// hanging; the function then returns -1.
+__device__ int group_sync_count(const SlotDev &s, int G, int r, int n, unsigned long long &seen0,
+                                unsigned long long &seen1)
+{
+    __shared__ int sh_total;
+    __syncthreads();
+    if (G == 1) return n;
+    if (threadIdx.x == 0) {
+        unsigned long long *bar = (unsigned long long *)&s.ctr[C_BAR] + (r & 1);
+        unsigned long long &seen = (r & 1) ? seen1 : seen0;
+        __threadfence();
+        atomicAdd(bar, (1ull << 32) | (unsigned long long)(uint32_t)n);
+        const unsigned long long target = (unsigned long long)(r / 2 + 1) * (unsigned long long)G;
+        uint32_t spins = 0;
+        unsigned long long w;
+        int total = -1;
+        for (;;) {
+            w = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((w >> 32) >= target) { total = (int)((uint32_t)w - (uint32_t)seen); seen = w; break; }
+            if (++spins > SPIN_LIMIT) { atomicOr(&s.ctr[C_ERR], 1); break; }
+        }
+        __threadfence();
+        sh_total = total;
+    }
+    __syncthreads();
+    return sh_total;
+}
+
+__device__ __forceinline__ int mover_reach(unsigned long long key)
+{
+    return (int)((key >> MEFF_SHIFT) & 7ull);
+}
+
+template <int V>
+__device__ __forceinline__ void reserve_list(const SlotDev &s, unsigned long long *res,
+                                             const Mover *list, int n, unsigned long long tagw)
+{
+    const int Wp = s.Wp;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const Mover mv = list[i];
+        const Line L = make_line(mv.cxy, mv.dxy);
+        const int me = mover_reach(mv.key);
+        const unsigned long long word = (mv.key & KEY_MASK) | tagw;
+#pragma unroll
+        for (int k = 0; k <= V; ++k) {
+            if (k <= me) {
+                int x, y;
+                L.at(k, x, y);
+                atomicMax(&res[y * Wp + x], word);
+            }
+        }
+    }
+}
+
+// Priority word [~x0:32][~id:20] of agent id in this step's motion order.
+__device__ __forceinline__ unsigned long long order_key(const SlotDev &s, uint32_t id, int step)
+{
+    const uint32_t x0 = philox_word0(id, (uint32_t)step, s.scn, STREAM_ORDER, s.seed_lo, s.seed_hi);
+    return ((unsigned long long)(~x0) << ID_BITS) | (unsigned long long)(~id & ID_MASK);
+}
+
+// The reach of a mover (see the protocol above), from the static cell types,
+// the start-cell stamps of this step and the current occupancy: returns the
+// m_eff, higher-priority-cell and exit bits of its key.
+template <int V>
+__device__ unsigned long long line_reach(const SlotDev &s, const Mover &mv, int step)
+{
+    const Line L = make_line(mv.cxy, mv.dxy);
+    const int Wp = s.Wp;
+    const unsigned long long self = mv.key & KEY_MASK;
+    const uint32_t stamp = (uint32_t)step + 1u;
+    // two memory round trips: the cell types first (walls and cut corners
+    // bound the line), then stamps and occupancy of the cells before that
+    int q[V + 1];
+    uint32_t wallm = 0, exitm = 0;               // bit k: cell k is a wall or cut corner / an exit
+    int px = L.cx, py = L.cy;
+#pragma unroll
+    for (int k = 1; k <= V; ++k) {
+        int qx = px, qy = py;
+        if (k <= L.m) L.at(k, qx, qy);
+        q[k] = qy * Wp + qx;
+        const uint8_t t = k <= L.m ? s.type[q[k]] : (uint8_t)CELL_WALL;
+        const bool diag = qx != px && qy != py;
+        const uint8_t ta = diag ? s.type[py * Wp + qx] : (uint8_t)0;
+        const uint8_t tb = diag ? s.type[qy * Wp + px] : (uint8_t)0;
+        wallm |= (t == CELL_WALL || ta == CELL_WALL || tb == CELL_WALL) ? 1u << k : 0u;
+        exitm |= t == CELL_EXIT ? 1u << k : 0u;
+        px = qx;
+        py = qy;
+    }
+    const int first_wall = __builtin_ctz(wallm | (1u << (V + 1)));   // V + 1: none
+    const int ms = min(first_wall - 1, L.m);
+    unsigned long long e[V + 1];
+    int o[V + 1];
+#pragma unroll
+    for (int k = 1; k <= V; ++k) {
+        e[k] = k <= ms ? __hip_atomic_load(&s.mcell[q[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : 0ull;
+        o[k] = k <= ms ? ld_agent(&s.occ[q[k]]) : -1;
+    }
+    int me = ms;
+    uint32_t hp = 0;
+    bool ex = false;
+#pragma unroll
+    for (int k = 1; k <= V; ++k) {
+        if (k > ms) break;
+        if ((uint32_t)(e[k] >> 32) == stamp) {
+            if (order_key(s, (uint32_t)e[k], step) > self) {
+                hp |= 1u << (k - 1);                // a higher-priority mover: may leave first
+                continue;
+            }
+            me = k - 1;                             // still there at this mover's turn
+            break;
+        }
+        if (o[k] >= 0) {
+            me = k - 1;                             // an occupant that never leaves
+            break;
+        }
+        if ((exitm >> k) & 1u) {
+            me = k;
+            ex = true;
+            break;
+        }
+    }
+    return ((unsigned long long)me << MEFF_SHIFT) | ((unsigned long long)hp << HP_SHIFT) |
+           (ex ? (1ull << EXIT_BIT) : 0ull);
+}
+
+// Check-and-commit for the workgroup's list (see the protocol above); movers
+// that cannot commit yet are appended to `nxt`.  Returns the number appended.
+template <int V>
+__device__ int commit_list(const SlotDev &s, const unsigned long long *res, Mover *cur,
+                           Mover *nxt, int n, unsigned long long tagw, int step, bool first)
+{
+    __shared__ int sh_cnt;
+    const int Wp = s.Wp;
+    if (threadIdx.x == 0) sh_cnt = 0;
+    if (first) {
+        // the reach of every mover, in a pass of its own (its loads and the
+        // check's would not fit the registers together)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const Mover mv = cur[i];
+            cur[i].key = (mv.key & KEY_MASK) | line_reach<V>(s, mv, step);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const Mover mv = cur[i];
+        const Line L = make_line(mv.cxy, mv.dxy);
+        const int me = mover_reach(mv.key);
+        const uint32_t hp = (uint32_t)(mv.key >> HP_SHIFT) & 0x1Fu;
+        const unsigned long long word = (mv.key & KEY_MASK) | tagw;
+        int cell[V + 1];
+        unsigned long long w[V + 1];
+        int o[V + 1];
+#pragma unroll
+        for (int k = 0; k <= V; ++k) {
+            int x = L.cx, y = L.cy;
+            if (k <= me) L.at(k, x, y);
+            cell[k] = y * Wp + x;
+            w[k] = (k >= 1 && k <= me) ? ld_res(&res[cell[k]]) : word;
+            o[k] = (k >= 1 && k <= me) ? ld_agent(&s.occ[cell[k]]) : -1;
+        }
+        // j: the reach cells still enterable; the mover must hold all of them
+        int j = me;
+#pragma unroll
+        for (int k = V; k >= 1; --k)
+            if (k <= me && o[k] >= 0 && !((hp >> (k - 1)) & 1u)) j = k - 1;
+        bool holds = true;
+#pragma unroll
+        for (int k = 1; k <= V; ++k) holds &= (k > j) || (w[k] == word);
+        if (!holds) {
+            nxt[atomicAdd(&sh_cnt, 1)] = mv;
+            continue;
+        }
+        const int id = (int)(~(uint32_t)mv.key & ID_MASK);
+        const int c = cell[0];
+        int at = c, reached = 0;
+#pragma unroll
+        for (int k = 1; k <= V; ++k) {
+            if (k > j || o[k] >= 0) break;
+            at = cell[k];
+            reached = k;
+        }
+        const bool gone = reached == me && me > 0 && ((mv.key >> EXIT_BIT) & 1ull);
+        if (gone) {
+            st_agent(&s.occ[c], -1);
+            atomicAdd(&s.ctr[C_EXITED], 1);
+            atomicSub(&s.ctr[C_NACTIVE], 1);
+        } else if (at != c) {
+            st_agent(&s.occ[c], -1);
+            st_agent(&s.occ[at], id);
+        }
+    }
+    __syncthreads();
+    return sh_cnt;
+}
+
+// Workgroup 0 gathers the movers left in every workgroup's list (lists in
+// `from`, laid out as in move_group, counts in ctr[C_SOLO + g]) into `to`,
+// starting at 0.  Other workgroups wrote them before the last group barrier,
+// so they are read with agent-scope loads.  Returns the count.
+__device__ int gather_lists(const SlotDev &s, int G, const Mover *from, Mover *to, int *sh_scan)
+{
+    const int tid = threadIdx.x;
+    const int T = s.ntx * s.nty, TC = s.tx * s.ty;
+    const int q = T / G, rm = T % G;
+    if (tid < G) sh_scan[tid] = ld_agent(&s.ctr[C_SOLO + tid]);
+    __syncthreads();
+    if (tid == 0)
+        for (int k = 1; k < G; ++k) sh_scan[k] += sh_scan[k - 1];
+    __syncthreads();
+    const int total = sh_scan[G - 1];
+    for (int i = tid; i < total; i += blockDim.x) {
+        int a = 0, b = G - 1;                       // first list whose inclusive count exceeds i
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (sh_scan[mid] > i) b = mid; else a = mid + 1;
+        }
+        const int k = i - (a ? sh_scan[a - 1] : 0);
+        const Mover *src = from + ((long)a * q + min(a, rm)) * TC + k;
+        Mover mv;
+        mv.key = __hip_atomic_load(&src->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        mv.cxy = __hip_atomic_load(&src->cxy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        mv.dxy = __hip_atomic_load(&src->dxy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        to[i] = mv;
+    }
+    __syncthreads();
+    return total;
+}
+
+template <int V>
+__device__ void move_group(const SlotDev &s, int g, int G, int step)
+{
+    __shared__ int sh_scan[MOVE_THREADS];
+    const int tid = threadIdx.x;
+    const int T = s.ntx * s.nty, TC = s.tx * s.ty;
+    // workgroup g takes tiles g, g + G, g + 2G, ...: every region of the grid
+    // (the congested exit above all) is spread over the whole group, so the
+    // rounds stay balanced; its mover lists own tiles' worth of room
+    const int q = T / G, rm = T % G;
+    const int nt_g = q + (g < rm ? 1 : 0);
+    const long base_g = ((long)g * q + min(g, rm)) * TC;
+    Mover *cur = s.mv_a + base_g, *nxt = s.mv_b + base_g;
+    unsigned long long seen0 = 0, seen1 = 0;
+    uint32_t tag = (uint32_t)s.ctr[C_TAG];
+    if (g == 0 && tid == 0)   // agents planned this step, for the throughput counters
+        atomicAdd(&s.stat[S_PLANNED], (unsigned long long)s.ctr[C_NACTIVE]);
+
+    // gather this workgroup's movers (the records of its tiles) with their
+    // priority words [~x0:32][~id:20] (larger = earlier)
+    int n = 0;
+    for (int j0 = 0; j0 < nt_g; j0 += MOVE_THREADS) {
+        const int nt = min(MOVE_THREADS, nt_g - j0);
+        sh_scan[tid] = tid < nt ? s.seg_cnt[g + (long)(j0 + tid) * G] : 0;
+        __syncthreads();
+        for (int off = 1; off < MOVE_THREADS; off <<= 1) {
+            const int add = tid >= off ? sh_scan[tid - off] : 0;
+            __syncthreads();
+            sh_scan[tid] += add;
+            __syncthreads();
+        }
+        const int chunk = sh_scan[MOVE_THREADS - 1];
+        for (int i = tid; i < chunk; i += blockDim.x) {
+            int a = 0, b = nt - 1;                   // first tile whose inclusive count exceeds i
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (sh_scan[mid] > i) b = mid; else a = mid + 1;
+            }
+            const int k = i - (a ? sh_scan[a - 1] : 0);
+            const MoveRec rec = s.seg[(g + (long)(j0 + a) * G) * TC + k];
+            Mover mv;
+            mv.key = order_key(s, rec.id, step);
+            mv.cxy = rec.cxy;
+            mv.dxy = rec.dxy;
+            const Line L = make_line(rec.cxy, rec.dxy);
+            mv.key |= ((unsigned long long)L.m << MEFF_SHIFT) | (1ull << RAW_BIT);
+            __hip_atomic_store(&s.mcell[L.cy * s.Wp + L.cx],
+                               ((unsigned long long)(step + 1) << 32) | rec.id, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            cur[n + i] = mv;
+        }
+        n += chunk;
+        __syncthreads();
+    }
+
+    int total = 1, rounds = 0, bar_r = 0;          // round 0's total comes from its barrier
+    int Gr = G;                                    // workgroups still in the phase
+    for (int r = 0; total > 0; ++r) {
+        unsigned long long *res = (r & 1) ? s.res1 : s.res0;
+        if (r > 0) {
+            // round r's movers are the losers of round r - 1 (this workgroup's share)
+            n = commit_list<V>(s, (r & 1) ? s.res0 : s.res1, cur, nxt, n,
+                               (unsigned long long)tag << TAG_SHIFT, step, r == 1);
+            Mover *t = cur; cur = nxt; nxt = t;
+        }
+        if (tag >= TAG_LIMIT) {
+            // tags are exhausted: once every check of the last round is done,
+            // wipe both reservation arrays and restart the tags at 1
+            if (group_sync_count(s, Gr, bar_r++, 0, seen0, seen1) < 0) return;
+            const long cells = (long)s.Wp * s.Hp;
+            for (long i = cells * g / Gr + tid; i < cells * (g + 1) / Gr; i += blockDim.x) {
+                __hip_atomic_store(&s.res0[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&s.res1[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            tag = 0;
+            if (group_sync_count(s, Gr, bar_r++, 0, seen0, seen1) < 0) return;
+        }
+        ++tag;
+        reserve_list<V>(s, res, cur, n, (unsigned long long)tag << TAG_SHIFT);
+        if (Gr > 1 && tid == 0) st_agent(&s.ctr[C_SOLO + g], n);
+        total = group_sync_count(s, Gr, bar_r++, n, seen0, seen1);
+        if (total < 0) return;
+        rounds += total > 0 ? 1 : 0;
+        if (Gr > 1 && total > 0 && total <= MOVE_SOLO_MAX) {
+            // the same decision in every workgroup (total is the group's sum)
+            if (g != 0) return;
+            const bool in_a = cur == s.mv_a;           // workgroup 0's lists start at offset 0
+            Mover *from = in_a ? s.mv_a : s.mv_b, *to = in_a ? s.mv_b : s.mv_a;
+            n = gather_lists(s, G, from, to, sh_scan);
+            cur = to;
+            nxt = from;
+            Gr = 1;
+        }
+    }
+    if (g == 0 && tid == 0) {
+        s.ctr[C_TAG] = (int)tag;
+        s.ctr[C_ROUNDS] = rounds;
+        s.ctr[C_STEP] = step + 1;
+    }
+}
+
+// mitems[i] = slot | g << 12 | (G - 1) << 22: workgroup g of the G that move
+// the slot's agents.
+__global__ __launch_bounds__(MOVE_THREADS) void move_kernel(const SlotDev *__restrict__ table,
+                                                            const uint32_t *__restrict__ mitems)
+{
+    const uint32_t it = mitems[blockIdx.x];
+    const SlotDev &s = table[it & 0xFFFu];
+    const int g = (int)((it >> 12) & 0x3FFu);
+    const int G = (int)(it >> 22) + 1;
+    const int step = s.ctr[C_STEP];
+    if (step >= s.ctr[C_LIMIT]) return;
+    switch (s.v) {
+        case 1: move_group<1>(s, g, G, step); break;
+        case 2: move_group<2>(s, g, G, step); break;
+        case 3: move_group<3>(s, g, G, step); break;
+        case 4: move_group<4>(s, g, G, step); break;
+        case 5: move_group<5>(s, g, G, step); break;
+        default: break;
+    }
+}
+
+}  // namespace fk
+
+extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,
+                                     hipStream_t stream)
+{
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fk::move_kernel, dim3(n_items), dim3(fk::MOVE_THREADS), 0, stream, table,
+                       mitems);
+    return hipGetLastError();
+}
+
+// Workgroups of move_kernel that one device holds at once.
+extern "C" hipError_t fk_move_capacity(int *blocks)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fk::move_kernel,
+                                                                fk::MOVE_THREADS, 0);
+    if (e != hipSuccess) return e;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *blocks = per_cu * cus;
+    return hipSuccess;
+}
+

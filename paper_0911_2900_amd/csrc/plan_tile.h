@@ -1,23 +1,15 @@
-// kernels.hip -- gfx950 kernels of the F.A.S.T. time step.
+// plan_tile.h -- device code of the planning phase (choose_desired_cell for
+// every agent, paper Sec. 1 and Sec. 2), shared by the planning kernels.
 //
-//   plan_kernel   the planning phase, choose_desired_cell for every agent
-//                 (paper Sec. 1 and Sec. 2): one workgroup per grid tile; the
-//                 tile's (tx+2v) x (ty+2v) window of the exp table, masked by
-//                 the occupancy snapshot, is staged in LDS; agents are found
-//                 by scanning the tile's occupancy; one lane per agent forms
-//                 the weights, the CDF over the reach disc, and the Philox
-//                 draw in FP32; draws inside the guard band are re-resolved
-//                 in FP64 by a whole wavefront.  The tile's movers are written
-//                 as (id, start, target) records to the tile's own segment.
-//   move_kernel   the motion phase with the model's sequential semantics
-//                 (Sec. 1), run as deterministic reservations: one workgroup
-//                 per scenario; every round each pending agent reserves its
-//                 path cells with atomicMax of its priority word, and the
-//                 agents holding all their cells move.  Agents that commit in
-//                 one round have disjoint paths and commute, and an agent
-//                 only moves once every earlier agent sharing a cell with it
-//                 has moved, so the result equals moving them one by one in
-//                 priority order.
+// One workgroup plans one grid tile: the tile's (tx + 2 round4(v)) x (ty + 2v)
+// window of the exp table, masked by the occupancy snapshot, is staged in
+// LDS; the tile's agents are found by scanning its occupancy; one lane per
+// agent forms the weights, the CDF over the reach disc and the Philox draw in
+// FP32; draws inside the guard band are re-resolved in FP64 by a whole
+// wavefront.  The tile's movers are written as (id, start, target) records to
+// the tile's own segment.
+#pragma once
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -128,16 +120,7 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
     return gc;   // not reached: the own cell has weight 1 and tau < W
 }
 
-// The same draw by a whole wavefront: lane j evaluates raster slots j and
-// j + 64 of the square window; the prefix sum is still taken sequentially,
-// slot by slot, in raster order, so the result is bit-identical to
-// resolve64_lane (slots outside the reach set add nothing).
-// Reachability is read from the tile's staged window (Em, agent cell l, pitch
-// P): on a fast tile a cell is zero there exactly when it is a wall, padding
-// or occupied, so only the floor field needs global reads.  For v <= 4 the
-// reach disc has at most 49 slots: lane j takes the j-th disc slot in raster
-// order and the sequential sum runs over the disc only (the slots it skips add
-// nothing in the raster-order sum); v = 5 uses the square window.
+// Number of slots of the reach disc (5, 13, 29, 49, 81 for v = 1..5).
 constexpr int disc_count(int V)
 {
     int n = 0;
@@ -162,30 +145,89 @@ __device__ __forceinline__ void disc_slot(int j, int &dx, int &dy)
     }
 }
 
-template <int V>
-__device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, const float *Em,
-                              int l, int P)
+// Inclusive prefix sum over the 64 lanes of a wavefront in FP64 with DPP
+// moves: row shifts by 1, 2, 4, 8 within each 16-lane row, then the row
+// broadcasts of lanes 15 and 31.  Every prefix is a sum of depth <= 6.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_take(double x)
 {
-    const double Sc = s.S[gc];
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_scan64(double x)
+{
+    x = x + dpp_take<0x111, 0xF>(x);      // row_shr:1
+    x = x + dpp_take<0x112, 0xF>(x);      // row_shr:2
+    x = x + dpp_take<0x114, 0xF>(x);      // row_shr:4
+    x = x + dpp_take<0x118, 0xF>(x);      // row_shr:8
+    x = x + dpp_take<0x142, 0xA>(x);      // row_bcast:15 into rows 1, 3
+    x = x + dpp_take<0x143, 0xC>(x);      // row_bcast:31 into rows 2, 3
+    return x;
+}
+
+__device__ __forceinline__ double lane_value(double x, int j)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), j),
+                            __builtin_amdgcn_readlane(__double2loint(x), j));
+}
+
+// The same draw by a whole wavefront: lane j takes the j-th slot of the reach
+// disc in raster order (v <= 4: at most 49 slots) or raster slots j and j + 64
+// of the square window (v = 5), and evaluates its weight.
+//
+// The oracle sums the weights sequentially; a wavefront scan rounds
+// differently, but for n <= 128 non-negative terms every scanned prefix and
+// W lie within (gamma_n + gamma_7) W < 1.5e-14 W of the sequential ones, and
+// tau within that plus two roundings.  So when no prefix lies within
+// s.near64 W = 1e-12 W of tau (a 30-fold margin), every comparison tau < C_j,
+// and with it the chosen slot, is the same as in the sequential sum;
+// otherwise the prefix is rebuilt strictly sequentially, slot by slot (slots
+// outside the reach set add exactly nothing), which is bit-identical to
+// resolve64_lane.
+//
+// Reachability is read from the tile's staged window (Em, agent cell l, pitch
+// P): on a fast tile a cell is zero there exactly when it is a wall, padding
+// or occupied, so only the floor field needs reads: from LDS with SS (Sw, the
+// same layout as Em), else from global memory.
+template <int V, bool SS>
+__device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, const float *Em,
+                              const double *Sw, int l, int P)
+{
+    const double NEAR = s.near64;
+    auto S_at = [&](int dx, int dy) -> double {
+        if constexpr (SS) return Sw[l + dy * P + dx];
+        else return s.S[gc + dy * s.Wp + dx];
+    };
+    const double Sc = S_at(0, 0);
     const double ks = s.k_s;
+    const double u = (double)u32;
     if constexpr (disc_count(V) <= 64) {
         constexpr int ND = disc_count(V);
         double w = 0.0;
         int dx = 0, dy = 0;
         disc_slot<V>(lane, dx, dy);
         if (lane < ND && ((dx == 0 && dy == 0) || Em[l + dy * P + dx] != 0.0f))
-            w = exp(ks * (Sc - s.S[gc + dy * s.Wp + dx]));
-        double C = 0.0, myC = 0.0;
+            w = exp(ks * (Sc - S_at(dx, dy)));
+        const double Cp = wave_scan64(w);
+        const double Wp = lane_value(Cp, ND - 1);
+        const double tp = u * Wp;
+        const bool in = lane < ND;
+        unsigned long long m;
+        if (__ballot(in && fabs(tp - Cp) <= NEAR * Wp) == 0) {
+            m = __ballot(in && tp < Cp);
+        } else {
+            double C = 0.0, myC = 0.0;
 #pragma unroll
-        for (int j = 0; j < ND; ++j) {
-            const int lo = __builtin_amdgcn_readlane(__double2loint(w), j);
-            const int hi = __builtin_amdgcn_readlane(__double2hiint(w), j);
-            C = C + __hiloint2double(hi, lo);
-            if (lane == j) myC = C;
+            for (int j = 0; j < ND; ++j) {
+                C = C + lane_value(w, j);
+                if (lane == j) myC = C;
+            }
+            const double tau = u * C;
+            m = __ballot(in && tau < myC);
         }
-        const double tau = (double)u32 * C;
-        const unsigned long long m = __ballot(lane < ND && tau < myC);
-        const int jw = m ? __builtin_ctzll(m) : V * 0 + (ND - 1) / 2;   // own cell if unreached
+        const int jw = m ? __builtin_ctzll(m) : (ND - 1) / 2;   // own cell if unreached
         int wx, wy;
         disc_slot<V>(jw, wx, wy);
         return gc + wy * s.Wp + wx;
@@ -200,22 +242,30 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
                 const int dy = j / SIDE - V, dx = j % SIDE - V;
                 const bool own = dx == 0 && dy == 0;
                 if (dx * dx + dy * dy <= V * V && (own || Em[l + dy * P + dx] != 0.0f))
-                    w[h] = exp(ks * (Sc - s.S[gc + dy * s.Wp + dx]));
+                    w[h] = exp(ks * (Sc - S_at(dx, dy)));
             }
         }
-        double C = 0.0, myC0 = 0.0, myC1 = 0.0;
+        const double C0 = wave_scan64(w[0]);
+        const double C1 = wave_scan64(w[1]) + lane_value(C0, 63);
+        const double Wp = lane_value(C1, NS - 65);
+        const double tp = u * Wp;
+        const bool in1 = lane + 64 < NS;
+        unsigned long long m0, m1;
+        if (__ballot(fabs(tp - C0) <= NEAR * Wp || (in1 && fabs(tp - C1) <= NEAR * Wp)) == 0) {
+            m0 = __ballot(tp < C0);
+            m1 = __ballot(in1 && tp < C1);
+        } else {
+            double C = 0.0, myC0 = 0.0, myC1 = 0.0;
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            const double wj = w[j / 64];
-            const int lo = __builtin_amdgcn_readlane(__double2loint(wj), j % 64);
-            const int hi = __builtin_amdgcn_readlane(__double2hiint(wj), j % 64);
-            C = C + __hiloint2double(hi, lo);
-            if (j < 64) { if (lane == j) myC0 = C; }
-            else { if (lane == j - 64) myC1 = C; }
+            for (int j = 0; j < NS; ++j) {
+                C = C + lane_value(w[j / 64], j % 64);
+                if (j < 64) { if (lane == j) myC0 = C; }
+                else { if (lane == j - 64) myC1 = C; }
+            }
+            const double tau = u * C;
+            m0 = __ballot(tau < myC0);
+            m1 = __ballot(in1 && tau < myC1);
         }
-        const double tau = (double)u32 * C;
-        const unsigned long long m0 = __ballot(lane < NS && tau < myC0);
-        const unsigned long long m1 = __ballot(lane + 64 < NS && tau < myC1);
         int j;
         if (m0) j = __builtin_ctzll(m0);
         else if (m1) j = 64 + __builtin_ctzll(m1);
@@ -227,17 +277,23 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
 // ---------------------------------------------------------------------------
 // Planning kernel.
 // ---------------------------------------------------------------------------
-struct PlanShared {
-    alignas(16) float Em[MAX_STAGE];    // masked exp table window, pitch P = round4(tx + 2v)
+struct PlanSharedBase {
+    alignas(16) float Em[MAX_STAGE];    // masked exp table window, pitch P = tx + 2 round4(v)
     int32_t a_pk[MAX_TILE_CELLS];       // agents of the tile: id << 12 | LDS cell
     float a_ec[MAX_TILE_CELLS];         // e_c of their own cell
     int32_t m_nb[9];
     int n_agents, n_flag, n_mov;
 };
+template <bool SS>
+struct PlanShared : PlanSharedBase {};
+template <>
+struct PlanShared<true> : PlanSharedBase {
+    alignas(16) double Sw[MAX_STAGE];   // floor-field window, same layout as Em
+};
 
 // Appends movers (target != own cell) to the tile's record segment, one LDS
 // atomic per wavefront.
-__device__ __forceinline__ void emit_movers(MoveRec *seg, PlanShared &sh, bool mover, MoveRec rec)
+__device__ __forceinline__ void emit_movers(MoveRec *seg, PlanSharedBase &sh, bool mover, MoveRec rec)
 {
     const unsigned long long mask = __ballot(mover);
     if (mask == 0) return;
@@ -269,9 +325,11 @@ __device__ __forceinline__ uint32_t plan_draw_word(uint32_t id, uint32_t step, u
 }
 
 // V = v_max, TX = tile width (a power of two, 8..64): both fix the LDS pitch,
-// so every window offset of the agent loop is a compile-time constant.
-template <int V, int TX, bool DEBUG>
-__device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
+// so every window offset of the agent loop is a compile-time constant.  SS
+// stages the floor-field window too (launches too small to hide the global
+// latency of the rare FP64 re-resolve).
+template <int V, int TX, bool DEBUG, bool SS>
+__device__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
 {
     constexpr int SIDE = 2 * V + 1;
     constexpr int Hc = (V + 3) & ~3;                          // column halo, a multiple of 4 >= V
@@ -322,20 +380,30 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
     }
     int4 o_in = make_int4(-1, -1, -1, -1), o_h0 = o_in, o_h1 = o_in;
     float4 g_in = make_float4(0.f, 0.f, 0.f, 0.f), g_h0 = g_in, g_h1 = g_in;
+    double4 s_in{}, s_h0{}, s_h1{};
+    auto load_S = [&](int g, double4 &d) {
+        if constexpr (SS) {
+            const double2 a = *(const double2 *)(s.S + g), b = *(const double2 *)(s.S + g + 2);
+            d = double4{a.x, a.y, b.x, b.y};
+        }
+    };
     if (ci < n_in) {
         const int g = (gy0 + ly_in) * s.Wp + gx0 + 4 * cc_in;
         o_in = *(const int4 *)(s.occ + g);
         g_in = *(const float4 *)(s.G + g);
+        load_S(g, s_in);
     }
     if (tid < n_halo) {
         const int g = (gy0 + ly_h[0]) * s.Wp + gx0 + 4 * cc_h[0];
         o_h0 = *(const int4 *)(s.occ + g);
         g_h0 = *(const float4 *)(s.G + g);
+        load_S(g, s_h0);
     }
     if (tid + nthr < n_halo) {
         const int g = (gy0 + ly_h[1]) * s.Wp + gx0 + 4 * cc_h[1];
         o_h1 = *(const int4 *)(s.occ + g);
         g_h1 = *(const float4 *)(s.G + g);
+        load_S(g, s_h1);
     }
     // the step counter is read while the staging loads are in flight
     const int step = s.ctr[C_STEP];
@@ -345,6 +413,12 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
     const int mT = sh.m_nb[4];
 
     // halo chunks: rescale to this tile's exponent, mask occupied cells
+    auto stage_S = [&](int l0, const double4 &d) {
+        if constexpr (SS) {
+            *(double2 *)&sh.Sw[l0] = double2{d.x, d.y};
+            *(double2 *)&sh.Sw[l0 + 2] = double2{d.z, d.w};
+        }
+    };
     auto stage_halo = [&](int ly, int cc, int4 o, float4 gv) {
         const int nby = (ly >= V) + (ly >= V + s.ty);
         const int nbx = (cc >= hc4) + (cc >= hc4 + cw);       // a chunk lies inside one tile column
@@ -353,17 +427,25 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
             make_float4(o.x < 0 ? ldexpf(gv.x, dm) : 0.f, o.y < 0 ? ldexpf(gv.y, dm) : 0.f,
                         o.z < 0 ? ldexpf(gv.z, dm) : 0.f, o.w < 0 ? ldexpf(gv.w, dm) : 0.f);
     };
-    if (tid < n_halo) stage_halo(ly_h[0], cc_h[0], o_h0, g_h0);
-    if (tid + nthr < n_halo) stage_halo(ly_h[1], cc_h[1], o_h1, g_h1);
+    if (tid < n_halo) {
+        stage_halo(ly_h[0], cc_h[0], o_h0, g_h0);
+        stage_S(ly_h[0] * P + 4 * cc_h[0], s_h0);
+    }
+    if (tid + nthr < n_halo) {
+        stage_halo(ly_h[1], cc_h[1], o_h1, g_h1);
+        stage_S(ly_h[1] * P + 4 * cc_h[1], s_h1);
+    }
 
     // interior chunk: already in the tile's scale; its occupied cells are the
     // tile's agents (one LDS atomic per wavefront to list them)
     {
         const bool live = ci < n_in;
         const int l0 = ly_in * P + 4 * cc_in;
-        if (live)
+        if (live) {
             *(float4 *)&sh.Em[l0] = make_float4(o_in.x < 0 ? g_in.x : 0.f, o_in.y < 0 ? g_in.y : 0.f,
                                                 o_in.z < 0 ? g_in.z : 0.f, o_in.w < 0 ? g_in.w : 0.f);
+            stage_S(l0, s_in);
+        }
         const int ov[4] = {o_in.x, o_in.y, o_in.z, o_in.w};
         const float gv[4] = {g_in.x, g_in.y, g_in.z, g_in.w};
         unsigned long long m[4];
@@ -530,7 +612,9 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
                 const uint32_t x0 = plan_draw_word((uint32_t)fid, (uint32_t)step, scn, kseed0,
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const int t = resolve64_wave<V>(s, gc, u, lane, sh.Em, l, P);
+                const double *Sw = nullptr;
+                if constexpr (SS) Sw = sh.Sw;
+                const int t = resolve64_wave<V, SS>(s, gc, u, lane, sh.Em, Sw, l, P);
                 if (lane == 0 && t != gc) {
                     const int d = t - gc;
                     const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
@@ -548,386 +632,30 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
     }
 }
 
-template <int V, bool DEBUG>
-__device__ __forceinline__ void plan_dispatch_tx(const SlotDev &s, int tile, PlanShared &sh)
+template <int V, bool DEBUG, bool SS>
+__device__ __forceinline__ void plan_dispatch_tx(const SlotDev &s, int tile, PlanShared<SS> &sh)
 {
     switch (s.tx) {
-        case 8: plan_tile<V, 8, DEBUG>(s, tile, sh); break;
-        case 16: plan_tile<V, 16, DEBUG>(s, tile, sh); break;
-        case 32: plan_tile<V, 32, DEBUG>(s, tile, sh); break;
-        case 64: plan_tile<V, 64, DEBUG>(s, tile, sh); break;
+        case 8: plan_tile<V, 8, DEBUG, SS>(s, tile, sh); break;
+        case 16: plan_tile<V, 16, DEBUG, SS>(s, tile, sh); break;
+        case 32: plan_tile<V, 32, DEBUG, SS>(s, tile, sh); break;
+        case 64: plan_tile<V, 64, DEBUG, SS>(s, tile, sh); break;
         default: break;
     }
 }
 
-template <bool DEBUG>
-__device__ __forceinline__ void plan_dispatch(const SlotDev &s, int tile, PlanShared &sh)
+// Device-side dispatch over (v_max, tile width): one launch can mix scenarios.
+template <bool DEBUG, bool SS>
+__device__ __forceinline__ void plan_dispatch(const SlotDev &s, int tile, PlanShared<SS> &sh)
 {
     switch (s.v) {
-        case 1: plan_dispatch_tx<1, DEBUG>(s, tile, sh); break;
-        case 2: plan_dispatch_tx<2, DEBUG>(s, tile, sh); break;
-        case 3: plan_dispatch_tx<3, DEBUG>(s, tile, sh); break;
-        case 4: plan_dispatch_tx<4, DEBUG>(s, tile, sh); break;
-        case 5: plan_dispatch_tx<5, DEBUG>(s, tile, sh); break;
-        default: break;
-    }
-}
-
-// Batched form: items[i] = (slot << 20) | tile index (row-major over the
-// slot's tiles); descriptors come from the device table.
-template <bool DEBUG>
-__global__ __launch_bounds__(PLAN_THREADS) __attribute__((amdgpu_waves_per_eu(7)))
-void plan_kernel(const SlotDev *__restrict__ table,
-                                                            const uint32_t *__restrict__ items)
-{
-    __shared__ PlanShared sh;
-    const uint32_t it = items[blockIdx.x];
-    plan_dispatch<DEBUG>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
-}
-
-// One scenario: its descriptor arrives by value with the kernel arguments and
-// workgroup i plans tile i, which saves two dependent memory round trips.
-template <bool DEBUG>
-__global__ __launch_bounds__(PLAN_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
-void plan_kernel_one(const SlotDev s)
-{
-    __shared__ PlanShared sh;
-    plan_dispatch<DEBUG>(s, (int)blockIdx.x, sh);
-}
-
-// ---------------------------------------------------------------------------
-// Motion kernel: deterministic reservations.  The movers of a scenario are
-// split over a group of G workgroups; each keeps its share in a private list.
-// Round r reserves into res[r & 1] with tag r (tags grow, so stale words of
-// earlier rounds always lose), so the checks of round r and the reservations
-// of round r + 1 never touch the same array and one group barrier per round
-// suffices:
-//     reserve r+1 (own losers) | count | barrier | check r+1, commit, ...
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int isgn(int a) { return (a > 0) - (a < 0); }
-
-__device__ __forceinline__ int ld_agent(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(int32_t *p, int v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_res(const unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Cells of the DDA line from (cx, cy) towards (cx + dx, cy + dy):
-// p_k = (cx + sgn dx floor((2k|dx| + m) / 2m), cy + sgn dy floor((2k|dy| + m) / 2m)),
-// k = 0..m, m = max(|dx|, |dy|) <= v.
-struct Line {
-    int cx, cy, sx, sy, adx, ady, m;
-    __device__ __forceinline__ void at(int k, int &x, int &y) const
-    {
-        x = cx + sx * ((2 * k * adx + m) / (2 * m));
-        y = cy + sy * ((2 * k * ady + m) / (2 * m));
-    }
-};
-
-__device__ __forceinline__ Line make_line(uint32_t cxy, uint32_t dxy)
-{
-    Line L;
-    L.cx = (int)(cxy & 0xFFFFu);
-    L.cy = (int)(cxy >> 16);
-    const int dx = (int)(dxy & 0xFFFFu) - L.cx, dy = (int)(dxy >> 16) - L.cy;
-    L.sx = isgn(dx);
-    L.sy = isgn(dy);
-    L.adx = abs(dx);
-    L.ady = abs(dy);
-    L.m = max(L.adx, L.ady);
-    return L;
-}
-
-// Barrier of the G workgroups of one scenario that also sums their mover
-// counts.  Round r uses the 64-bit word bar[r & 1] = [arrivals:32][count:32]
-// (both zeroed by the planning kernel): each workgroup adds (1 << 32) | n and
-// waits until the arrivals reach (r / 2 + 1) * G.  A word is touched again only
-// two barriers later, after every workgroup has read it, so the count part
-// minus its value at the previous barrier of the same parity is this round's
-// total.  All data shared between the workgroups moves through agent-scope
-// atomics; the fences of thread 0 order them around the arrival.  A wait
-// longer than SPIN_LIMIT polls marks the scenario as failed (C_ERR) instead of
-// hanging; the function then returns -1.
-__device__ int group_sync_count(const SlotDev &s, int G, int r, int n, unsigned long long &seen0,
-                                unsigned long long &seen1)
-{
-    __shared__ int sh_total;
-    __syncthreads();
-    if (G == 1) return n;
-    if (threadIdx.x == 0) {
-        unsigned long long *bar = (unsigned long long *)&s.ctr[C_BAR] + (r & 1);
-        unsigned long long &seen = (r & 1) ? seen1 : seen0;
-        __threadfence();
-        atomicAdd(bar, (1ull << 32) | (unsigned long long)(uint32_t)n);
-        const unsigned long long target = (unsigned long long)(r / 2 + 1) * (unsigned long long)G;
-        uint32_t spins = 0;
-        unsigned long long w;
-        int total = -1;
-        for (;;) {
-            w = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((w >> 32) >= target) { total = (int)((uint32_t)w - (uint32_t)seen); seen = w; break; }
-            if (++spins > SPIN_LIMIT) { atomicOr(&s.ctr[C_ERR], 1); break; }
-        }
-        __threadfence();
-        sh_total = total;
-    }
-    __syncthreads();
-    return sh_total;
-}
-
-template <int V>
-__device__ __forceinline__ void reserve_list(const SlotDev &s, unsigned long long *res,
-                                             const Mover *list, int n, unsigned long long tagw)
-{
-    const int Wp = s.Wp;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const Mover mv = list[i];
-        const Line L = make_line(mv.cxy, mv.dxy);
-        const unsigned long long key = mv.key | tagw;
-#pragma unroll
-        for (int k = 0; k <= V; ++k) {
-            if (k <= L.m) {
-                int x, y;
-                L.at(k, x, y);
-                atomicMax(&res[y * Wp + x], key);
-            }
-        }
-    }
-}
-
-// Check-and-commit for the workgroup's list: a mover holding every cell of
-// its line walks it (stopping before a wall, an occupied cell, or a diagonal
-// step past a wall corner; leaving at an exit); the others are appended to
-// `nxt`.  Returns the number appended.
-template <int V>
-__device__ int commit_list(const SlotDev &s, const unsigned long long *res, const Mover *cur,
-                           Mover *nxt, int n, unsigned long long tagw)
-{
-    __shared__ int sh_cnt;
-    const int Wp = s.Wp;
-    if (threadIdx.x == 0) sh_cnt = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const Mover mv = cur[i];
-        const Line L = make_line(mv.cxy, mv.dxy);
-        const unsigned long long key = mv.key | tagw;
-        int cell[V + 1];
-        unsigned long long w[V + 1];
-        int o[V + 1];
-#pragma unroll
-        for (int k = 0; k <= V; ++k) {
-            int x = L.cx, y = L.cy;
-            if (k <= L.m) L.at(k, x, y);
-            cell[k] = y * Wp + x;
-            w[k] = k <= L.m ? ld_res(&res[cell[k]]) : key;
-            o[k] = (k >= 1 && k <= L.m) ? ld_agent(&s.occ[cell[k]]) : -1;
-        }
-        bool holds = true;
-#pragma unroll
-        for (int k = 0; k <= V; ++k) holds &= (w[k] == key);
-        if (!holds) {
-            nxt[atomicAdd(&sh_cnt, 1)] = mv;
-            continue;
-        }
-        const int id = (int)(~(uint32_t)mv.key & ID_MASK);
-        const int c = cell[0];
-        int at = c, px = L.cx, py = L.cy;
-        bool gone = false, stop = false;
-#pragma unroll
-        for (int k = 1; k <= V; ++k) {
-            if (k > L.m || stop) break;
-            int qx, qy;
-            L.at(k, qx, qy);
-            const int q = cell[k];
-            const uint8_t tq = s.type[q];
-            if (tq == CELL_WALL || o[k] != -1) { stop = true; break; }
-            if (qx != px && qy != py &&
-                (s.type[py * Wp + qx] == CELL_WALL || s.type[qy * Wp + px] == CELL_WALL)) {
-                stop = true;
-                break;
-            }
-            if (tq == CELL_EXIT) { gone = true; break; }
-            at = q; px = qx; py = qy;
-        }
-        if (gone) {
-            st_agent(&s.occ[c], -1);
-            atomicAdd(&s.ctr[C_EXITED], 1);
-            atomicSub(&s.ctr[C_NACTIVE], 1);
-        } else if (at != c) {
-            st_agent(&s.occ[c], -1);
-            st_agent(&s.occ[at], id);
-        }
-    }
-    __syncthreads();
-    return sh_cnt;
-}
-
-template <int V>
-__device__ void move_group(const SlotDev &s, int g, int G, int step)
-{
-    __shared__ int sh_scan[MOVE_THREADS];
-    const int tid = threadIdx.x;
-    const int T = s.ntx * s.nty, TC = s.tx * s.ty;
-    // workgroup g takes tiles g, g + G, g + 2G, ...: every region of the grid
-    // (the congested exit above all) is spread over the whole group, so the
-    // rounds stay balanced; its mover lists own tiles' worth of room
-    const int q = T / G, rm = T % G;
-    const int nt_g = q + (g < rm ? 1 : 0);
-    const long base_g = ((long)g * q + min(g, rm)) * TC;
-    Mover *cur = s.mv_a + base_g, *nxt = s.mv_b + base_g;
-    unsigned long long seen0 = 0, seen1 = 0;
-    uint32_t tag = (uint32_t)s.ctr[C_TAG];
-    if (g == 0 && tid == 0)   // agents planned this step, for the throughput counters
-        atomicAdd(&s.stat[S_PLANNED], (unsigned long long)s.ctr[C_NACTIVE]);
-
-    // gather this workgroup's movers (the records of its tiles) with their
-    // priority words [~x0:32][~id:20] (larger = earlier)
-    int n = 0;
-    for (int j0 = 0; j0 < nt_g; j0 += MOVE_THREADS) {
-        const int nt = min(MOVE_THREADS, nt_g - j0);
-        sh_scan[tid] = tid < nt ? s.seg_cnt[g + (long)(j0 + tid) * G] : 0;
-        __syncthreads();
-        for (int off = 1; off < MOVE_THREADS; off <<= 1) {
-            const int add = tid >= off ? sh_scan[tid - off] : 0;
-            __syncthreads();
-            sh_scan[tid] += add;
-            __syncthreads();
-        }
-        const int chunk = sh_scan[MOVE_THREADS - 1];
-        for (int i = tid; i < chunk; i += blockDim.x) {
-            int a = 0, b = nt - 1;                   // first tile whose inclusive count exceeds i
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                if (sh_scan[mid] > i) b = mid; else a = mid + 1;
-            }
-            const int k = i - (a ? sh_scan[a - 1] : 0);
-            const MoveRec rec = s.seg[(g + (long)(j0 + a) * G) * TC + k];
-            const uint32_t x0 = philox_word0(rec.id, (uint32_t)step, s.scn, STREAM_ORDER,
-                                             s.seed_lo, s.seed_hi);
-            Mover mv;
-            mv.key = ((unsigned long long)(~x0) << ID_BITS) | (unsigned long long)(~rec.id & ID_MASK);
-            mv.cxy = rec.cxy;
-            mv.dxy = rec.dxy;
-            cur[n + i] = mv;
-        }
-        n += chunk;
-        __syncthreads();
-    }
-
-    int total = 1, rounds = 0, bar_r = 0;          // round 0's total comes from its barrier
-    for (int r = 0; total > 0; ++r) {
-        unsigned long long *res = (r & 1) ? s.res1 : s.res0;
-        if (r > 0) {
-            // round r's movers are the losers of round r - 1 (this workgroup's share)
-            n = commit_list<V>(s, (r & 1) ? s.res0 : s.res1, cur, nxt, n,
-                               (unsigned long long)tag << TAG_SHIFT);
-            Mover *t = cur; cur = nxt; nxt = t;
-        }
-        if (tag >= TAG_LIMIT) {
-            // tags are exhausted: once every check of the last round is done,
-            // wipe both reservation arrays and restart the tags at 1
-            if (group_sync_count(s, G, bar_r++, 0, seen0, seen1) < 0) return;
-            const long cells = (long)s.Wp * s.Hp;
-            for (long i = cells * g / G + tid; i < cells * (g + 1) / G; i += blockDim.x) {
-                __hip_atomic_store(&s.res0[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&s.res1[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            tag = 0;
-            if (group_sync_count(s, G, bar_r++, 0, seen0, seen1) < 0) return;
-        }
-        ++tag;
-        reserve_list<V>(s, res, cur, n, (unsigned long long)tag << TAG_SHIFT);
-        total = group_sync_count(s, G, bar_r++, n, seen0, seen1);
-        if (total < 0) return;
-        rounds += total > 0 ? 1 : 0;
-    }
-    if (g == 0 && tid == 0) {
-        s.ctr[C_TAG] = (int)tag;
-        s.ctr[C_ROUNDS] = rounds;
-        s.ctr[C_STEP] = step + 1;
-    }
-}
-
-// mitems[i] = slot | g << 12 | (G - 1) << 22: workgroup g of the G that move
-// the slot's agents.
-__global__ __launch_bounds__(MOVE_THREADS) void move_kernel(const SlotDev *__restrict__ table,
-                                                            const uint32_t *__restrict__ mitems)
-{
-    const uint32_t it = mitems[blockIdx.x];
-    const SlotDev &s = table[it & 0xFFFu];
-    const int g = (int)((it >> 12) & 0x3FFu);
-    const int G = (int)(it >> 22) + 1;
-    const int step = s.ctr[C_STEP];
-    if (step >= s.ctr[C_LIMIT]) return;
-    switch (s.v) {
-        case 1: move_group<1>(s, g, G, step); break;
-        case 2: move_group<2>(s, g, G, step); break;
-        case 3: move_group<3>(s, g, G, step); break;
-        case 4: move_group<4>(s, g, G, step); break;
-        case 5: move_group<5>(s, g, G, step); break;
+        case 1: plan_dispatch_tx<1, DEBUG, SS>(s, tile, sh); break;
+        case 2: plan_dispatch_tx<2, DEBUG, SS>(s, tile, sh); break;
+        case 3: plan_dispatch_tx<3, DEBUG, SS>(s, tile, sh); break;
+        case 4: plan_dispatch_tx<4, DEBUG, SS>(s, tile, sh); break;
+        case 5: plan_dispatch_tx<5, DEBUG, SS>(s, tile, sh); break;
         default: break;
     }
 }
 
 }  // namespace fk
-
-// ---------------------------------------------------------------------------
-// Launchers used by the host runtime.
-// ---------------------------------------------------------------------------
-extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, int debug,
-                                         hipStream_t stream)
-{
-    if (n_tiles <= 0) return hipSuccess;
-    if (debug)
-        hipLaunchKernelGGL(fk::plan_kernel_one<true>, dim3(n_tiles), dim3(fk::PLAN_THREADS), 0, stream,
-                           *slot);
-    else
-        hipLaunchKernelGGL(fk::plan_kernel_one<false>, dim3(n_tiles), dim3(fk::PLAN_THREADS), 0,
-                           stream, *slot);
-    return hipGetLastError();
-}
-
-extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
-                                     int debug, hipStream_t stream)
-{
-    if (n_items <= 0) return hipSuccess;
-    if (debug)
-        hipLaunchKernelGGL(fk::plan_kernel<true>, dim3(n_items), dim3(fk::PLAN_THREADS), 0, stream,
-                           table, items);
-    else
-        hipLaunchKernelGGL(fk::plan_kernel<false>, dim3(n_items), dim3(fk::PLAN_THREADS), 0, stream,
-                           table, items);
-    return hipGetLastError();
-}
-
-extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,
-                                     hipStream_t stream)
-{
-    if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fk::move_kernel, dim3(n_items), dim3(fk::MOVE_THREADS), 0, stream, table,
-                       mitems);
-    return hipGetLastError();
-}
-
-// Workgroups of move_kernel that one device holds at once.
-extern "C" hipError_t fk_move_capacity(int *blocks)
-{
-    int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fk::move_kernel,
-                                                                fk::MOVE_THREADS, 0);
-    if (e != hipSuccess) return e;
-    e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    *blocks = per_cu * cus;
-    return hipSuccess;
-}
-

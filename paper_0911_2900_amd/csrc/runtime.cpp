@@ -11,6 +11,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -295,6 +296,7 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
                  o_seg = take(tcells * sizeof(fk::MoveRec)), o_ka = take(tcells * sizeof(fk::Mover)),
                  o_kb = take(tcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
+                 o_mcell = take(cells * 8),
                  o_mitems = take(fk::MOVE_GROUP_MAX * 4);
     void *block = nullptr;
     st = dev_alloc(c, off, &block);
@@ -306,12 +308,17 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     sd.tx = b.tx; sd.ty = b.ty; sd.ntx = b.ntx; sd.nty = b.nty; sd.n_agents = b.n;
     sd.seed_lo = (uint32_t)d->seed; sd.seed_hi = (uint32_t)(d->seed >> 32);
     sd.scn = d->scenario_id; sd.eps = b.eps; sd.k_s = d->k_s;
+    // FAST_FP64_SEQUENTIAL=1 (read when the scenario is set up) sends every
+    // FP64 re-resolve through the sequential sum, so tests can cover it
+    const char *seq = std::getenv("FAST_FP64_SEQUENTIAL");
+    sd.near64 = (seq && seq[0] == '1') ? 1e300 : 1e-12;
     sd.S = (const double *)(base + o_S);
     sd.res0 = (unsigned long long *)(base + o_res);
     sd.res1 = (unsigned long long *)(base + o_res + cells * 8);
 
     sd.G = (const float *)(base + o_G);
     sd.occ = (int32_t *)(base + o_occ);
+    sd.mcell = (unsigned long long *)(base + o_mcell);
     sd.type = (const uint8_t *)(base + o_type);
     sd.tile_m = (const int32_t *)(base + o_tm);
     sd.tile_fb = (const uint8_t *)(base + o_fb);
@@ -347,6 +354,7 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     if (e == hipSuccess) e = hipMemset(base + o_scnt, 0, ntiles * 4);   // no movers planned yet
     cp(o_ctr, ctr.data(), fk::C_NCTR * 4);
     if (e == hipSuccess) e = hipMemset(base + o_stat, 0, fk::S_NSTAT * 8);
+    if (e == hipSuccess) e = hipMemset(base + o_mcell, 0, cells * 8);
     cp(o_items, items.data(), ntiles * 4);
     cp(o_self, &self, 4);
     cp(o_mitems, mitems.data(), mitems.size() * 4);
@@ -487,7 +495,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b)
 {
     if (b->exec) return FAST_OK;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, 0, c->stream);
+    hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, c->stream);
     hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -526,7 +534,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     fast_status st = get_batch(c, hs, &b);
     if (st) return st;
     for (int k = 0; k < steps; ++k) {
-        HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, 0, c->stream));
+        HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, c->stream));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
     }
     for (int32_t h : hs) c->slots[h].host_steps += steps;
@@ -848,7 +856,7 @@ fast_status fast_plan_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     Batch *b = nullptr;
     st = get_batch(c, v, &b);
     if (st) return st;
-    HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, 0, c->stream));
+    HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, c->stream));
     for (int32_t h : v) c->slots[h].planned = true;
     return FAST_OK;
 }

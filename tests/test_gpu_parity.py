@@ -336,3 +336,26 @@ def test_large_grid_396_steps_bit_exact(ctx):
     compare_state(ctx, sim, h, where="after 396 steps")
     assert ctx.stats(h)["exited"] == sim.exited
     ctx.destroy(h)
+
+
+@pytest.mark.parametrize("v", [4, 5])
+def test_sequential_fp64_resolve_path(ctx, monkeypatch, v):
+    """The FP64 re-resolve normally accepts a wavefront scan when no prefix is
+    near tau; FAST_FP64_SEQUENTIAL=1 sends every flagged draw through the
+    strictly sequential sum instead.  Both the single-scenario launch (floor
+    field staged in LDS) and the batched launch (floor field from global
+    memory) must stay bit-exact on that path too."""
+    monkeypatch.setenv("FAST_FP64_SEQUENTIAL", "1")
+    s = sc.room(v=v, n_agents=20000, scn=7)
+    sim, h = make_pair(ctx, s)
+    step_both(ctx, sim, h, 12, check_every=4, where=f"sequential resolve v={v}")
+    assert ctx.stats(h)["flagged"] > 0
+    ctx.destroy(h)
+    members = [m for m in (sc.ensemble_member(k) for k in range(40)) if m.v == v][:3]
+    hs = [ctx.init_from(m, batched=True) for m in members]
+    ctx.run(hs, 15)
+    for m, h in zip(members, hs):
+        o = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents)
+        o.run(15)
+        compare_state(ctx, o, h, where=m.name)
+        ctx.destroy(h)
