@@ -7,17 +7,27 @@ k_S = 1.2, k_other = 0 (paper Sec. 2 parameters; the paper times 396 steps of
 `warmup` first steps of the run are untimed, the next `steps` are timed (the
 defaults cover the paper's 396 steps).  `value` is planning agent-updates/s:
 agents planned over the timed steps divided by the summed duration of the
-planning kernel, taken with HIP events on the stream the kernel runs on.
+planning kernel, recorded by HIP events that the kernel launch itself stamps
+at the kernel's start and end (the interval a kernel trace reports).  Events
+recorded on the stream around each launch, which add the dispatch latency,
+give the `_bracketed` figures; `ms_per_step` is the whole step (plan + move).
 
 Also printed on the same JSON line:
   roofline      the planning kernel's algorithmic bytes per launch (5 B per
                 cell inside some agent's reach window: occupancy 1 B + exp
                 table 4 B; 12 B per agent: position 8 B + desired cell 4 B)
-                over its average duration, against 8 TB/s of HBM.
+                over its average kernel duration, against 8 TB/s of HBM;
+                `traffic` is the HBM bytes per launch measured with hardware
+                counters (profiles/plan_traffic.json), or null when the
+                planning sources have changed since it was measured.
+  large         the same for 16 scenarios of 1000 x 1000 cells (200,000
+                agents each) planned in one launch, the throughput regime.
   ensemble      the 256-scenario ensemble workload run as one batch (one
                 planning and one motion launch per step, replayed from a HIP
                 graph), scenario-steps/s, next to the same scenarios stepped
                 one at a time with plain launches.
+  serving       the continuous-batching server on Poisson arrivals: p50 / p99
+                latency and scenarios/s, open and closed loop.
   cpu_baseline  the CPU oracle's planning loop (the paper's OpenMP schedule)
                 on the host's cores, on the first steps of the same run.
 """
@@ -40,6 +50,35 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+PLAN_SOURCES = ("paper_0911_2900_amd/csrc/plan_tile.h", "paper_0911_2900_amd/csrc/plan_one.hip",
+                "paper_0911_2900_amd/csrc/plan_batch.hip", "paper_0911_2900_amd/csrc/fast_dev.h")
+
+
+def plan_sources_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in PLAN_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per planning launch from the hardware counters summarised in
+    profiles/plan_traffic.json, or None if that file is missing or was taken
+    on other planning sources than these."""
+    path = os.path.join(ROOT, "profiles", "plan_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("plan_sources_sha256") != plan_sources_digest() or workload not in t:
+        return None
+    return t[workload]["hbm_bytes_per_launch"]
 
 
 def window_cells(cell_type: np.ndarray, xy: np.ndarray, v: int) -> int:
@@ -72,6 +111,7 @@ def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4):
           for _ in range(steps)]
     e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    ctx.timing_start(steps)
     t0 = time.perf_counter()
     e_start.record(stream)
     for k in range(steps):
@@ -82,13 +122,15 @@ def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4):
     e_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    plan_ms = [a.elapsed_time(b) for a, b in ev]
+    kernel_ms = ctx.timing_read()
+    assert len(kernel_ms) == steps
+    bracket_ms = [a.elapsed_time(b) for a, b in ev]
     total_ms = e_start.elapsed_time(e_end)
     stt = ctx.stats(h)
     planned = stt["planned"] - planned0
     res = {
-        "planned": planned, "plan_ms": plan_ms, "total_ms": total_ms, "wall_s": wall,
-        "cells": cells, "stats": stt, "handle": h,
+        "planned": planned, "plan_ms": [float(x) for x in kernel_ms], "bracket_ms": bracket_ms,
+        "total_ms": total_ms, "wall_s": wall, "cells": cells, "stats": stt, "handle": h,
     }
     ctx.destroy(h)
     return res
@@ -141,7 +183,8 @@ def bench_ensemble(ctx, torch, warmup: int, steps: int, plain_steps: int):
     }
 
 
-def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int):
+def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int,
+                     traffic_key: str = ""):
     """Planning kernel of many scenarios in one launch (fast_plan_batch), the
     throughput regime: events around each launch, motion between them."""
     t0 = time.perf_counter()
@@ -160,13 +203,16 @@ def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int):
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     torch.cuda.synchronize()
+    ctx.timing_start(steps)
     for k in range(steps):
         ev[k][0].record(stream)
         ctx.plan_batch(hs)
         ev[k][1].record(stream)
         ctx.move_batch(hs)
     torch.cuda.synchronize()
-    plan_ms = [a.elapsed_time(b) for a, b in ev]
+    plan_ms = [float(x) for x in ctx.timing_read()]
+    assert len(plan_ms) == steps
+    bracket_ms = [a.elapsed_time(b) for a, b in ev]
     planned = sum(ctx.stats(h)["planned"] for h in hs) - planned0
     for h in hs:
         ctx.destroy(h)
@@ -178,8 +224,10 @@ def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int):
         "tile": tile,
         "planning_agent_updates_per_s": planned / (sum(plan_ms) / 1e3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "plan_kernel",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(traffic_key),
+                     "kernel": "plan_kernel",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_ms * 1e3},
+        "plan_us_bracketed": float(np.mean(bracket_ms)) * 1e3,
         "init_s": init_s,
     }
 
@@ -349,7 +397,7 @@ def main():
         large = bench_batch_plan(ctx, torch, sc.large(16),
                                  "16 scenarios of 1000x1000 cells, 10 % pillars, 4 exits, "
                                  "200,000 agents each, v_m=4, one planning launch", 2,
-                                 args.large_steps)
+                                 args.large_steps, traffic_key="large")
         log(f"large: {large}")
     replicas = None
     if args.room_replicas:
@@ -398,10 +446,12 @@ def main():
         },
         "whole_step_agent_updates_per_s": r["planned"] / (r["total_ms"] / 1e3),
         "plan_us_per_step": avg_plan_ms * 1e3,
+        "plan_us_bracketed": float(np.mean(r["bracket_ms"])) * 1e3,
+        "planning_agent_updates_per_s_bracketed": r["planned"] / (sum(r["bracket_ms"]) / 1e3),
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "plan_kernel", "bytes_per_launch": bytes_per_launch,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("room"),
+            "kernel": "plan_kernel_one", "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": avg_plan_ms * 1e3,
         },
         "ensemble": ens,

@@ -182,6 +182,20 @@ fast_status fast_get_stats(fast_ctx *ctx, int32_t handle, fast_stats *out);
 fast_status fast_debug_plan(fast_ctx *ctx, int32_t handle, float *w32, uint8_t *flag,
                             float *margin);
 
+/* ---- Kernel timing ------------------------------------------------------ */
+
+/* Starts timing planning kernels: the next `max_launches` planning launches
+ * of fast_plan_step and fast_plan_batch (not those inside fast_run graphs)
+ * record the kernel's own start and end on the device, the same interval a
+ * kernel trace reports, without waiting on the host.  Restarting discards
+ * earlier records.  FAST_E_INVALID unless 1 <= max_launches <= 2^20. */
+fast_status fast_timing_start(fast_ctx *ctx, int32_t max_launches);
+
+/* Synchronises the context stream, writes the durations (milliseconds) of
+ * the timed launches in launch order to ms[0 .. min(n, cap)), sets *n to the
+ * number timed, and stops timing. */
+fast_status fast_timing_read(fast_ctx *ctx, float *ms, int32_t cap, int32_t *n);
+
 /* ---- Serving: continuous batching of scenario requests ------------------ */
 
 /* Starts serving on host threads of the context.  Builder threads (half the

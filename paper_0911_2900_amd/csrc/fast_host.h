@@ -38,9 +38,9 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
 }  // namespace fh
 
 extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
-                                     hipStream_t stream);
+                                     hipStream_t stream, hipEvent_t start, hipEvent_t stop);
 extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, int debug,
-                                         hipStream_t stream);
+                                         hipStream_t stream, hipEvent_t start, hipEvent_t stop);
 extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,
                                      hipStream_t stream);
 extern "C" hipError_t fk_move_capacity(int *blocks);

@@ -1,6 +1,8 @@
 // plan_batch.hip -- the batched planning kernel: one launch plans the tiles
 // of many scenarios (uneven grids, agent counts, v_max and tile shapes), one
 // workgroup per tile.
+#include <hip/hip_ext.h>
+
 #include "plan_tile.h"
 
 namespace fk {
@@ -17,11 +19,12 @@ void plan_kernel(const SlotDev *__restrict__ table, const uint32_t *__restrict__
 
 }  // namespace fk
 
+// start / stop (optional): events that record the kernel's own start and end.
 extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
-                                     hipStream_t stream)
+                                     hipStream_t stream, hipEvent_t start, hipEvent_t stop)
 {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fk::plan_kernel, dim3(n_items), dim3(fk::PLAN_THREADS), 0, stream, table,
-                       items);
+    hipExtLaunchKernelGGL(fk::plan_kernel, dim3(n_items), dim3(fk::PLAN_THREADS), 0, stream, start,
+                          stop, 0, table, items);
     return hipGetLastError();
 }

@@ -9,6 +9,8 @@
 // re-resolve makes no global reads.  Launches with many tiles keep 256
 // threads and read the floor field from global memory, like the batched
 // kernel.  The debug form also writes weights, flags and margins.
+#include <hip/hip_ext.h>
+
 #include "plan_tile.h"
 
 namespace fk {
@@ -25,8 +27,10 @@ __global__ __launch_bounds__(ONE_MAX_THREADS) void plan_kernel_one(const SlotDev
 
 }  // namespace fk
 
+// start / stop (optional): events that record the kernel's own start and end
+// (hipExtLaunchKernelGGL), the timestamps a kernel trace reports.
 extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, int debug,
-                                         hipStream_t stream)
+                                         hipStream_t stream, hipEvent_t start, hipEvent_t stop)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (debug) {
@@ -36,11 +40,11 @@ extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, i
         const int cells = slot->tx * slot->ty;
         const int threads = cells < fk::PLAN_THREADS ? fk::PLAN_THREADS
                             : cells > fk::ONE_MAX_THREADS ? fk::ONE_MAX_THREADS : cells;
-        hipLaunchKernelGGL((fk::plan_kernel_one<false, true>), dim3(n_tiles), dim3(threads), 0,
-                           stream, *slot);
+        hipExtLaunchKernelGGL((fk::plan_kernel_one<false, true>), dim3(n_tiles), dim3(threads), 0,
+                              stream, start, stop, 0, *slot);
     } else {
-        hipLaunchKernelGGL((fk::plan_kernel_one<false, false>), dim3(n_tiles),
-                           dim3(fk::PLAN_THREADS), 0, stream, *slot);
+        hipExtLaunchKernelGGL((fk::plan_kernel_one<false, false>), dim3(n_tiles),
+                              dim3(fk::PLAN_THREADS), 0, stream, start, stop, 0, *slot);
     }
     return hipGetLastError();
 }

@@ -112,6 +112,8 @@ struct fast_ctx {
     int move_capacity = 0;           // motion workgroups the device holds at once
     std::vector<Slot> slots;
     std::map<std::vector<int32_t>, Batch> batches;
+    std::vector<hipEvent_t> timing;  // kernel timing: start / stop pairs of plan launches
+    int timing_used = 0;
     std::recursive_mutex mu;         // guards everything above
 
     // serving
@@ -130,6 +132,16 @@ struct fast_ctx {
 };
 
 namespace {
+
+// The next start / stop event pair of kernel timing (none when it is off or full).
+void next_timing_pair(fast_ctx *c, hipEvent_t *e0, hipEvent_t *e1)
+{
+    if (c->timing_used * 2 + 1 < (int)c->timing.size()) {
+        *e0 = c->timing[c->timing_used * 2];
+        *e1 = c->timing[c->timing_used * 2 + 1];
+        ++c->timing_used;
+    }
+}
 
 fast_status dev_alloc(fast_ctx *c, size_t bytes, void **out)
 {
@@ -495,7 +507,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b)
 {
     if (b->exec) return FAST_OK;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, c->stream);
+    hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, c->stream, nullptr, nullptr);
     hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -534,7 +546,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     fast_status st = get_batch(c, hs, &b);
     if (st) return st;
     for (int k = 0; k < steps; ++k) {
-        HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, c->stream));
+        HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, c->stream, nullptr, nullptr));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
     }
     for (int32_t h : hs) c->slots[h].host_steps += steps;
@@ -791,6 +803,8 @@ fast_status fast_ctx_destroy(fast_ctx *c)
             dev_free(c, kv.second.block, kv.second.bytes);
         }
         c->batches.clear();
+        for (hipEvent_t e : c->timing) (void)hipEventDestroy(e);
+        c->timing.clear();
         (void)hipFree(c->table);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
@@ -818,7 +832,9 @@ fast_status fast_plan_step(fast_ctx *c, int32_t h)
     std::lock_guard<std::recursive_mutex> g(c->mu);
     Slot *s = get_slot(c, h);
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
-    HIP_TRY(fk_launch_plan_one(&s->dev, s->n_items, 0, c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    next_timing_pair(c, &e0, &e1);
+    HIP_TRY(fk_launch_plan_one(&s->dev, s->n_items, 0, c->stream, e0, e1));
     s->planned = true;
     return FAST_OK;
 }
@@ -856,8 +872,43 @@ fast_status fast_plan_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     Batch *b = nullptr;
     st = get_batch(c, v, &b);
     if (st) return st;
-    HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    next_timing_pair(c, &e0, &e1);
+    HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, c->stream, e0, e1));
     for (int32_t h : v) c->slots[h].planned = true;
+    return FAST_OK;
+}
+
+fast_status fast_timing_start(fast_ctx *c, int32_t max_launches)
+{
+    if (!c || max_launches < 1 || max_launches > (1 << 20))
+        return fail(FAST_E_INVALID, "bad arguments to fast_timing_start");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    for (hipEvent_t e : c->timing) (void)hipEventDestroy(e);
+    c->timing.assign((size_t)2 * max_launches, nullptr);
+    for (auto &e : c->timing) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (hipEvent_t x : c->timing) if (x) (void)hipEventDestroy(x);
+            c->timing.clear();
+            return fail(FAST_E_DEVICE, "hipEventCreate failed");
+        }
+    }
+    c->timing_used = 0;
+    return FAST_OK;
+}
+
+fast_status fast_timing_read(fast_ctx *c, float *ms, int32_t cap, int32_t *n)
+{
+    if (!c || !n || cap < 0 || (cap > 0 && !ms)) return fail(FAST_E_INVALID, "bad arguments to fast_timing_read");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int used = c->timing_used;
+    for (int i = 0; i < used && i < cap; ++i)
+        HIP_TRY(hipEventElapsedTime(&ms[i], c->timing[2 * i], c->timing[2 * i + 1]));
+    *n = used;
+    for (hipEvent_t e : c->timing) (void)hipEventDestroy(e);
+    c->timing.clear();
+    c->timing_used = 0;
     return FAST_OK;
 }
 
@@ -941,7 +992,7 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     sd.dbg_flag = (uint8_t *)((char *)block + bw);
     sd.dbg_margin = (float *)((char *)block + bw + bf);
     hipError_t e = hipMemsetAsync(block, 0, bw + bf + bm, c->stream);
-    if (e == hipSuccess) e = fk_launch_plan_one(&sd, s->n_items, 1, c->stream);
+    if (e == hipSuccess) e = fk_launch_plan_one(&sd, s->n_items, 1, c->stream, nullptr, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) {
         s->planned = true;

@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
         "fast_get_state": [P, I32, P, P, P, P, P],
         "fast_get_stats": [P, I32, P],
         "fast_debug_plan": [P, I32, P, P, P],
+        "fast_timing_start": [P, I32],
+        "fast_timing_read": [P, P, I32, P],
         "fast_serve_start": [P, ctypes.c_size_t, I32],
         "fast_serve_submit": [P, P, I32, P],
         "fast_serve_poll": [P, U64, P, P],
@@ -258,6 +260,20 @@ class Context:
         margin = np.zeros(m, dtype=np.float32)
         _check(lib().fast_debug_plan(self.ctx, h, _ptr(w), _ptr(flag), _ptr(margin)))
         return w[:n], flag[:n], margin[:n]
+
+    # -- kernel timing -----------------------------------------------------
+    def timing_start(self, max_launches: int):
+        """The next max_launches planning launches record their kernel time."""
+        _check(lib().fast_timing_start(self.ctx, int(max_launches)))
+        self._timing_cap = int(max_launches)
+
+    def timing_read(self) -> np.ndarray:
+        """Kernel durations (ms) of the timed planning launches; stops timing."""
+        cap = getattr(self, "_timing_cap", 0)
+        ms = np.zeros(max(cap, 1), dtype=np.float32)
+        n = ctypes.c_int32(0)
+        _check(lib().fast_timing_read(self.ctx, _ptr(ms), cap, ctypes.byref(n)))
+        return ms[: min(n.value, cap)].copy()
 
     # -- serving -----------------------------------------------------------
     def serve_start(self, budget: int = 0, max_active: int = 0):
