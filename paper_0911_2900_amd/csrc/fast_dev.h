@@ -72,14 +72,13 @@ enum : int {
 // key: bits 0..51 the priority word [~x0:32][~id:20] (larger = earlier);
 // bits 52..54 the reach m_eff of the line; bits 55..59 flag the line cells
 // k = 1..5 that hold a higher-priority mover at the start of the phase; bit
-// 60 marks a line that ends on an exit; bit 61 marks a mover whose reach is
-// not known yet (m_eff is then the whole line).
+// 60 marks a line that ends on an exit.
 struct Mover {
     unsigned long long key;
     uint32_t cxy, dxy;
 };
 constexpr unsigned long long KEY_MASK = (1ull << 52) - 1ull;
-constexpr int MEFF_SHIFT = 52, HP_SHIFT = 55, EXIT_BIT = 60, RAW_BIT = 61;
+constexpr int MEFF_SHIFT = 52, HP_SHIFT = 55, EXIT_BIT = 60;
 
 // A mover as planned: agent id and packed start / target cells.
 struct MoveRec {
@@ -107,7 +106,6 @@ struct SlotDev {
     const int32_t *tile_m;   // (ntx+2)*(nty+2), a ring of zeros around
     const uint8_t *tile_fb;  // ntx*nty
     int32_t *occ;            // Wp*Hp
-    unsigned long long *mcell;// Wp*Hp: (step + 1) << 32 | id at the start cell of each mover
     unsigned long long *res0;// Wp*Hp, reservations of even rounds
     unsigned long long *res1;// Wp*Hp, reservations of odd rounds
     int32_t *seg_cnt;        // ntx*nty: movers planned per tile

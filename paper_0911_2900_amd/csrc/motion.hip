@@ -2,17 +2,15 @@
 // (paper Sec. 1): agents walk their lines one by one in priority order.  It
 // runs as deterministic reservations on a group of workgroups per scenario.
 //
-// What an agent A can meet on its line is decided once per phase: a wall or
-// a cut wall corner ends the line; so does the start cell of a mover of lower
-// priority (it is still there when A's turn comes) and any other occupied
-// cell (an agent that does not move this step, or a committed mover that has
-// arrived: occupants of cells other than start cells never leave); the start
-// cell of a higher-priority mover B stays open (B may leave first).  The line
-// up to that point, cells 0..m_eff, is A's reach.  Start cells are stamped in
-// mcell when the movers are gathered; the reach is formed at a mover's first
-// check, after the first group barrier has made every stamp visible, so its
-// first reservation covers the whole line (a superset of the reach, which
-// can only delay a commit).
+// What an agent A can meet on its line is decided once per phase, when the
+// movers are gathered and nothing has moved yet: a wall or a cut wall corner
+// ends the line; so does a cell held by an agent of lower priority in this
+// step's order (a mover of lower priority is still there when A's turn comes;
+// an agent that does not move stays anyway); a cell held by an agent of
+// higher priority stays open (if it is a mover it may leave first; if not,
+// A finds the cell occupied when it walks).  The line up to that point, cells
+// 0..m_eff, is A's reach.  Cells other than movers' start cells only ever
+// gain occupants, committed movers that stay.
 //
 // Every round each pending mover reserves its reach with atomicMax of its
 // priority word.  A mover commits once it holds every reach cell it can still
@@ -161,61 +159,50 @@ __device__ __forceinline__ unsigned long long order_key(const SlotDev &s, uint32
     return ((unsigned long long)(~x0) << ID_BITS) | (unsigned long long)(~id & ID_MASK);
 }
 
-// The reach of a mover (see the protocol above), from the static cell types,
-// the start-cell stamps of this step and the current occupancy: returns the
-// m_eff, higher-priority-cell and exit bits of its key.
+// The reach of a mover (see the protocol above), from the cell types and the
+// occupancy at the start of the phase: returns the m_eff, higher-priority-cell
+// and exit bits of its key.  Runs while the movers are gathered, before any
+// mover of the scenario moves.
 template <int V>
 __device__ unsigned long long line_reach(const SlotDev &s, const Mover &mv, int step)
 {
     const Line L = make_line(mv.cxy, mv.dxy);
     const int Wp = s.Wp;
     const unsigned long long self = mv.key & KEY_MASK;
-    const uint32_t stamp = (uint32_t)step + 1u;
-    // two memory round trips: the cell types first (walls and cut corners
-    // bound the line), then stamps and occupancy of the cells before that
-    int q[V + 1];
-    uint32_t wallm = 0, exitm = 0;               // bit k: cell k is a wall or cut corner / an exit
+    // every load of the line first (one memory round trip), then the walk
+    uint32_t wallm = 0, exitm = 0;                      // bit k: wall or cut corner / exit
+    int o[V + 1];
     int px = L.cx, py = L.cy;
 #pragma unroll
     for (int k = 1; k <= V; ++k) {
         int qx = px, qy = py;
         if (k <= L.m) L.at(k, qx, qy);
-        q[k] = qy * Wp + qx;
-        const uint8_t t = k <= L.m ? s.type[q[k]] : (uint8_t)CELL_WALL;
+        const int q = qy * Wp + qx;
+        const bool in = k <= L.m;
+        const uint8_t t = in ? s.type[q] : (uint8_t)CELL_WALL;
         const bool diag = qx != px && qy != py;
         const uint8_t ta = diag ? s.type[py * Wp + qx] : (uint8_t)0;
         const uint8_t tb = diag ? s.type[qy * Wp + px] : (uint8_t)0;
         wallm |= (t == CELL_WALL || ta == CELL_WALL || tb == CELL_WALL) ? 1u << k : 0u;
         exitm |= t == CELL_EXIT ? 1u << k : 0u;
+        o[k] = in && t != CELL_WALL ? s.occ[q] : -1;
         px = qx;
         py = qy;
     }
     const int first_wall = __builtin_ctz(wallm | (1u << (V + 1)));   // V + 1: none
     const int ms = min(first_wall - 1, L.m);
-    unsigned long long e[V + 1];
-    int o[V + 1];
-#pragma unroll
-    for (int k = 1; k <= V; ++k) {
-        e[k] = k <= ms ? __hip_atomic_load(&s.mcell[q[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                       : 0ull;
-        o[k] = k <= ms ? ld_agent(&s.occ[q[k]]) : -1;
-    }
     int me = ms;
     uint32_t hp = 0;
     bool ex = false;
 #pragma unroll
     for (int k = 1; k <= V; ++k) {
         if (k > ms) break;
-        if ((uint32_t)(e[k] >> 32) == stamp) {
-            if (order_key(s, (uint32_t)e[k], step) > self) {
-                hp |= 1u << (k - 1);                // a higher-priority mover: may leave first
+        if (o[k] >= 0) {
+            if (order_key(s, (uint32_t)o[k], step) > self) {
+                hp |= 1u << (k - 1);                // higher priority: may have left by then
                 continue;
             }
-            me = k - 1;                             // still there at this mover's turn
-            break;
-        }
-        if (o[k] >= 0) {
-            me = k - 1;                             // an occupant that never leaves
+            me = k - 1;                             // there when this mover's turn comes
             break;
         }
         if ((exitm >> k) & 1u) {
@@ -231,20 +218,12 @@ __device__ unsigned long long line_reach(const SlotDev &s, const Mover &mv, int 
 // Check-and-commit for the workgroup's list (see the protocol above); movers
 // that cannot commit yet are appended to `nxt`.  Returns the number appended.
 template <int V>
-__device__ int commit_list(const SlotDev &s, const unsigned long long *res, Mover *cur,
-                           Mover *nxt, int n, unsigned long long tagw, int step, bool first)
+__device__ int commit_list(const SlotDev &s, const unsigned long long *res, const Mover *cur,
+                           Mover *nxt, int n, unsigned long long tagw)
 {
     __shared__ int sh_cnt;
     const int Wp = s.Wp;
     if (threadIdx.x == 0) sh_cnt = 0;
-    if (first) {
-        // the reach of every mover, in a pass of its own (its loads and the
-        // check's would not fit the registers together)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            const Mover mv = cur[i];
-            cur[i].key = (mv.key & KEY_MASK) | line_reach<V>(s, mv, step);
-        }
-    }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const Mover mv = cur[i];
@@ -375,11 +354,7 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
             mv.key = order_key(s, rec.id, step);
             mv.cxy = rec.cxy;
             mv.dxy = rec.dxy;
-            const Line L = make_line(rec.cxy, rec.dxy);
-            mv.key |= ((unsigned long long)L.m << MEFF_SHIFT) | (1ull << RAW_BIT);
-            __hip_atomic_store(&s.mcell[L.cy * s.Wp + L.cx],
-                               ((unsigned long long)(step + 1) << 32) | rec.id, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            mv.key |= line_reach<V>(s, mv, step);
             cur[n + i] = mv;
         }
         n += chunk;
@@ -393,7 +368,7 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
         if (r > 0) {
             // round r's movers are the losers of round r - 1 (this workgroup's share)
             n = commit_list<V>(s, (r & 1) ? s.res0 : s.res1, cur, nxt, n,
-                               (unsigned long long)tag << TAG_SHIFT, step, r == 1);
+                               (unsigned long long)tag << TAG_SHIFT);
             Mover *t = cur; cur = nxt; nxt = t;
         }
         if (tag >= TAG_LIMIT) {

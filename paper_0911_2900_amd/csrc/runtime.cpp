@@ -308,7 +308,6 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
                  o_seg = take(tcells * sizeof(fk::MoveRec)), o_ka = take(tcells * sizeof(fk::Mover)),
                  o_kb = take(tcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
-                 o_mcell = take(cells * 8),
                  o_mitems = take(fk::MOVE_GROUP_MAX * 4);
     void *block = nullptr;
     st = dev_alloc(c, off, &block);
@@ -330,7 +329,6 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
 
     sd.G = (const float *)(base + o_G);
     sd.occ = (int32_t *)(base + o_occ);
-    sd.mcell = (unsigned long long *)(base + o_mcell);
     sd.type = (const uint8_t *)(base + o_type);
     sd.tile_m = (const int32_t *)(base + o_tm);
     sd.tile_fb = (const uint8_t *)(base + o_fb);
@@ -366,7 +364,6 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     if (e == hipSuccess) e = hipMemset(base + o_scnt, 0, ntiles * 4);   // no movers planned yet
     cp(o_ctr, ctr.data(), fk::C_NCTR * 4);
     if (e == hipSuccess) e = hipMemset(base + o_stat, 0, fk::S_NSTAT * 8);
-    if (e == hipSuccess) e = hipMemset(base + o_mcell, 0, cells * 8);
     cp(o_items, items.data(), ntiles * 4);
     cp(o_self, &self, 4);
     cp(o_mitems, mitems.data(), mitems.size() * 4);
