@@ -217,9 +217,14 @@ __device__ unsigned long long line_reach(const SlotDev &s, const Mover &mv, int 
 
 // Check-and-commit for the workgroup's list (see the protocol above); movers
 // that cannot commit yet are appended to `nxt`.  Returns the number appended.
+// `fenced`: the last group barrier ended with an agent-scope acquire fence,
+// after which plain (cacheable) loads see every reservation of the round and
+// at least the occupancy at its start (commits of this round may or may not
+// be seen, which the protocol allows); without it (workgroup barriers only)
+// the loads go to the coherence point.
 template <int V>
 __device__ int commit_list(const SlotDev &s, const unsigned long long *res, const Mover *cur,
-                           Mover *nxt, int n, unsigned long long tagw)
+                           Mover *nxt, int n, unsigned long long tagw, bool fenced)
 {
     __shared__ int sh_cnt;
     const int Wp = s.Wp;
@@ -239,8 +244,14 @@ __device__ int commit_list(const SlotDev &s, const unsigned long long *res, cons
             int x = L.cx, y = L.cy;
             if (k <= me) L.at(k, x, y);
             cell[k] = y * Wp + x;
-            w[k] = (k >= 1 && k <= me) ? ld_res(&res[cell[k]]) : word;
-            o[k] = (k >= 1 && k <= me) ? ld_agent(&s.occ[cell[k]]) : -1;
+            const bool in = k >= 1 && k <= me;
+            if (fenced) {
+                w[k] = in ? res[cell[k]] : word;
+                o[k] = in ? s.occ[cell[k]] : -1;
+            } else {
+                w[k] = in ? ld_res(&res[cell[k]]) : word;
+                o[k] = in ? ld_agent(&s.occ[cell[k]]) : -1;
+            }
         }
         // j: the reach cells still enterable; the mover must hold all of them
         int j = me;
@@ -310,10 +321,17 @@ __device__ int gather_lists(const SlotDev &s, int G, const Mover *from, Mover *t
     return total;
 }
 
+__device__ __forceinline__ int lanes_below(unsigned long long mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 template <int V>
 __device__ void move_group(const SlotDev &s, int g, int G, int step)
 {
     __shared__ int sh_scan[MOVE_THREADS];
+    __shared__ int sh_kept;
     const int tid = threadIdx.x;
     const int T = s.ntx * s.nty, TC = s.tx * s.ty;
     // workgroup g takes tiles g, g + G, g + 2G, ...: every region of the grid
@@ -342,22 +360,40 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
             __syncthreads();
         }
         const int chunk = sh_scan[MOVE_THREADS - 1];
-        for (int i = tid; i < chunk; i += blockDim.x) {
-            int a = 0, b = nt - 1;                   // first tile whose inclusive count exceeds i
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                if (sh_scan[mid] > i) b = mid; else a = mid + 1;
-            }
-            const int k = i - (a ? sh_scan[a - 1] : 0);
-            const MoveRec rec = s.seg[(g + (long)(j0 + a) * G) * TC + k];
+        if (tid == 0) sh_kept = 0;
+        __syncthreads();
+        for (int i0 = 0; i0 < chunk; i0 += blockDim.x) {
+            const int i = i0 + tid;
             Mover mv;
-            mv.key = order_key(s, rec.id, step);
-            mv.cxy = rec.cxy;
-            mv.dxy = rec.dxy;
-            mv.key |= line_reach<V>(s, mv, step);
-            cur[n + i] = mv;
+            bool keep = false;
+            if (i < chunk) {
+                int a = 0, b = nt - 1;               // first tile whose inclusive count exceeds i
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (sh_scan[mid] > i) b = mid; else a = mid + 1;
+                }
+                const int k = i - (a ? sh_scan[a - 1] : 0);
+                const MoveRec rec = s.seg[(g + (long)(j0 + a) * G) * TC + k];
+                mv.key = order_key(s, rec.id, step);
+                mv.cxy = rec.cxy;
+                mv.dxy = rec.dxy;
+                mv.key |= line_reach<V>(s, mv, step);
+                // a mover blocked at its first cell never moves: at every
+                // other mover's turn it is still where it started, which is
+                // what they see without it taking part
+                keep = mover_reach(mv.key) > 0;
+            }
+            const unsigned long long m = __ballot(keep);
+            if (m) {
+                const int lane = __lane_id();
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&sh_kept, __popcll(m));
+                base = __shfl(base, 0);
+                if (keep) cur[n + base + lanes_below(m)] = mv;
+            }
         }
-        n += chunk;
+        __syncthreads();
+        n += sh_kept;
         __syncthreads();
     }
 
@@ -368,7 +404,7 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
         if (r > 0) {
             // round r's movers are the losers of round r - 1 (this workgroup's share)
             n = commit_list<V>(s, (r & 1) ? s.res0 : s.res1, cur, nxt, n,
-                               (unsigned long long)tag << TAG_SHIFT);
+                               (unsigned long long)tag << TAG_SHIFT, Gr > 1);
             Mover *t = cur; cur = nxt; nxt = t;
         }
         if (tag >= TAG_LIMIT) {
@@ -409,7 +445,7 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
 
 // mitems[i] = slot | g << 12 | (G - 1) << 22: workgroup g of the G that move
 // the slot's agents.
-__global__ __launch_bounds__(MOVE_THREADS) void move_kernel(const SlotDev *__restrict__ table,
+__global__ __launch_bounds__(MOVE_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void move_kernel(const SlotDev *__restrict__ table,
                                                             const uint32_t *__restrict__ mitems)
 {
     const uint32_t it = mitems[blockIdx.x];

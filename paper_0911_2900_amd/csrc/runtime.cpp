@@ -17,6 +17,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -202,24 +203,28 @@ uint32_t motion_item(int32_t slot, int g, int G)
     return (uint32_t)slot | ((uint32_t)g << 12) | ((uint32_t)(G - 1) << 22);
 }
 
-// Group sizes for a batch: the workgroups of scenarios that use a group
-// barrier must all fit on the device at once, with room to spare; larger
-// groups are shrunk until they do.
+// Group sizes for a batch.  Every workgroup of the motion launch must be
+// resident at once (group barriers), so the sizes share the device's
+// capacity: every scenario gets one workgroup, and the rest go one at a time
+// to the scenario with the most agents per workgroup (the one whose rounds
+// take longest), up to its own size alone.  A batch with more scenarios than
+// the capacity runs one workgroup each (those need no group barrier).
 std::vector<int> batch_groups(const fast_ctx *c, const std::vector<int32_t> &hs)
 {
-    std::vector<int> G(hs.size());
-    long total = 0;
-    for (size_t i = 0; i < hs.size(); ++i) {
-        G[i] = motion_group(c->slots[hs[i]].n_agents);
-        if (G[i] > 1) total += G[i];
-    }
-    const long cap = std::max(2, c->move_capacity / 2);
-    while (total > cap) {
-        total = 0;
-        for (size_t i = 0; i < hs.size(); ++i) {
-            if (G[i] > 1) G[i] = std::max(1, G[i] / 2);
-            if (G[i] > 1) total += G[i];
-        }
+    std::vector<int> G(hs.size(), 1);
+    long total = (long)hs.size();
+    const long cap = std::max(1, c->move_capacity);
+    using Item = std::pair<double, size_t>;          // (agents per workgroup, index)
+    std::priority_queue<Item> q;
+    for (size_t i = 0; i < hs.size(); ++i)
+        if (motion_group(c->slots[hs[i]].n_agents) > 1) q.push({(double)c->slots[hs[i]].n_agents, i});
+    while (total < cap && !q.empty()) {
+        const size_t i = q.top().second;
+        q.pop();
+        ++G[i];
+        ++total;
+        const int n = c->slots[hs[i]].n_agents;
+        if (G[i] < motion_group(n)) q.push({(double)n / G[i], i});
     }
     return G;
 }
