@@ -324,91 +324,107 @@ __device__ __forceinline__ uint32_t plan_draw_word(uint32_t id, uint32_t step, u
     return philox_word0(id, step, scn, STREAM_PLAN, k0, k1);
 }
 
-// V = v_max, TX = tile width (a power of two, 8..64): both fix the LDS pitch,
-// so every window offset of the agent loop is a compile-time constant.  SS
-// stages the floor-field window too (launches too small to hide the global
-// latency of the rare FP64 re-resolve).
-template <int V, int TX, bool DEBUG, bool SS>
-__device__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
-{
-    constexpr int SIDE = 2 * V + 1;
-    constexpr int Hc = (V + 3) & ~3;                          // column halo, a multiple of 4 >= V
-    constexpr int P = TX + 2 * Hc;                            // LDS pitch = staged width
-    constexpr int cpr = P >> 2;                               // 4-cell chunks per row
-    constexpr int hc4 = Hc >> 2;
-    constexpr int cw = TX >> 2;                               // interior chunks per row
-    constexpr int cw_log = __builtin_ctz(cw);
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    const int lane = __lane_id();
-    const int LY = s.ty + 2 * V;
-    const int n_in = cw * s.ty;                               // interior chunks (<= nthr)
-    const int n_top = V * cpr;                                // halo chunks: V rows above / below,
-    const int n_halo = 2 * n_top + s.ty * 2 * hc4;            // then hc4 chunks left and right
-    const int tile_y = tile / s.ntx, tile_x = tile - tile_y * s.ntx;
-    const int gx0 = tile_x * TX, gy0 = tile_y * s.ty + Hc - V;     // padded origin of the window
-    const int tstride = s.ntx + 2;
-    const bool fallback = s.tile_fb[tile_y * s.ntx + tile_x] != 0;
+// Geometry of one tile's staging: tile (tile_x, tile_y), the padded origin of
+// its window, and the 16-byte chunks of the window this thread stages (one
+// interior chunk, up to two halo chunks: V rows above and below, then hc4
+// chunks left and right of the interior).
+template <int V, int TX>
+struct TileGeom {
+    static constexpr int SIDE = 2 * V + 1;
+    static constexpr int Hc = (V + 3) & ~3;                   // column halo, a multiple of 4 >= V
+    static constexpr int P = TX + 2 * Hc;                     // LDS pitch = staged width
+    static constexpr int cpr = P >> 2;                        // 4-cell chunks per row
+    static constexpr int hc4 = Hc >> 2;
+    static constexpr int cw = TX >> 2;                        // interior chunks per row
+    static constexpr int cw_log = __builtin_ctz(cw);
+    int n_in, n_top, n_halo, tile_x, tile_y, gx0, gy0, ly_in, cc_in, ly_h[2], cc_h[2];
 
-    if (tid < 9) sh.m_nb[tid] = s.tile_m[(tile_y + tid / 3) * tstride + tile_x + tid % 3];
-    if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; sh.n_mov = 0; }
-    MoveRec *seg = s.seg + (long)tile * (TX * s.ty);
-
-    // --- stage the window: one interior chunk and up to two halo chunks per
-    // thread, 16-byte loads of occupancy and exp table, all issued first
-    const int ci = tid;
-    const int ly_in = V + (ci >> cw_log), cc_in = hc4 + (ci & (cw - 1));
-    int ly_h[2], cc_h[2];
+    __device__ __forceinline__ TileGeom(const SlotDev &s, int tile)
+    {
+        const int tid = threadIdx.x, nthr = blockDim.x;
+        n_in = cw * s.ty;                                     // interior chunks (<= nthr)
+        n_top = V * cpr;
+        n_halo = 2 * n_top + s.ty * 2 * hc4;
+        tile_y = tile / s.ntx;
+        tile_x = tile - tile_y * s.ntx;
+        gx0 = tile_x * TX;
+        gy0 = tile_y * s.ty + Hc - V;
+        ly_in = V + (tid >> cw_log);
+        cc_in = hc4 + (tid & (cw - 1));
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int h = tid + j * nthr;
-        int ly, cc;
-        if (h < 2 * n_top) {                                  // rows above, then rows below
-            const int hh = h < n_top ? h : h - n_top;
-            ly = (int)((unsigned)hh / cpr);
-            cc = hh - ly * cpr;
-            if (h >= n_top) ly += V + s.ty;
-        } else {                                              // left / right columns
-            const int hh = h - 2 * n_top;
-            const int r = (int)((unsigned)hh / (2 * hc4));
-            const int c = hh - r * 2 * hc4;
-            ly = V + r;
-            cc = c < hc4 ? c : c + cw;
+        for (int j = 0; j < 2; ++j) {
+            const int h = tid + j * nthr;
+            int ly, cc;
+            if (h < 2 * n_top) {                              // rows above, then rows below
+                const int hh = h < n_top ? h : h - n_top;
+                ly = (int)((unsigned)hh / cpr);
+                cc = hh - ly * cpr;
+                if (h >= n_top) ly += V + s.ty;
+            } else {                                          // left / right columns
+                const int hh = h - 2 * n_top;
+                const int rr = (int)((unsigned)hh / (2 * hc4));
+                const int c = hh - rr * 2 * hc4;
+                ly = V + rr;
+                cc = c < hc4 ? c : c + cw;
+            }
+            ly_h[j] = ly;
+            cc_h[j] = cc;
         }
-        ly_h[j] = ly;
-        cc_h[j] = cc;
     }
-    int4 o_in = make_int4(-1, -1, -1, -1), o_h0 = o_in, o_h1 = o_in;
-    float4 g_in = make_float4(0.f, 0.f, 0.f, 0.f), g_h0 = g_in, g_h1 = g_in;
-    double4 s_in{}, s_h0{}, s_h1{};
-    auto load_S = [&](int g, double4 &d) {
+};
+
+// What a thread loads from global memory to stage one tile.
+template <bool SS>
+struct StageRegs {
+    int4 o_in, o_h0, o_h1;
+    float4 g_in, g_h0, g_h1;
+    double4 s_in, s_h0, s_h1;                                 // floor field (SS only)
+    int mnb;                                                  // scale exponent of a neighbour tile
+    int fb;                                                   // the tile is a fallback tile
+};
+
+// Issues every global load of a tile's staging (16-byte chunks of occupancy,
+// exp table and, with SS, floor field; the 3x3 tile scale exponents; the
+// fallback flag) without waiting for any of them.
+template <int V, int TX, bool SS>
+__device__ __forceinline__ void stage_issue(const SlotDev &s, const TileGeom<V, TX> &tg,
+                                            StageRegs<SS> &r)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tstride = s.ntx + 2;
+    r.mnb = tid < 9 ? s.tile_m[(tg.tile_y + tid / 3) * tstride + tg.tile_x + tid % 3] : 0;
+    r.fb = s.tile_fb[tg.tile_y * s.ntx + tg.tile_x];
+    r.o_in = r.o_h0 = r.o_h1 = make_int4(-1, -1, -1, -1);
+    r.g_in = r.g_h0 = r.g_h1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto load = [&](int g, int4 &o, float4 &gv, double4 &d) {
+        o = *(const int4 *)(s.occ + g);
+        gv = *(const float4 *)(s.G + g);
         if constexpr (SS) {
-            const double2 a = *(const double2 *)(s.S + g), b = *(const double2 *)(s.S + g + 2);
-            d = double4{a.x, a.y, b.x, b.y};
+            const double2 x = *(const double2 *)(s.S + g), y = *(const double2 *)(s.S + g + 2);
+            d = double4{x.x, x.y, y.x, y.y};
         }
     };
-    if (ci < n_in) {
-        const int g = (gy0 + ly_in) * s.Wp + gx0 + 4 * cc_in;
-        o_in = *(const int4 *)(s.occ + g);
-        g_in = *(const float4 *)(s.G + g);
-        load_S(g, s_in);
-    }
-    if (tid < n_halo) {
-        const int g = (gy0 + ly_h[0]) * s.Wp + gx0 + 4 * cc_h[0];
-        o_h0 = *(const int4 *)(s.occ + g);
-        g_h0 = *(const float4 *)(s.G + g);
-        load_S(g, s_h0);
-    }
-    if (tid + nthr < n_halo) {
-        const int g = (gy0 + ly_h[1]) * s.Wp + gx0 + 4 * cc_h[1];
-        o_h1 = *(const int4 *)(s.occ + g);
-        g_h1 = *(const float4 *)(s.G + g);
-        load_S(g, s_h1);
-    }
-    // the step counter is read while the staging loads are in flight
-    const int step = s.ctr[C_STEP];
-    if (step >= s.ctr[C_LIMIT]) return;                       // scenario finished: nothing to do
-    if (tile == 0 && tid < 4) s.ctr[C_BAR + tid] = 0;          // fresh motion barriers
+    if (tid < tg.n_in) load((tg.gy0 + tg.ly_in) * s.Wp + tg.gx0 + 4 * tg.cc_in, r.o_in, r.g_in, r.s_in);
+    if (tid < tg.n_halo)
+        load((tg.gy0 + tg.ly_h[0]) * s.Wp + tg.gx0 + 4 * tg.cc_h[0], r.o_h0, r.g_h0, r.s_h0);
+    if (tid + nthr < tg.n_halo)
+        load((tg.gy0 + tg.ly_h[1]) * s.Wp + tg.gx0 + 4 * tg.cc_h[1], r.o_h1, r.g_h1, r.s_h1);
+}
+
+// Writes the staged tile into LDS (halo chunks rescaled to the tile's
+// exponent, occupied cells masked) and lists the tile's agents.  Only thread 0
+// may have touched the LDS counters since the workgroup's last barrier.
+template <int V, int TX, bool SS>
+__device__ __forceinline__ void stage_commit(const SlotDev &s, const TileGeom<V, TX> &tg,
+                                             PlanShared<SS> &sh, const StageRegs<SS> &r)
+{
+    using T = TileGeom<V, TX>;
+    constexpr int P = T::P, hc4 = T::hc4, cw = T::cw;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = __lane_id();
+    const int ci = tid, n_in = tg.n_in, n_halo = tg.n_halo, ly_in = tg.ly_in, cc_in = tg.cc_in;
+    const int *ly_h = tg.ly_h, *cc_h = tg.cc_h;
+    if (tid < 9) sh.m_nb[tid] = r.mnb;
+    if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; sh.n_mov = 0; }
     __syncthreads();                                          // m_nb, counters ready
     const int mT = sh.m_nb[4];
 
@@ -428,23 +444,25 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
                         o.z < 0 ? ldexpf(gv.z, dm) : 0.f, o.w < 0 ? ldexpf(gv.w, dm) : 0.f);
     };
     if (tid < n_halo) {
-        stage_halo(ly_h[0], cc_h[0], o_h0, g_h0);
-        stage_S(ly_h[0] * P + 4 * cc_h[0], s_h0);
+        stage_halo(ly_h[0], cc_h[0], r.o_h0, r.g_h0);
+        stage_S(ly_h[0] * P + 4 * cc_h[0], r.s_h0);
     }
     if (tid + nthr < n_halo) {
-        stage_halo(ly_h[1], cc_h[1], o_h1, g_h1);
-        stage_S(ly_h[1] * P + 4 * cc_h[1], s_h1);
+        stage_halo(ly_h[1], cc_h[1], r.o_h1, r.g_h1);
+        stage_S(ly_h[1] * P + 4 * cc_h[1], r.s_h1);
     }
 
     // interior chunk: already in the tile's scale; its occupied cells are the
     // tile's agents (one LDS atomic per wavefront to list them)
     {
+        const int4 o_in = r.o_in;
+        const float4 g_in = r.g_in;
         const bool live = ci < n_in;
         const int l0 = ly_in * P + 4 * cc_in;
         if (live) {
             *(float4 *)&sh.Em[l0] = make_float4(o_in.x < 0 ? g_in.x : 0.f, o_in.y < 0 ? g_in.y : 0.f,
                                                 o_in.z < 0 ? g_in.z : 0.f, o_in.w < 0 ? g_in.w : 0.f);
-            stage_S(l0, s_in);
+            stage_S(l0, r.s_in);
         }
         const int ov[4] = {o_in.x, o_in.y, o_in.z, o_in.w};
         const float gv[4] = {g_in.x, g_in.y, g_in.z, g_in.w};
@@ -471,6 +489,22 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
         }
     }
     __syncthreads();
+}
+
+// The draws of a staged tile: one lane per agent (FP32 from the LDS table,
+// flagged draws re-resolved in FP64 by their wavefront), or every draw in
+// FP64 on a fallback tile; movers go to the tile's record segment.  Ends with
+// a workgroup barrier after which only thread 0 touches the LDS counters.
+template <int V, int TX, bool DEBUG, bool SS>
+__device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, TX> &tg, int tile,
+                                            PlanShared<SS> &sh, int step, bool fallback)
+{
+    using T = TileGeom<V, TX>;
+    constexpr int SIDE = T::SIDE, P = T::P, Hc = T::Hc;
+    (void)Hc;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = __lane_id();
+    const int gx0 = tg.gx0, gy0 = tg.gy0;
+    MoveRec *seg = s.seg + (long)tile * (TX * s.ty);
     const int na = sh.n_agents;
     const uint32_t kseed0 = s.seed_lo, kseed1 = s.seed_hi;
     const uint32_t scn = s.scn;          // held in registers: the loops below store to memory
@@ -625,11 +659,30 @@ __device__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
         }
     }
     __syncthreads();
-    const int nf = sh.n_flag;
     if (tid == 0) {
+        const int nf = sh.n_flag;
         s.seg_cnt[tile] = sh.n_mov;
         if (nf) atomicAdd(&s.stat[S_FLAGGED], (unsigned long long)nf);
     }
+}
+
+
+// One tile, V = v_max, TX = tile width (a power of two, 8..64): both fix the
+// LDS pitch, so every window offset of the agent loop is a compile-time
+// constant.  SS stages the floor-field window too (launches too small to hide
+// the global latency of the rare FP64 re-resolve).
+template <int V, int TX, bool DEBUG, bool SS>
+__device__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
+{
+    const TileGeom<V, TX> tg(s, tile);
+    StageRegs<SS> r;
+    stage_issue<V, TX, SS>(s, tg, r);
+    // the step counter is read while the staging loads are in flight
+    const int step = s.ctr[C_STEP];
+    if (step >= s.ctr[C_LIMIT]) return;                       // scenario finished: nothing to do
+    if (tile == 0 && threadIdx.x < 4) s.ctr[C_BAR + threadIdx.x] = 0;   // fresh motion barriers
+    stage_commit<V, TX, SS>(s, tg, sh, r);
+    plan_agents<V, TX, DEBUG, SS>(s, tg, tile, sh, step, r.fb != 0);
 }
 
 template <int V, bool DEBUG, bool SS>

@@ -359,3 +359,40 @@ def test_sequential_fp64_resolve_path(ctx, monkeypatch, v):
         o.run(15)
         compare_state(ctx, o, h, where=m.name)
         ctx.destroy(h)
+
+
+def _uniform_batch_vs_oracle(ctx, members, tile, steps):
+    hs = [ctx.init_from(m, tile=tile, batched=True) for m in members]
+    sims = [oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents) for m in members]
+    cores = oracle.num_threads()
+    for step in range(steps):
+        ctx.plan_batch(hs)
+        for sim in sims:
+            sim.plan_omp(cores)
+        for m, sim, h in zip(members, sims, hs):
+            st = ctx.state(h)
+            alive = sim.alive[: sim.n].astype(bool)
+            bad = np.nonzero(st["desired"][alive] != sim.desired[: sim.n][alive])[0]
+            assert len(bad) == 0, f"{m.name} step {step}: {len(bad)} desired cells differ"
+        ctx.move_batch(hs)
+        for sim in sims:
+            sim.move()
+            sim.end_step()
+    for m, sim, h in zip(members, sims, hs):
+        compare_state(ctx, sim, h, where=m.name)
+        ctx.destroy(h)
+
+
+def test_uniform_batch_large(ctx):
+    """Four 1000 x 1000 instances (v_m = 4, 64 x 16 tiles) planned in one
+    launch: a batch whose members share v_m and the tile shape takes the
+    planning kernel specialised for them."""
+    _uniform_batch_vs_oracle(ctx, [sc.large_member(k) for k in range(4)], (64, 16), 3)
+
+
+@pytest.mark.parametrize("v,tile", [(2, (16, 16)), (5, (32, 8))])
+def test_uniform_batch_rooms(ctx, v, tile):
+    """Eight 400 x 400 rooms sharing v_m and the tile shape, planned in one
+    launch by the specialised planning kernel."""
+    members = [sc.room(n_agents=12000, v=v, scn=20 + k) for k in range(8)]
+    _uniform_batch_vs_oracle(ctx, members, tile, 3)
