@@ -29,23 +29,20 @@ CANDIDATES = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8), (32, 16), (16, 32), (
 
 
 def _time_plan(ctx, torch, hs, reps: int) -> float:
-    """Median planning-launch time (ms) over `reps` launches for handles hs."""
-    stream = ctx.stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(reps)]
+    """Median planning-kernel time (ms) over `reps` launches for handles hs,
+    stamped by the launches themselves (the kernel's own start and end)."""
     torch.cuda.synchronize()
-    for a, b in ev:
-        a.record(stream)
+    ctx.timing_start(reps)
+    for _ in range(reps):
         if len(hs) == 1:
             ctx.plan(hs[0])
         else:
             ctx.plan_batch(hs)
-        b.record(stream)
-    torch.cuda.synchronize()
-    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+    ms = ctx.timing_read()
+    return float(np.median(ms))
 
 
-def tune(ctx, scenarios, candidates=None, reps: int = 15, warm_steps: int = 2):
+def tune(ctx, scenarios, candidates=None, reps: int = 31, warm_steps: int = 2):
     """Returns ((tx, ty), {tile: ms}) for the list of scenarios planned together."""
     import torch
 

@@ -53,20 +53,21 @@ __device__ __forceinline__ void load_row(const float *Eb, float ec, float (&x)[2
     }
 }
 
-// Row sums, software-pipelined by one row: the loads of row R+1 are issued
+// Row sums, software-pipelined by two rows: the loads of row R+2 are issued
 // before row R is summed, and the scheduling barrier keeps later rows from
-// being hoisted, so at most two rows of values are live.
+// being hoisted, so at most three rows of values are live.
 template <int V, int P, int R>
 struct RowPipe {
     static __device__ __forceinline__ void run(const float *Eb, float ec, float *Rs,
-                                               const float (&cur)[2 * V + 1])
+                                               const float (&cur)[2 * V + 1],
+                                               const float (&nx1)[2 * V + 1])
     {
         constexpr int a = half_width(V, R - V);
-        float nxt[2 * V + 1];
-        if constexpr (R + 1 < 2 * V + 1) load_row<V, P, R + 1>(Eb, ec, nxt);
+        float nx2[2 * V + 1];
+        if constexpr (R + 2 < 2 * V + 1) load_row<V, P, R + 2>(Eb, ec, nx2);
         Rs[R] = Tree<2 * a + 1, 0>::sum(cur);
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (R + 1 < 2 * V + 1) RowPipe<V, P, R + 1>::run(Eb, ec, Rs, nxt);
+        if constexpr (R + 1 < 2 * V + 1) RowPipe<V, P, R + 1>::run(Eb, ec, Rs, nx1, nx2);
     }
 };
 
@@ -556,13 +557,14 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
 
             const float *Eb = sh.Em + (l - V * P - V);      // window origin (dy, dx) = (-V, -V)
-            float Rs[SIDE], row0[SIDE];
+            float Rs[SIDE], row0[SIDE], row1[SIDE];
             load_row<V, P, 0>(Eb, ec, row0);
+            load_row<V, P, 1>(Eb, ec, row1);
             __builtin_amdgcn_sched_barrier(0);
-            // the draw's counter-based word overlaps the first row's LDS reads
+            // the draw's counter-based word overlaps the first rows' LDS reads
             const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0, kseed1);
             __builtin_amdgcn_sched_barrier(0);
-            RowPipe<V, P, 0>::run(Eb, ec, Rs, row0);
+            RowPipe<V, P, 0>::run(Eb, ec, Rs, row0, row1);
             float Pr[SIDE + 1];
             Pr[0] = 0.0f;
             Pr[1] = Rs[0];
