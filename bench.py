@@ -337,6 +337,66 @@ def cpu_baseline(budget_s: float = 15.0, max_steps: int = 396, v: int = 4):
     }
 
 
+def sweep_v(ctx, torch, warmup: int, steps: int):
+    """The room at v_m = 1..5 (40,000 agents): planning agent-updates/s from
+    the kernel times, and the whole step."""
+    out = []
+    from paper_0911_2900_amd import scenarios as sc
+
+    for v in (1, 2, 3, 4, 5):
+        r = bench_room(ctx, torch, warmup, steps, v=v)
+        out.append({"v_m": v, "planning_agent_updates_per_s": r["planned"] / (sum(r["plan_ms"]) / 1e3),
+                    "plan_us": float(np.mean(r["plan_ms"])) * 1e3,
+                    "whole_step_us": r["total_ms"] / steps * 1e3,
+                    "tile": [r["stats"]["tile_w"], r["stats"]["tile_h"]],
+                    "flagged_per_step": r["stats"]["flagged"] / (warmup + steps)})
+        log(f"v_m={v}: {out[-1]}")
+    return out
+
+
+def cpu_table(budget_steps: int = 5):
+    """The oracle on the host: one thread, and its OpenMP planning loop on
+    every host thread, per workload (planning agent-updates/s and whole steps
+    per second; the room, ensemble and 1000 x 1000 rows time the first
+    `budget_steps` steps, the corridor its full 396)."""
+    import oracle
+    from paper_0911_2900_amd import scenarios as sc
+
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    rows = []
+
+    def time_sim(name, members, steps, extrapolate=1.0):
+        for threads in (1, cores):
+            sims = [oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents) for m in members]
+            planned, plan_s, t0 = 0, 0.0, time.perf_counter()
+            for _ in range(steps):
+                for sim in sims:
+                    n = sim.n_alive()
+                    t1 = time.perf_counter()
+                    if threads == 1:
+                        sim.plan()
+                    else:
+                        sim.plan_omp(threads)
+                    plan_s += time.perf_counter() - t1
+                    planned += n
+                    sim.move()
+                    sim.end_step()
+            whole = time.perf_counter() - t0
+            rows.append({"workload": name, "threads": threads, "steps": steps,
+                         "planning_agent_updates_per_s": planned / plan_s,
+                         "whole_steps_per_s": steps / whole / extrapolate,
+                         "extrapolated_from": f"{len(members)} of {int(len(members) * extrapolate)} "
+                                              "scenarios" if extrapolate != 1.0 else None})
+            log(rows[-1])
+
+    time_sim("corridor 60x25, 200 agents, v_m=4", [sc.corridor()], 396)
+    for v in (1, 2, 3, 4, 5):
+        time_sim(f"room 400x400, 40,000 agents, v_m={v}", [sc.room(v=v)], budget_steps)
+    time_sim("ensemble, 256 scenarios", sc.ensemble(256), budget_steps)
+    time_sim("16 x 1000x1000, 200,000 agents each", [sc.large_member(0)], budget_steps, 16.0)
+    return {"cores": cores, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +416,11 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests in the open-loop serving run (0 = no serving run)")
     ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--sweep-v", action="store_true",
+                    help="only time the room at v_m = 1..5 and print one JSON line")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the oracle on the host (one thread and all threads) per "
+                         "workload and print one JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -363,6 +428,9 @@ def main():
               "has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.cpu_table:
+        print(json.dumps(cpu_table()), flush=True)
+        return
     import torch
     from paper_0911_2900_amd import fast
 
@@ -380,6 +448,10 @@ def main():
         log(f"copied {n} bytes 5 times")
         return
     ctx = fast.Context(device=0)
+    if args.sweep_v:
+        print(json.dumps({"sweep_v": sweep_v(ctx, torch, args.warmup, args.steps)}), flush=True)
+        ctx.close()
+        return
     log(f"room: warmup {args.warmup}, timed {args.steps} steps")
     r = bench_room(ctx, torch, args.warmup, args.steps)
     plan_s = sum(r["plan_ms"]) / 1e3
