@@ -94,10 +94,10 @@ def window_cells(cell_type: np.ndarray, xy: np.ndarray, v: int) -> int:
     return int(binary_dilation(occ, structure=disc).sum())
 
 
-def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4):
+def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4, n_agents: int = 40000):
     from paper_0911_2900_amd import scenarios as sc
 
-    s = sc.room(v=v)
+    s = sc.room(v=v, n_agents=n_agents)
     h = ctx.init_from(s)
     for _ in range(warmup):
         ctx.plan(h)
@@ -354,6 +354,32 @@ def sweep_v(ctx, torch, warmup: int, steps: int):
     return out
 
 
+def sweep_n(ctx, torch, warmup: int, steps: int):
+    """The room at v_m = 4 with 5,000 .. 150,000 agents (160,000 would exceed
+    its 158,404 free interior cells): planning agent-updates/s and the whole
+    step."""
+    out = []
+    for n in (5000, 10000, 20000, 40000, 80000, 150000):
+        r = bench_room(ctx, torch, warmup, steps, v=4, n_agents=n)
+        out.append({"agents": n, "planning_agent_updates_per_s": r["planned"] / (sum(r["plan_ms"]) / 1e3),
+                    "plan_us": float(np.mean(r["plan_ms"])) * 1e3,
+                    "whole_step_us": r["total_ms"] / steps * 1e3,
+                    "tile": [r["stats"]["tile_w"], r["stats"]["tile_h"]]})
+        log(f"N={n}: {out[-1]}")
+    return out
+
+
+def achievable(ctx, achieved_gbs: float, footprint: float, stream_4g: float) -> dict:
+    """The planning launch's algorithmic rate against what the streaming
+    kernel reaches beyond the cache (4 GiB) and at the launch's own
+    footprint (cache-resident)."""
+    same, same_us = ctx.stream_bandwidth(int(footprint), 50)
+    return {"stream_4GiB_GBs": stream_4g, "stream_same_footprint_GBs": same,
+            "stream_same_footprint_us": same_us,
+            "frac_of_stream_4GiB": achieved_gbs / stream_4g,
+            "frac_of_stream_same_footprint": achieved_gbs / same}
+
+
 def cpu_table(budget_steps: int = 5):
     """The oracle on the host: one thread, and its OpenMP planning loop on
     every host thread, per workload (planning agent-updates/s and whole steps
@@ -410,12 +436,15 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 5 times (the reference "
                          "kernel for scaling the HBM traffic counters) and exit")
-    ap.add_argument("--room-replicas", type=int, default=0,
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--room-replicas", type=int, default=64,
                     help="also time the planning launch over this many copies of the room")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests in the open-loop serving run (0 = no serving run)")
     ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--sweep-n", action="store_true",
+                    help="only the room at v_m = 4 with 5k .. 150k agents")
     ap.add_argument("--sweep-v", action="store_true",
                     help="only time the room at v_m = 1..5 and print one JSON line")
     ap.add_argument("--cpu-table", action="store_true",
@@ -452,6 +481,10 @@ def main():
         print(json.dumps({"sweep_v": sweep_v(ctx, torch, args.warmup, args.steps)}), flush=True)
         ctx.close()
         return
+    if args.sweep_n:
+        print(json.dumps({"sweep_n": sweep_n(ctx, torch, args.warmup, args.steps)}), flush=True)
+        ctx.close()
+        return
     log(f"room: warmup {args.warmup}, timed {args.steps} steps")
     r = bench_room(ctx, torch, args.warmup, args.steps)
     plan_s = sum(r["plan_ms"]) / 1e3
@@ -478,6 +511,17 @@ def main():
         replicas = bench_batch_plan(ctx, torch, rooms, f"{args.room_replicas} x room 400x400, "
                                     "40,000 agents, v_m=4, one planning launch", 2, args.large_steps)
         log(f"replicas: {replicas}")
+
+    room_ach = None
+    if not args.no_stream:
+        stream4, _ = ctx.stream_bandwidth(4 << 30, 20)
+        log(f"stream kernel, 4 GiB footprint: {stream4:.1f} GB/s")
+        room_ach = achievable(ctx, achieved, bytes_per_launch, stream4)
+        for x in (large, replicas):
+            if x is not None:
+                x["roofline"]["achievable"] = achievable(ctx, x["roofline"]["achieved"],
+                                                         x["roofline"]["bytes_per_launch"], stream4)
+        log(f"achievable: room {room_ach}")
 
     ens = None
     if not args.no_ensemble:
@@ -524,7 +568,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("room"),
             "kernel": "plan_kernel_one", "bytes_per_launch": bytes_per_launch,
-            "avg_launch_us": avg_plan_ms * 1e3,
+            "avg_launch_us": avg_plan_ms * 1e3, "achievable": room_ach,
         },
         "ensemble": ens,
         "large": large,

@@ -196,6 +196,20 @@ fast_status fast_timing_start(fast_ctx *ctx, int32_t max_launches);
  * number timed, and stops timing. */
 fast_status fast_timing_read(fast_ctx *ctx, float *ms, int32_t cap, int32_t *n);
 
+/* ---- Bandwidth yardstick ------------------------------------------------- */
+
+/* Measures what a streaming kernel reaches at a given footprint: six arrays
+ * of footprint/96 float4 each (rounded down), out = a + b + c + d + e, five
+ * reads for each write.  The arrays come from the context allocator and are
+ * freed before returning.  After two untimed launches, `reps` launches are
+ * timed by the kernel's own start and end events; *gb_per_s = bytes moved
+ * per launch / average duration, *us_per_launch (may be NULL) = that
+ * duration in microseconds.  Synchronises the context stream.
+ * FAST_E_INVALID unless 96 <= footprint <= 64 GiB and 1 <= reps <= 10000;
+ * FAST_E_BUDGET / FAST_E_NOMEM if the arrays do not fit. */
+fast_status fast_stream_bandwidth(fast_ctx *ctx, size_t footprint, int32_t reps, double *gb_per_s,
+                                  double *us_per_launch);
+
 /* ---- Serving: continuous batching of scenario requests ------------------ */
 
 /* Starts serving on host threads of the context.  Builder threads (half the

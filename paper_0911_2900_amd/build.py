@@ -19,7 +19,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["plan_batch.hip", "plan_one.hip", "motion.hip", "builder.cpp", "runtime.cpp"]
+SOURCES = ["plan_batch.hip", "plan_one.hip", "motion.hip", "stream.hip", "builder.cpp",
+           "runtime.cpp"]
 
 
 def _run(cmd):

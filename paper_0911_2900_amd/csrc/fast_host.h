@@ -44,3 +44,5 @@ extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, i
 extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,
                                      hipStream_t stream);
 extern "C" hipError_t fk_move_capacity(int *blocks);
+extern "C" hipError_t fk_launch_stream(float4 *base, size_t n4, hipStream_t stream,
+                                       hipEvent_t start, hipEvent_t stop);

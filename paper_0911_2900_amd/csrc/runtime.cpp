@@ -1008,6 +1008,41 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     return FAST_OK;
 }
 
+fast_status fast_stream_bandwidth(fast_ctx *c, size_t footprint, int32_t reps, double *gb_per_s,
+                                  double *us_per_launch)
+{
+    if (!c || !gb_per_s || reps < 1 || reps > 10000 || footprint < 96 || footprint > ((size_t)64 << 30))
+        return fail(FAST_E_INVALID, "bad arguments to fast_stream_bandwidth");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    const size_t n4 = footprint / 96;                          // six arrays of n4 float4
+    const size_t bytes = n4 * 96;
+    void *block = nullptr;
+    fast_status st = dev_alloc(c, bytes, &block);
+    if (st) return st;
+    std::vector<hipEvent_t> ev((size_t)2 * (reps + 2), nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess) e = hipMemsetAsync(block, 0, bytes, c->stream);
+    for (int i = 0; i < reps + 2 && e == hipSuccess; ++i)       // two untimed launches first
+        e = fk_launch_stream((float4 *)block, n4, c->stream, ev[2 * i], ev[2 * i + 1]);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    double total_ms = 0.0;
+    for (int i = 2; i < reps + 2 && e == hipSuccess; ++i) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+        total_ms += ms;
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    dev_free(c, block, bytes);
+    if (e != hipSuccess) return fail(FAST_E_DEVICE, "stream bandwidth: %s", hipGetErrorString(e));
+    const double avg_s = total_ms / reps / 1e3;
+    *gb_per_s = (double)bytes / avg_s / 1e9;
+    if (us_per_launch) *us_per_launch = avg_s * 1e6;
+    return FAST_OK;
+}
+
 fast_status fast_serve_start(fast_ctx *c, size_t budget, int32_t max_active)
 {
     if (!c || max_active < 0) return fail(FAST_E_INVALID, "bad arguments to fast_serve_start");

@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         "fast_debug_plan": [P, I32, P, P, P],
         "fast_timing_start": [P, I32],
         "fast_timing_read": [P, P, I32, P],
+        "fast_stream_bandwidth": [P, ctypes.c_size_t, I32, P, P],
         "fast_serve_start": [P, ctypes.c_size_t, I32],
         "fast_serve_submit": [P, P, I32, P],
         "fast_serve_poll": [P, U64, P, P],
@@ -274,6 +275,14 @@ class Context:
         n = ctypes.c_int32(0)
         _check(lib().fast_timing_read(self.ctx, _ptr(ms), cap, ctypes.byref(n)))
         return ms[: min(n.value, cap)].copy()
+
+    def stream_bandwidth(self, footprint: int, reps: int = 20) -> tuple:
+        """(GB/s, us per launch) of the 5-read/1-write streaming kernel at
+        this footprint in bytes."""
+        gbs, us = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(lib().fast_stream_bandwidth(self.ctx, int(footprint), int(reps), ctypes.byref(gbs),
+                                           ctypes.byref(us)))
+        return gbs.value, us.value
 
     # -- serving -----------------------------------------------------------
     def serve_start(self, budget: int = 0, max_active: int = 0):

@@ -257,6 +257,22 @@ def test_state_errors(ctx):
     ctx.destroy(h)
 
 
+
+def test_stream_bandwidth_yardstick(ctx):
+    """The bandwidth yardstick runs at a small and a cache-exceeding
+    footprint, reports a plausible rate, and rejects bad sizes."""
+    from paper_0911_2900_amd import fast
+    say("stream bandwidth: 1 MiB and 512 MiB footprints")
+    small, us_small = ctx.stream_bandwidth(1 << 20, 5)
+    big, us_big = ctx.stream_bandwidth(512 << 20, 5)
+    assert 0.0 < small and 0.0 < us_small
+    assert 100.0 < big < 20000.0 and us_big > us_small
+    for bad in (0, 95, (64 << 30) + 1):
+        with pytest.raises(fast.FastError):
+            ctx.stream_bandwidth(bad, 5)
+    with pytest.raises(fast.FastError):
+        ctx.stream_bandwidth(1 << 20, 0)
+
 # ---------------------------------------------------------------------------
 # batched runs: every scenario in the mix equals the oracle and itself alone
 # ---------------------------------------------------------------------------
