@@ -21,6 +21,9 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 
 SOURCES = ["plan_batch.hip", "plan_one.hip", "motion.hip", "stream.hip", "builder.cpp",
            "runtime.cpp"]
+# plan_fixed.hip is compiled once per v_max (PLAN_V), into one object each.
+FIXED = "plan_fixed.hip"
+V_MAX = 5
 
 
 def _run(cmd):
@@ -31,11 +34,12 @@ def _run(cmd):
     return r
 
 
-def _compile_cmd(src: str):
+def _compile_cmd(src: str, v: int = 0):
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
+    obj = os.path.join(BUILD, src + (f".v{v}" if v else "") + ".o")
     if src.endswith(".hip"):
-        cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, "-c", path, "-o", obj]
+        defs = [f"-DPLAN_V={v}"] if v else []
+        cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, *defs, "-c", path, "-o", obj]
     else:
         cmd = [CLANGXX, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON,
                "-c", path, "-o", obj]
@@ -48,7 +52,8 @@ def build(verbose: bool = False) -> str:
     from concurrent.futures import ThreadPoolExecutor
 
     os.makedirs(BUILD, exist_ok=True)
-    jobs = [_compile_cmd(src) for src in SOURCES]
+    jobs = [_compile_cmd(FIXED, v) for v in range(V_MAX, 0, -1)]
+    jobs += [_compile_cmd(src) for src in SOURCES]
     if verbose:
         for cmd, _ in jobs:
             print(" ".join(cmd), flush=True)

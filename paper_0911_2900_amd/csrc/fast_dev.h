@@ -39,6 +39,8 @@ constexpr int MAX_V = 5;
 constexpr int MAX_TILE_CELLS = 1024;   // tx * ty
 constexpr int MAX_STAGE = 2368;        // (tx + 2 pad) * (ty + 2v) over the allowed tiles
 constexpr int PLAN_THREADS = 256;
+constexpr int ONE_MAX_THREADS = 1024;     // single-scenario planning launches: up to one thread per tile cell
+constexpr int ONE_STAGE_S_TILES = 2048;   // ... and the floor field staged in LDS up to this many tiles
 constexpr int MOVE_THREADS = 1024;
 constexpr int MOVE_GROUP_MAX = 64;        // workgroups per scenario in the motion phase
 constexpr int MOVE_SOLO_MAX = 256;        // movers left at which one workgroup takes over
@@ -80,7 +82,7 @@ struct Mover {
 constexpr unsigned long long KEY_MASK = (1ull << 52) - 1ull;
 constexpr int MEFF_SHIFT = 52, HP_SHIFT = 55, EXIT_BIT = 60;
 
-// A mover as planned: agent id and packed start / target cells.
+// A planned agent: id and packed start / chosen cells (equal when it stays).
 struct MoveRec {
     uint32_t id, cxy, dxy;
 };
@@ -108,7 +110,7 @@ struct SlotDev {
     int32_t *occ;            // Wp*Hp
     unsigned long long *res0;// Wp*Hp, reservations of even rounds
     unsigned long long *res1;// Wp*Hp, reservations of odd rounds
-    int32_t *seg_cnt;        // ntx*nty: movers planned per tile
+    int32_t *seg_cnt;        // ntx*nty: agents planned per tile
     MoveRec *seg;            // ntx*nty*tx*ty: their records, tile by tile
     Mover *mv_a, *mv_b;      // ntx*nty*tx*ty each: movers of the current / next round
     int32_t *ctr;            // C_NCTR

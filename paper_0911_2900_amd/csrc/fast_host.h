@@ -37,8 +37,26 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
 
 }  // namespace fh
 
+// Batched planning: v, tx = the v_max and tile width shared by every item's
+// scenario (the specialised kernels), or 0, 0 for a mixed batch.
 extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
-                                     hipStream_t stream, hipEvent_t start, hipEvent_t stop);
+                                     int v, int tx, hipStream_t stream, hipEvent_t start,
+                                     hipEvent_t stop);
+// plan_fixed.hip, one object per v_max.
+#define FK_FIXED_LAUNCHERS(V)                                                                     \
+    extern "C" hipError_t fk_launch_plan_fixed_v##V(int tx, const fk::SlotDev *table,              \
+                                                    const uint32_t *items, int n_items,            \
+                                                    hipStream_t stream, hipEvent_t start,          \
+                                                    hipEvent_t stop);                              \
+    extern "C" hipError_t fk_launch_plan_one_fixed_v##V(const fk::SlotDev *slot, int n_tiles,      \
+                                                        hipStream_t stream, hipEvent_t start,      \
+                                                        hipEvent_t stop);
+FK_FIXED_LAUNCHERS(1)
+FK_FIXED_LAUNCHERS(2)
+FK_FIXED_LAUNCHERS(3)
+FK_FIXED_LAUNCHERS(4)
+FK_FIXED_LAUNCHERS(5)
+#undef FK_FIXED_LAUNCHERS
 extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, int debug,
                                          hipStream_t stream, hipEvent_t start, hipEvent_t stop);
 extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,

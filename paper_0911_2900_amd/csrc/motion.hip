@@ -346,7 +346,7 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
     if (g == 0 && tid == 0)   // agents planned this step, for the throughput counters
         atomicAdd(&s.stat[S_PLANNED], (unsigned long long)s.ctr[C_NACTIVE]);
 
-    // gather this workgroup's movers (the records of its tiles) with their
+    // gather this workgroup's movers (from the records of its tiles) with their
     // priority words [~x0:32][~id:20] (larger = earlier)
     int n = 0;
     for (int j0 = 0; j0 < nt_g; j0 += MOVE_THREADS) {
@@ -374,14 +374,16 @@ __device__ void move_group(const SlotDev &s, int g, int G, int step)
                 }
                 const int k = i - (a ? sh_scan[a - 1] : 0);
                 const MoveRec rec = s.seg[(g + (long)(j0 + a) * G) * TC + k];
-                mv.key = order_key(s, rec.id, step);
-                mv.cxy = rec.cxy;
-                mv.dxy = rec.dxy;
-                mv.key |= line_reach<V>(s, mv, step);
-                // a mover blocked at its first cell never moves: at every
-                // other mover's turn it is still where it started, which is
-                // what they see without it taking part
-                keep = mover_reach(mv.key) > 0;
+                // an agent that stays, or a mover blocked at its first cell,
+                // never moves: at every other mover's turn it is still where
+                // it started, which is what they see without it taking part
+                if (rec.dxy != rec.cxy) {
+                    mv.key = order_key(s, rec.id, step);
+                    mv.cxy = rec.cxy;
+                    mv.dxy = rec.dxy;
+                    mv.key |= line_reach<V>(s, mv, step);
+                    keep = mover_reach(mv.key) > 0;
+                }
             }
             const unsigned long long m = __ballot(keep);
             if (m) {

@@ -1,8 +1,11 @@
-// plan_batch.hip -- the batched planning kernel: one launch plans the tiles
-// of many scenarios (uneven grids, agent counts, v_max and tile shapes), one
-// workgroup per tile.
+// plan_batch.hip -- the batched planning launch: one launch plans the tiles of
+// many scenarios, one workgroup per tile.  A batch whose scenarios share
+// v_max and tile width runs the kernel specialised to that shape
+// (plan_fixed.hip); a mixed batch (uneven grids, agent counts, v_max and tile
+// shapes) runs this kernel, which dispatches per tile on the device.
 #include <hip/hip_ext.h>
 
+#include "fast_host.h"
 #include "plan_tile.h"
 
 namespace fk {
@@ -19,11 +22,23 @@ void plan_kernel(const SlotDev *__restrict__ table, const uint32_t *__restrict__
 
 }  // namespace fk
 
-// start / stop (optional): events that record the kernel's own start and end.
+// v, tx: the shared v_max and tile width of every item's scenario, or 0 for a
+// mixed batch.  start / stop (optional): events that record the kernel's own
+// start and end.
 extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
-                                     hipStream_t stream, hipEvent_t start, hipEvent_t stop)
+                                     int v, int tx, hipStream_t stream, hipEvent_t start,
+                                     hipEvent_t stop)
 {
     if (n_items <= 0) return hipSuccess;
+    switch (v) {
+        case 0: break;
+        case 1: return fk_launch_plan_fixed_v1(tx, table, items, n_items, stream, start, stop);
+        case 2: return fk_launch_plan_fixed_v2(tx, table, items, n_items, stream, start, stop);
+        case 3: return fk_launch_plan_fixed_v3(tx, table, items, n_items, stream, start, stop);
+        case 4: return fk_launch_plan_fixed_v4(tx, table, items, n_items, stream, start, stop);
+        case 5: return fk_launch_plan_fixed_v5(tx, table, items, n_items, stream, start, stop);
+        default: return hipErrorInvalidValue;
+    }
     hipExtLaunchKernelGGL(fk::plan_kernel, dim3(n_items), dim3(fk::PLAN_THREADS), 0, stream, start,
                           stop, 0, table, items);
     return hipGetLastError();

@@ -6,8 +6,8 @@
 // LDS; the tile's agents are found by scanning its occupancy; one lane per
 // agent forms the weights, the CDF over the reach disc and the Philox draw in
 // FP32; draws inside the guard band are re-resolved in FP64 by a whole
-// wavefront.  The tile's movers are written as (id, start, target) records to
-// the tile's own segment.
+// wavefront.  Each agent's (id, cell, chosen cell) record is written to its
+// slot of the tile's own segment.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,17 +39,41 @@ struct Tree<1, O> {
     static __device__ __forceinline__ float sum(const float *x) { return x[O]; }
 };
 
-// Row R (dy = R - V) of the reach disc: its 2a+1 masked exp values, read
-// from Eb = the agent's window origin (row -V, column -V) with pitch P; the
+// An agent's (2V+1)-row window in the staged table (pitch P), from its
+// origin (row -V, column -V) at LDS index eo >= 0.  Rows are grouped under
+// separate base registers so that every read is a non-negative immediate
+// offset of at most 255 words from its group's base, the reach of a paired
+// LDS read; the empty asm keeps the compiler from folding the bases back
+// into one address with negative or out-of-range offsets.
+template <int V, int P>
+struct Window {
+    static constexpr int G = (255 - 2 * V) / P + 1;          // rows per base
+    static constexpr int NB = (2 * V + G) / G;                // ceil((2V + 1) / G)
+    const float *b[NB];
+    __device__ __forceinline__ Window(const float *Em, int eo)
+    {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            int o = eo + i * G * P;
+            asm volatile("" : "+v"(o));
+            b[i] = Em + o;
+        }
+    }
+    template <int R>
+    __device__ __forceinline__ const float *row() const { return b[R / G] + (R % G) * P; }
+};
+
+// Row R (dy = R - V) of the reach disc: its 2a+1 masked exp values; the
 // agent's own cell takes e_c.
 template <int V, int P, int R>
-__device__ __forceinline__ void load_row(const float *Eb, float ec, float (&x)[2 * V + 1])
+__device__ __forceinline__ void load_row(const Window<V, P> &w, float ec, float (&x)[2 * V + 1])
 {
     constexpr int a = half_width(V, R - V);
+    const float *rp = w.template row<R>();
 #pragma unroll
     for (int k = 0; k <= 2 * a; ++k) {
         if (R == V && k == a) x[k] = ec;
-        else x[k] = Eb[R * P + (V - a) + k];
+        else x[k] = rp[(V - a) + k];
     }
 }
 
@@ -58,16 +82,16 @@ __device__ __forceinline__ void load_row(const float *Eb, float ec, float (&x)[2
 // being hoisted, so at most three rows of values are live.
 template <int V, int P, int R>
 struct RowPipe {
-    static __device__ __forceinline__ void run(const float *Eb, float ec, float *Rs,
+    static __device__ __forceinline__ void run(const Window<V, P> &w, float ec, float *Rs,
                                                const float (&cur)[2 * V + 1],
                                                const float (&nx1)[2 * V + 1])
     {
         constexpr int a = half_width(V, R - V);
         float nx2[2 * V + 1];
-        if constexpr (R + 2 < 2 * V + 1) load_row<V, P, R + 2>(Eb, ec, nx2);
+        if constexpr (R + 2 < 2 * V + 1) load_row<V, P, R + 2>(w, ec, nx2);
         Rs[R] = Tree<2 * a + 1, 0>::sum(cur);
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (R + 1 < 2 * V + 1) RowPipe<V, P, R + 1>::run(Eb, ec, Rs, nx1, nx2);
+        if constexpr (R + 1 < 2 * V + 1) RowPipe<V, P, R + 1>::run(w, ec, Rs, nx1, nx2);
     }
 };
 
@@ -119,6 +143,14 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
             }
         }
     return gc;   // not reached: the own cell has weight 1 and tau < W
+}
+
+// Half widths of the disc's rows, 4 bits per row, row 0 (dy = -V) lowest.
+constexpr unsigned long long row_half_widths(int V)
+{
+    unsigned long long t = 0;
+    for (int r = 0; r <= 2 * V; ++r) t |= (unsigned long long)half_width(V, r - V) << (4 * r);
+    return t;
 }
 
 // Number of slots of the reach disc (5, 13, 29, 49, 81 for v = 1..5).
@@ -283,7 +315,7 @@ struct PlanSharedBase {
     int32_t a_pk[MAX_TILE_CELLS];       // agents of the tile: id << 12 | LDS cell
     float a_ec[MAX_TILE_CELLS];         // e_c of their own cell
     int32_t m_nb[9];
-    int n_agents, n_flag, n_mov;
+    int n_agents, n_flag;
 };
 template <bool SS>
 struct PlanShared : PlanSharedBase {};
@@ -291,20 +323,6 @@ template <>
 struct PlanShared<true> : PlanSharedBase {
     alignas(16) double Sw[MAX_STAGE];   // floor-field window, same layout as Em
 };
-
-// Appends movers (target != own cell) to the tile's record segment, one LDS
-// atomic per wavefront.
-__device__ __forceinline__ void emit_movers(MoveRec *seg, PlanSharedBase &sh, bool mover, MoveRec rec)
-{
-    const unsigned long long mask = __ballot(mover);
-    if (mask == 0) return;
-    const int lane = __lane_id();
-    const int leader = __builtin_ctzll(mask);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&sh.n_mov, __popcll(mask));
-    base = __shfl(base, leader);
-    if (mover) seg[base + __popcll(mask & ((1ull << lane) - 1ull))] = rec;
-}
 
 __device__ __forceinline__ uint32_t pack_xy(int x, int y) { return (uint32_t)x | ((uint32_t)y << 16); }
 
@@ -321,6 +339,8 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
 __device__ __forceinline__ uint32_t plan_draw_word(uint32_t id, uint32_t step, uint32_t scn,
                                                    uint32_t k0, uint32_t k1)
 {
+    k0 = __builtin_amdgcn_readfirstlane(k0);                  // uniform: the scenario's seed
+    k1 = __builtin_amdgcn_readfirstlane(k1);
     asm volatile("" : "+s"(k0), "+s"(k1));
     return philox_word0(id, step, scn, STREAM_PLAN, k0, k1);
 }
@@ -425,7 +445,7 @@ __device__ __forceinline__ void stage_commit(const SlotDev &s, const TileGeom<V,
     const int ci = tid, n_in = tg.n_in, n_halo = tg.n_halo, ly_in = tg.ly_in, cc_in = tg.cc_in;
     const int *ly_h = tg.ly_h, *cc_h = tg.cc_h;
     if (tid < 9) sh.m_nb[tid] = r.mnb;
-    if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; sh.n_mov = 0; }
+    if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; }
     __syncthreads();                                          // m_nb, counters ready
     const int mT = sh.m_nb[4];
 
@@ -494,8 +514,10 @@ __device__ __forceinline__ void stage_commit(const SlotDev &s, const TileGeom<V,
 
 // The draws of a staged tile: one lane per agent (FP32 from the LDS table,
 // flagged draws re-resolved in FP64 by their wavefront), or every draw in
-// FP64 on a fallback tile; movers go to the tile's record segment.  Ends with
-// a workgroup barrier after which only thread 0 touches the LDS counters.
+// FP64 on a fallback tile.  The record of the tile's k-th agent (id, cell,
+// chosen cell; the chosen cell is its own when it stays) goes to slot k of
+// the tile's segment, and the segment count is the tile's agent count.  Ends
+// with a workgroup barrier after which only thread 0 touches the LDS counters.
 template <int V, int TX, bool DEBUG, bool SS>
 __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, TX> &tg, int tile,
                                             PlanShared<SS> &sh, int step, bool fallback)
@@ -515,8 +537,6 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
         // every draw of this tile in FP64, one lane per agent
         for (int base = 0; base < na; base += nthr) {
             const int k = base + tid;
-            bool mover = false;
-            MoveRec rec{};
             if (k < na) {
                 const int id = sh.a_pk[k] >> 12;
                 const int l = sh.a_pk[k] & 0xFFF;
@@ -527,28 +547,25 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
                 const int t = resolve64_lane<V, DEBUG>(s, gc, id, u);
-                mover = t != gc;
                 const int d = t - gc;                       // |dx|, |dy| <= V < Wp / 2
                 const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
-                rec = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                seg[k] = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
                 if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
                 if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
             }
-            emit_movers(seg, sh, mover, rec);
         }
-        __syncthreads();
         if (tid == 0) {
-            s.seg_cnt[tile] = sh.n_mov;
+            s.seg_cnt[tile] = na;
             if (na > 0) atomicAdd(&s.stat[S_FALLBACK], (unsigned long long)na);
         }
+        __syncthreads();
         return;
     }
 
     // --- one lane per agent, FP32 from the LDS table
     for (int base = 0; base < na; base += nthr) {
         const int k = base + tid;
-        bool mover = false, flagged = false;
-        MoveRec rec{};
+        bool flagged = false;
         if (k < na) {
             const int id = sh.a_pk[k] >> 12;
             const int l = sh.a_pk[k] & 0xFFF;
@@ -556,15 +573,15 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             const int ly = (int)((unsigned)l / P);
             const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
 
-            const float *Eb = sh.Em + (l - V * P - V);      // window origin (dy, dx) = (-V, -V)
+            const Window<V, P> win(sh.Em, l - V * P - V);     // origin (dy, dx) = (-V, -V)
             float Rs[SIDE], row0[SIDE], row1[SIDE];
-            load_row<V, P, 0>(Eb, ec, row0);
-            load_row<V, P, 1>(Eb, ec, row1);
+            load_row<V, P, 0>(win, ec, row0);
+            load_row<V, P, 1>(win, ec, row1);
             __builtin_amdgcn_sched_barrier(0);
             // the draw's counter-based word overlaps the first rows' LDS reads
             const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0, kseed1);
             __builtin_amdgcn_sched_barrier(0);
-            RowPipe<V, P, 0>::run(Eb, ec, Rs, row0, row1);
+            RowPipe<V, P, 0>::run(win, ec, Rs, row0, row1);
             float Pr[SIDE + 1];
             Pr[0] = 0.0f;
             Pr[1] = Rs[0];
@@ -575,38 +592,44 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             const float u = (float)(x0 >> 8) * 0x1p-24f;
             const float tau = u * Wsum;
 
-            // row: the last r with Pr_r <= tau
-            int rs = 0, as = half_width(V, -V);
+            // row: the last r with Pr_r <= tau (the row prefixes never
+            // decrease, so that is the number of them <= tau)
+            int rs = 0;
             float Ps = 0.0f;
 #pragma unroll
             for (int r = 1; r < SIDE; ++r) {
                 const bool le = Pr[r] <= tau;
-                rs = le ? r : rs;
+                rs += le ? 1 : 0;
                 Ps = le ? Pr[r] : Ps;
-                as = le ? half_width(V, r - V) : as;
             }
+            const int as = (int)((row_half_widths(V) >> (4 * rs)) & 15u);
             // slot within the row: count of in-row boundaries <= tau.  The
             // row's cells are read at once (slots past 2a stay inside the
             // LDS block and are not used).
-            const float *rb = Eb + rs * P + (V - as);
+            const float *rb = win.b[0] + rs * P + (V - as);
             float rv[SIDE];
 #pragma unroll
             for (int d = 0; d < SIDE; ++d) rv[d] = rb[d];
+            // (the own cell is the middle slot, d = V, of the middle row)
+            const bool own_row = rs == V;
+            const float thr = eps * Wsum;
             float Q = 0.0f;
-            float margin = fabsf(tau - Ps);
+            float margin = fabsf(tau - Ps);                  // smallest |tau - C| (debug output)
+            bool near = margin <= thr;
             int ks = 0;
 #pragma unroll
             for (int d = 0; d < SIDE; ++d) {
                 if (d <= 2 * as) {
-                    const float val = (rs == V && d == as) ? ec : rv[d];
+                    const float val = (d == V && own_row) ? ec : rv[d];
                     Q = Q + val;
                     const float C = Ps + Q;
                     const float diff = tau - C;
                     ks += diff >= 0.0f ? 1 : 0;
-                    margin = fminf(margin, fabsf(diff));
+                    near = near || fabsf(diff) <= thr;
+                    if constexpr (DEBUG) margin = fminf(margin, fabsf(diff));
                 }
             }
-            const bool flag = (margin <= eps * Wsum) || (ks > 2 * as);
+            const bool flag = near || (ks > 2 * as);
 
             if (DEBUG) {
                 if (s.dbg_w) {
@@ -624,12 +647,10 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             }
             if (!flag) {
                 const int ddx = ks - as, ddy = rs - V;
-                mover = ddx != 0 || ddy != 0;
-                rec = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                seg[k] = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
             }
             flagged = flag;
         }
-        emit_movers(seg, sh, mover, rec);
 
         // FP64 re-resolve of this wavefront's flagged draws, one draw at a
         // time by the whole wavefront, without waiting for the other waves
@@ -651,11 +672,10 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const double *Sw = nullptr;
                 if constexpr (SS) Sw = sh.Sw;
                 const int t = resolve64_wave<V, SS>(s, gc, u, lane, sh.Em, Sw, l, P);
-                if (lane == 0 && t != gc) {
+                if (lane == 0) {
                     const int d = t - gc;
                     const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
-                    seg[atomicAdd(&sh.n_mov, 1)] =
-                        MoveRec{(uint32_t)fid, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                    seg[kk] = MoveRec{(uint32_t)fid, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
                 }
             }
         }
@@ -663,7 +683,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
     __syncthreads();
     if (tid == 0) {
         const int nf = sh.n_flag;
-        s.seg_cnt[tile] = sh.n_mov;
+        s.seg_cnt[tile] = na;
         if (nf) atomicAdd(&s.stat[S_FLAGGED], (unsigned long long)nf);
     }
 }
@@ -674,7 +694,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
 // constant.  SS stages the floor-field window too (launches too small to hide
 // the global latency of the rare FP64 re-resolve).
 template <int V, int TX, bool DEBUG, bool SS>
-__device__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
+__device__ __forceinline__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
 {
     const TileGeom<V, TX> tg(s, tile);
     StageRegs<SS> r;

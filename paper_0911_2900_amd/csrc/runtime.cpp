@@ -73,6 +73,7 @@ struct Batch {
     uint32_t *mitems = nullptr;
     int32_t *slots = nullptr;
     int n_items = 0, n_mitems = 0, n_slots = 0;
+    int v = 0, tx = 0;           // v_max and tile width shared by all members, else 0
     void *block = nullptr;
     size_t bytes = 0;
     std::vector<int32_t> members;
@@ -485,6 +486,10 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
         for (int g = 0; g < G[i]; ++g) mitems.push_back(motion_item(order[i], g, G[i]));
     Batch b;
     b.members = hs;
+    b.v = c->slots[order[0]].dev.v;
+    b.tx = c->slots[order[0]].dev.tx;
+    for (int32_t h : order)
+        if (c->slots[h].dev.v != b.v || c->slots[h].dev.tx != b.tx) b.v = b.tx = 0;
     const size_t ib = align_up(items.size() * 4, 256), mb = align_up(mitems.size() * 4, 256);
     b.bytes = ib + mb + order.size() * 4;
     fast_status st = dev_alloc(c, b.bytes, &b.block);
@@ -509,7 +514,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b)
 {
     if (b->exec) return FAST_OK;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, c->stream, nullptr, nullptr);
+    hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
     hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -548,7 +553,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     fast_status st = get_batch(c, hs, &b);
     if (st) return st;
     for (int k = 0; k < steps; ++k) {
-        HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, c->stream, nullptr, nullptr));
+        HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
     }
     for (int32_t h : hs) c->slots[h].host_steps += steps;
@@ -876,7 +881,7 @@ fast_status fast_plan_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     if (st) return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     next_timing_pair(c, &e0, &e1);
-    HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, c->stream, e0, e1));
+    HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, e0, e1));
     for (int32_t h : v) c->slots[h].planned = true;
     return FAST_OK;
 }
