@@ -53,7 +53,8 @@ def log(*a):
 
 
 PLAN_SOURCES = ("paper_0911_2900_amd/csrc/plan_tile.h", "paper_0911_2900_amd/csrc/plan_one.hip",
-                "paper_0911_2900_amd/csrc/plan_batch.hip", "paper_0911_2900_amd/csrc/fast_dev.h")
+                "paper_0911_2900_amd/csrc/plan_batch.hip", "paper_0911_2900_amd/csrc/plan_fixed.hip",
+                "paper_0911_2900_amd/csrc/fast_dev.h")
 
 
 def plan_sources_digest() -> str:
@@ -191,6 +192,9 @@ def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int,
     hs = [ctx.init_from(m, batched=True) for m in scenarios]
     init_s = time.perf_counter() - t0
     tile = [ctx.stats(hs[0])["tile_w"], ctx.stats(hs[0])["tile_h"]]
+    uniform = all(m.v == scenarios[0].v for m in scenarios) and all(
+        [ctx.stats(h)["tile_w"], ctx.stats(h)["tile_h"]] == tile for h in hs)
+    kernel = f"plan_kernel_fixed<{scenarios[0].v}, {tile[0]}>" if uniform else "plan_kernel"
     for _ in range(warmup):
         ctx.plan_batch(hs)
         ctx.move_batch(hs)
@@ -225,7 +229,7 @@ def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int,
         "planning_agent_updates_per_s": planned / (sum(plan_ms) / 1e3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(traffic_key),
-                     "kernel": "plan_kernel",
+                     "kernel": kernel,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_ms * 1e3},
         "plan_us_bracketed": float(np.mean(bracket_ms)) * 1e3,
         "init_s": init_s,
@@ -567,7 +571,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("room"),
-            "kernel": "plan_kernel_one", "bytes_per_launch": bytes_per_launch,
+            "kernel": f"plan_kernel_one_fixed<4, {r['stats']['tile_w']}, true>",
+            "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": avg_plan_ms * 1e3, "achievable": room_ach,
         },
         "ensemble": ens,
