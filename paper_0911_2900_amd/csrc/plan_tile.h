@@ -312,7 +312,7 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
 // ---------------------------------------------------------------------------
 struct PlanSharedBase {
     alignas(16) float Em[MAX_STAGE];    // masked exp table window, pitch P = tx + 2 round4(v)
-    int32_t a_pk[MAX_TILE_CELLS];       // agents of the tile: id << 12 | LDS cell
+    uint32_t a_pk[MAX_TILE_CELLS];      // agents of the tile: id << 12 | LDS cell (id < 2^20)
     float a_ec[MAX_TILE_CELLS];         // e_c of their own cell
     int32_t m_nb[9];
     int n_agents, n_flag;
@@ -502,7 +502,7 @@ __device__ __forceinline__ void stage_commit(const SlotDev &s, const TileGeom<V,
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (live && ov[k] >= 0) {
-                    sh.a_pk[idx] = (ov[k] << 12) | (l0 + k);
+                    sh.a_pk[idx] = ((uint32_t)ov[k] << 12) | (uint32_t)(l0 + k);
                     sh.a_ec[idx] = gv[k];
                     ++idx;
                 }
@@ -538,8 +538,8 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
         for (int base = 0; base < na; base += nthr) {
             const int k = base + tid;
             if (k < na) {
-                const int id = sh.a_pk[k] >> 12;
-                const int l = sh.a_pk[k] & 0xFFF;
+                const int id = (int)(sh.a_pk[k] >> 12);
+                const int l = (int)(sh.a_pk[k] & 0xFFFu);
                 const int ly = (int)((unsigned)l / P);
                 const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
                 const int gc = cy * s.Wp + cx;
@@ -567,8 +567,8 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
         const int k = base + tid;
         bool flagged = false;
         if (k < na) {
-            const int id = sh.a_pk[k] >> 12;
-            const int l = sh.a_pk[k] & 0xFFF;
+            const int id = (int)(sh.a_pk[k] >> 12);
+            const int l = (int)(sh.a_pk[k] & 0xFFFu);
             const float ec = sh.a_ec[k];
             const int ly = (int)((unsigned)l / P);
             const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
@@ -661,8 +661,8 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const int src = __builtin_ctzll(fm);
                 fm &= fm - 1ull;
                 const int kk = base + (tid & ~63) + src;
-                const int fid = sh.a_pk[kk] >> 12;
-                const int l = sh.a_pk[kk] & 0xFFF;
+                const int fid = (int)(sh.a_pk[kk] >> 12);
+                const int l = (int)(sh.a_pk[kk] & 0xFFFu);
                 const int ly = (int)((unsigned)l / P);
                 const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
                 const int gc = cy * s.Wp + cx;

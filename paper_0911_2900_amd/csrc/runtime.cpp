@@ -447,7 +447,7 @@ fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_
         for (size_t t = 0; t < ntiles; ++t)
             for (int k = 0; k < cnt[t]; ++k) {
                 const fk::MoveRec &r = rec[t * tc + k];
-                if ((int)r.id < n) tgt[r.id] = (int32_t)((r.dxy >> 16) * Wp + (r.dxy & 0xFFFFu));
+                if (r.id < (uint32_t)n) tgt[r.id] = (int32_t)((r.dxy >> 16) * Wp + (r.dxy & 0xFFFFu));
             }
     }
     for (int i = 0; i < n; ++i) {

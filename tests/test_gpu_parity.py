@@ -219,6 +219,32 @@ def test_dense_room_all_cells_but_one(ctx):
     ctx.destroy(h)
 
 
+def test_maximum_agent_count(ctx):
+    """The most agents the boundary accepts, 2^20 - 1 (ids fill the 20-bit id
+    fields), in a 1100 x 1100 room at 87 % density: plans and positions equal
+    the oracle's, through the single-scenario launch and through a batched
+    launch of the scenario."""
+    s = sc.room(n_agents=(1 << 20) - 1, size=1100)
+    say("max agents: single-scenario launches")
+    sim, h = make_pair(ctx, s)
+    step_both(ctx, sim, h, 2, where="max agents")
+    ctx.destroy(h)
+    say("max agents: batched launches")
+    sim, h = make_pair(ctx, s)
+    for step in range(2):
+        ctx.plan_batch([h])
+        sim.plan()
+        st = ctx.state(h)
+        alive = sim.alive[: sim.n].astype(bool)
+        bad = np.nonzero(st["desired"][alive] != sim.desired[: sim.n][alive])[0]
+        assert len(bad) == 0, f"batched plan of step {step} differs for {len(bad)} agents"
+        ctx.move_batch([h])
+        sim.move()
+        sim.end_step()
+        compare_state(ctx, sim, h, where=f"batched step {step}")
+    ctx.destroy(h)
+
+
 def test_plan_twice_then_move(ctx):
     s = sc.corridor()
     sim, h = make_pair(ctx, s)
