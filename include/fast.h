@@ -157,7 +157,9 @@ fast_status fast_move_step(fast_ctx *ctx, int32_t handle);
 fast_status fast_run(fast_ctx *ctx, const int32_t *handles, int32_t n, int32_t steps);
 
 /* One planning phase of each of the n scenarios in a single launch over all
- * their tiles (the batched form of fast_plan_step). */
+ * their tiles (the batched form of fast_plan_step).  The batched calls
+ * (fast_run, fast_plan_batch, fast_move_batch) return FAST_E_INVALID for a
+ * scenario of more than 2^20 tiles. */
 fast_status fast_plan_batch(fast_ctx *ctx, const int32_t *handles, int32_t n);
 
 /* One motion phase of each of the n scenarios in a single launch (the batched

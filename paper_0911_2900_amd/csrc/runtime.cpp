@@ -469,6 +469,10 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
 {
     auto it = c->batches.find(hs);
     if (it != c->batches.end()) { *out = &it->second; return FAST_OK; }
+    for (int32_t h : hs)                              // items carry a 20-bit tile index
+        if (c->slots[h].n_items > (1 << 20))
+            return fail(FAST_E_INVALID, "scenario %d has %d tiles; batched launches take at most 2^20 "
+                        "per scenario (choose a larger tile)", h, c->slots[h].n_items);
     // work items: all tiles of all members; the larger scenarios first so
     // their tiles start early on the hardware queue
     std::vector<int32_t> order(hs);
