@@ -394,6 +394,44 @@ struct TileGeom {
     }
 };
 
+// A load through a global (not generic) address: the access is a global_load,
+// counted by vmcnt only, so waits for LDS results do not also wait for it.
+template <typename T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+// 16-byte forms (through the native vector types: the HIP vector classes
+// cannot be copied out of another address space).
+__device__ __forceinline__ int4 gload_i4(const int32_t *p)
+{
+    typedef int v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *(const __attribute__((address_space(1))) v4 *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float4 gload_f4(const float *p)
+{
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *(const __attribute__((address_space(1))) v4 *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 gload_d2(const double *p)
+{
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const __attribute__((address_space(1))) v2 *)p;
+    return double2{v.x, v.y};
+}
+// A planned record, stored through a global address.
+__device__ __forceinline__ void gstore_rec(MoveRec *p, uint32_t id, uint32_t cxy, uint32_t dxy)
+{
+    typedef uint32_t v3 __attribute__((ext_vector_type(3)));
+    v3 v;
+    v.x = id;
+    v.y = cxy;
+    v.z = dxy;
+    *(__attribute__((address_space(1))) v3 *)p = v;
+}
+
 // What a thread loads from global memory to stage one tile.
 template <bool SS>
 struct StageRegs {
@@ -413,16 +451,25 @@ __device__ __forceinline__ void stage_issue(const SlotDev &s, const TileGeom<V, 
 {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int tstride = s.ntx + 2;
-    r.mnb = tid < 9 ? s.tile_m[(tg.tile_y + tid / 3) * tstride + tg.tile_x + tid % 3] : 0;
-    r.fb = s.tile_fb[tg.tile_y * s.ntx + tg.tile_x];
+    const int *tm = &s.tile_m[(tg.tile_y + tid / 3) * tstride + tg.tile_x + tid % 3];
+    const uint8_t *tf = &s.tile_fb[tg.tile_y * s.ntx + tg.tile_x];
+    r.mnb = tid < 9 ? (SS ? *tm : gload(tm)) : 0;
+    r.fb = SS ? *tf : gload(tf);
     r.o_in = r.o_h0 = r.o_h1 = make_int4(-1, -1, -1, -1);
     r.g_in = r.g_h0 = r.g_h1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    // Launches that stage the floor field (single scenarios, descriptor by
+    // value: the compiler already knows the arrays are global) use plain
+    // loads; the others read descriptors from memory, where plain loads would
+    // be generic (flat) ones, counted against the LDS wait counter too.
     auto load = [&](int g, int4 &o, float4 &gv, double4 &d) {
-        o = *(const int4 *)(s.occ + g);
-        gv = *(const float4 *)(s.G + g);
         if constexpr (SS) {
+            o = *(const int4 *)(s.occ + g);
+            gv = *(const float4 *)(s.G + g);
             const double2 x = *(const double2 *)(s.S + g), y = *(const double2 *)(s.S + g + 2);
             d = double4{x.x, x.y, y.x, y.y};
+        } else {
+            o = gload_i4(s.occ + g);
+            gv = gload_f4(s.G + g);
         }
     };
     if (tid < tg.n_in) load((tg.gy0 + tg.ly_in) * s.Wp + tg.gx0 + 4 * tg.cc_in, r.o_in, r.g_in, r.s_in);
@@ -549,7 +596,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const int t = resolve64_lane<V, DEBUG>(s, gc, id, u);
                 const int d = t - gc;                       // |dx|, |dy| <= V < Wp / 2
                 const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
-                seg[k] = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                gstore_rec(seg + k, (uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy));
                 if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
                 if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
             }
@@ -647,7 +694,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             }
             if (!flag) {
                 const int ddx = ks - as, ddy = rs - V;
-                seg[k] = MoveRec{(uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                gstore_rec(seg + k, (uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy));
             }
             flagged = flag;
         }
@@ -675,7 +722,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 if (lane == 0) {
                     const int d = t - gc;
                     const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
-                    seg[kk] = MoveRec{(uint32_t)fid, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy)};
+                    gstore_rec(seg + kk, (uint32_t)fid, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy));
                 }
             }
         }
@@ -696,12 +743,14 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
 template <int V, int TX, bool DEBUG, bool SS>
 __device__ __forceinline__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
 {
+    // the step counter is loaded first and read once the staging loads are
+    // in flight
+    const int step = SS ? s.ctr[C_STEP] : gload(&s.ctr[C_STEP]);
+    const int limit = SS ? s.ctr[C_LIMIT] : gload(&s.ctr[C_LIMIT]);
     const TileGeom<V, TX> tg(s, tile);
     StageRegs<SS> r;
     stage_issue<V, TX, SS>(s, tg, r);
-    // the step counter is read while the staging loads are in flight
-    const int step = s.ctr[C_STEP];
-    if (step >= s.ctr[C_LIMIT]) return;                       // scenario finished: nothing to do
+    if (step >= limit) return;                                // scenario finished: nothing to do
     if (tile == 0 && threadIdx.x < 4) s.ctr[C_BAR + threadIdx.x] = 0;   // fresh motion barriers
     stage_commit<V, TX, SS>(s, tg, sh, r);
     plan_agents<V, TX, DEBUG, SS>(s, tg, tile, sh, step, r.fb != 0);
