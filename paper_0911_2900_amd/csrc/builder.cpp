@@ -154,6 +154,26 @@ float guard_band(int v)
     return (float)std::max(1.01e-6, band);
 }
 
+std::vector<uint8_t> cell_bytes(const Built &b)
+{
+    const int Wp = b.Wp, Hp = b.Hp;
+    auto wall = [&](int x, int y) {
+        return x < 0 || y < 0 || x >= Wp || y >= Hp || b.type[(size_t)y * Wp + x] == fk::CELL_WALL;
+    };
+    std::vector<uint8_t> out(b.type.size());
+    for (int y = 0; y < Hp; ++y)
+        for (int x = 0; x < Wp; ++x) {
+            uint32_t c = b.type[(size_t)y * Wp + x];
+            // a diagonal step (sx, sy) into (x, y) comes from (x - sx, y - sy);
+            // it cuts a corner if (x, y - sy) or (x - sx, y) is a wall
+            for (int sx = -1; sx <= 1; sx += 2)
+                for (int sy = -1; sy <= 1; sy += 2)
+                    if (wall(x, y - sy) || wall(x - sx, y)) c |= 1u << fk::cut_bit(sx, sy);
+            out[(size_t)y * Wp + x] = (uint8_t)c;
+        }
+    return out;
+}
+
 int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::string &err)
 {
     const int W = d.width, H = d.height, v = d.v_max;

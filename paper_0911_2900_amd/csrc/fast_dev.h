@@ -34,6 +34,10 @@
 namespace fk {
 
 enum : int { CELL_FREE = 0, CELL_WALL = 1, CELL_EXIT = 2 };
+// Device cell bytes: the type in bits 0-1, and in bits 2-5 whether a diagonal
+// step into the cell cuts a wall corner, one bit per direction (sx, sy).
+constexpr int CELL_TYPE_MASK = 3, CUT_SHIFT = 2;
+__host__ __device__ inline int cut_bit(int sx, int sy) { return CUT_SHIFT + (sx < 0 ? 2 : 0) + (sy < 0 ? 1 : 0); }
 
 constexpr int MAX_V = 5;
 constexpr int MAX_TILE_CELLS = 1024;   // tx * ty
@@ -102,7 +106,7 @@ struct SlotDev {
     double k_s;
     double near64;           // FP64 re-resolve: scanned prefixes this close to tau (relative
                              // to W) send the draw to the sequential sum
-    const uint8_t *type;     // Wp*Hp
+    const uint8_t *cell;     // Wp*Hp: type | corner-cut bits (see cut_bit)
     const float *G;          // Wp*Hp
     const double *S;         // Wp*Hp
     const int32_t *tile_m;   // (ntx+2)*(nty+2), a ring of zeros around

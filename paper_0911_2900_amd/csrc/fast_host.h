@@ -33,6 +33,8 @@ void floor_field(int W, int H, std::vector<uint8_t> &type, std::vector<double> &
 bool place(int W, int H, const std::vector<uint8_t> &type, int n, uint64_t seed, uint32_t scn,
            std::vector<int32_t> &xy);
 float guard_band(int v);
+// The device cell bytes of a built scenario (fk::cut_bit).
+std::vector<uint8_t> cell_bytes(const Built &b);
 int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::string &err);
 
 }  // namespace fh

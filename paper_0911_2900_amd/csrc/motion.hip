@@ -179,13 +179,16 @@ __device__ unsigned long long line_reach(const SlotDev &s, const Mover &mv, int 
         if (k <= L.m) L.at(k, qx, qy);
         const int q = qy * Wp + qx;
         const bool in = k <= L.m;
-        const uint8_t t = in ? s.type[q] : (uint8_t)CELL_WALL;
+        // one byte holds the cell's type and, per diagonal direction,
+        // whether stepping in that way cuts a wall corner; walls are never
+        // occupied, so the occupancy load need not wait for the type
+        const uint32_t cb = in ? s.cell[q] : (uint32_t)CELL_WALL;
         const bool diag = qx != px && qy != py;
-        const uint8_t ta = diag ? s.type[py * Wp + qx] : (uint8_t)0;
-        const uint8_t tb = diag ? s.type[qy * Wp + px] : (uint8_t)0;
-        wallm |= (t == CELL_WALL || ta == CELL_WALL || tb == CELL_WALL) ? 1u << k : 0u;
+        const bool cut = diag && ((cb >> cut_bit(qx - px, qy - py)) & 1u);
+        const uint32_t t = cb & CELL_TYPE_MASK;
+        wallm |= (t == CELL_WALL || cut) ? 1u << k : 0u;
         exitm |= t == CELL_EXIT ? 1u << k : 0u;
-        o[k] = in && t != CELL_WALL ? s.occ[q] : -1;
+        o[k] = in ? s.occ[q] : -1;
         px = qx;
         py = qy;
     }

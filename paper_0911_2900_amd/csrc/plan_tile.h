@@ -104,7 +104,7 @@ template <int V>
 __device__ __forceinline__ bool reach_ok(const SlotDev &s, int gc, int t, int dx, int dy)
 {
     if (dx * dx + dy * dy > V * V) return false;
-    if (s.type[t] == CELL_WALL) return false;
+    if ((s.cell[t] & CELL_TYPE_MASK) == CELL_WALL) return false;
     const int o = s.occ[t];
     return o < 0 || t == gc;
 }

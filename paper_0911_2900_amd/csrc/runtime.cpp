@@ -335,7 +335,7 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
 
     sd.G = (const float *)(base + o_G);
     sd.occ = (int32_t *)(base + o_occ);
-    sd.type = (const uint8_t *)(base + o_type);
+    sd.cell = (const uint8_t *)(base + o_type);
     sd.tile_m = (const int32_t *)(base + o_tm);
     sd.tile_fb = (const uint8_t *)(base + o_fb);
     sd.seg_cnt = (int32_t *)(base + o_scnt);
@@ -364,7 +364,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     if (e == hipSuccess) e = hipMemset(base + o_res, 0, cells * 16);
     cp(o_G, b.G.data(), cells * 4);
     cp(o_occ, b.occ.data(), cells * 4);
-    cp(o_type, b.type.data(), cells);
+    const std::vector<uint8_t> cellb = fh::cell_bytes(b);
+    cp(o_type, cellb.data(), cells);
     cp(o_tm, b.tile_m.data(), tm * 4);
     cp(o_fb, b.tile_fb.data(), ntiles);
     if (e == hipSuccess) e = hipMemset(base + o_scnt, 0, ntiles * 4);   // no movers planned yet
