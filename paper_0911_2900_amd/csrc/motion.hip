@@ -291,6 +291,15 @@ __device__ int commit_list(const SlotDev &s, const unsigned long long *res, cons
     return sh_cnt;
 }
 
+// Room of each workgroup's mover lists (mv_a, mv_b): ceil(tiles / G) tiles'
+// worth, enough for either split of the records (even runs of records, or
+// runs of tiles); the arrays hold (tiles + MOVE_GROUP_MAX) tiles' worth.
+__device__ __forceinline__ long list_capacity(const SlotDev &s, int G)
+{
+    const int T = s.ntx * s.nty;
+    return (long)((T + G - 1) / G) * (s.tx * s.ty);
+}
+
 // Workgroup 0 gathers the movers left in every workgroup's list (lists in
 // `from`, laid out as in move_group, counts in ctr[C_SOLO + g]) into `to`,
 // starting at 0.  Other workgroups wrote them before the last group barrier,
@@ -298,8 +307,7 @@ __device__ int commit_list(const SlotDev &s, const unsigned long long *res, cons
 __device__ int gather_lists(const SlotDev &s, int G, const Mover *from, Mover *to, int *sh_scan)
 {
     const int tid = threadIdx.x;
-    const int T = s.ntx * s.nty, TC = s.tx * s.ty;
-    const int q = T / G, rm = T % G;
+    const long cap = list_capacity(s, G);
     if (tid < G) sh_scan[tid] = ld_agent(&s.ctr[C_SOLO + tid]);
     __syncthreads();
     if (tid == 0)
@@ -313,7 +321,7 @@ __device__ int gather_lists(const SlotDev &s, int G, const Mover *from, Mover *t
             if (sh_scan[mid] > i) b = mid; else a = mid + 1;
         }
         const int k = i - (a ? sh_scan[a - 1] : 0);
-        const Mover *src = from + ((long)a * q + min(a, rm)) * TC + k;
+        const Mover *src = from + (long)a * cap + k;
         Mover mv;
         mv.key = __hip_atomic_load(&src->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         mv.cxy = __hip_atomic_load(&src->cxy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -330,76 +338,132 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-template <int V>
-__device__ void move_group(const SlotDev &s, int g, int G, int step)
+// Inclusive prefix sum of sh[0 .. MOVE_THREADS) in place (all threads call).
+__device__ __forceinline__ void block_scan(int *sh)
 {
-    __shared__ int sh_scan[MOVE_THREADS];
-    __shared__ int sh_kept;
+    const int tid = threadIdx.x;
+    for (int off = 1; off < MOVE_THREADS; off <<= 1) {
+        const int add = tid >= off ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += add;
+        __syncthreads();
+    }
+}
+
+// The mover of record rec (an agent's plan) with its priority word
+// [~x0:32][~id:20] (larger = earlier) and reach bits; false if it never
+// moves: an agent that stays, or a mover blocked at its first cell, is at
+// every other mover's turn still where it started, which is what they see
+// without it taking part.
+template <int V>
+__device__ __forceinline__ bool gather_one(const SlotDev &s, const MoveRec &rec, int step, Mover &mv)
+{
+    if (rec.dxy == rec.cxy) return false;
+    mv.key = order_key(s, rec.id, step);
+    mv.cxy = rec.cxy;
+    mv.dxy = rec.dxy;
+    mv.key |= line_reach<V>(s, mv, step);
+    return mover_reach(mv.key) > 0;
+}
+
+// Appends the kept movers of one pass of the workgroup to list + n (the
+// count comes from sh_kept after the caller's barrier).
+__device__ __forceinline__ void append_kept(Mover *list, int n, bool keep, const Mover &mv, int *sh_kept)
+{
+    const unsigned long long m = __ballot(keep);
+    if (m) {
+        const int lane = __lane_id();
+        int base = 0;
+        if (lane == 0) base = atomicAdd(sh_kept, __popcll(m));
+        base = __shfl(base, 0);
+        if (keep) list[n + base + lanes_below(m)] = mv;
+    }
+}
+
+// sh_scan[MOVE_THREADS], sh_tp[GATHER_TILES_MAX], sh_kept: LDS of the kernel
+// (declared there once, not per v_max).
+template <int V>
+__device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int step, int *sh_scan, int *sh_tp,
+                           int &sh_kept)
+{
     const int tid = threadIdx.x;
     const int T = s.ntx * s.nty, TC = s.tx * s.ty;
-    // workgroup g takes tiles g, g + G, g + 2G, ...: every region of the grid
-    // (the congested exit above all) is spread over the whole group, so the
-    // rounds stay balanced; its mover lists own tiles' worth of room
-    const int q = T / G, rm = T % G;
-    const int nt_g = q + (g < rm ? 1 : 0);
-    const long base_g = ((long)g * q + min(g, rm)) * TC;
-    Mover *cur = s.mv_a + base_g, *nxt = s.mv_b + base_g;
+    const long cap = list_capacity(s, G);
+    Mover *cur = s.mv_a + (long)g * cap, *nxt = s.mv_b + (long)g * cap;
     unsigned long long seen0 = 0, seen1 = 0;
     uint32_t tag = (uint32_t)s.ctr[C_TAG];
     if (g == 0 && tid == 0)   // agents planned this step, for the throughput counters
         atomicAdd(&s.stat[S_PLANNED], (unsigned long long)s.ctr[C_NACTIVE]);
 
-    // gather this workgroup's movers (from the records of its tiles) with their
-    // priority words [~x0:32][~id:20] (larger = earlier)
+    // gather this workgroup's movers from the planned records
     int n = 0;
-    for (int j0 = 0; j0 < nt_g; j0 += MOVE_THREADS) {
-        const int nt = min(MOVE_THREADS, nt_g - j0);
-        sh_scan[tid] = tid < nt ? s.seg_cnt[g + (long)(j0 + tid) * G] : 0;
-        __syncthreads();
-        for (int off = 1; off < MOVE_THREADS; off <<= 1) {
-            const int add = tid >= off ? sh_scan[tid - off] : 0;
+    if (T <= GATHER_TILES_MAX) {
+        // the scenario's records, numbered tile by tile, split into G equal
+        // runs: every workgroup gets the same count, from neighbouring tiles
+        // (dealing records out in turn instead balances regions, but scatters
+        // every workgroup's memory accesses over the whole grid: slower)
+        int carry = 0;
+        for (int j0 = 0; j0 < T; j0 += MOVE_THREADS) {
+            const int nt = min(MOVE_THREADS, T - j0);
+            sh_scan[tid] = tid < nt ? s.seg_cnt[j0 + tid] : 0;
             __syncthreads();
-            sh_scan[tid] += add;
+            block_scan(sh_scan);
+            if (tid < nt) sh_tp[j0 + tid] = sh_scan[tid] + carry;
+            carry += sh_scan[MOVE_THREADS - 1];
             __syncthreads();
         }
-        const int chunk = sh_scan[MOVE_THREADS - 1];
+        const int r0 = (int)((long)carry * g / G), mine = (int)((long)carry * (g + 1) / G) - r0;
         if (tid == 0) sh_kept = 0;
         __syncthreads();
-        for (int i0 = 0; i0 < chunk; i0 += blockDim.x) {
-            const int i = i0 + tid;
+        for (int j0 = 0; j0 < mine; j0 += blockDim.x) {
+            const int i = r0 + j0 + tid;
             Mover mv;
             bool keep = false;
-            if (i < chunk) {
-                int a = 0, b = nt - 1;               // first tile whose inclusive count exceeds i
+            if (j0 + tid < mine) {
+                int a = 0, b = T - 1;                // first tile whose inclusive count exceeds i
                 while (a < b) {
                     const int mid = (a + b) >> 1;
-                    if (sh_scan[mid] > i) b = mid; else a = mid + 1;
+                    if (sh_tp[mid] > i) b = mid; else a = mid + 1;
                 }
-                const int k = i - (a ? sh_scan[a - 1] : 0);
-                const MoveRec rec = s.seg[(g + (long)(j0 + a) * G) * TC + k];
-                // an agent that stays, or a mover blocked at its first cell,
-                // never moves: at every other mover's turn it is still where
-                // it started, which is what they see without it taking part
-                if (rec.dxy != rec.cxy) {
-                    mv.key = order_key(s, rec.id, step);
-                    mv.cxy = rec.cxy;
-                    mv.dxy = rec.dxy;
-                    mv.key |= line_reach<V>(s, mv, step);
-                    keep = mover_reach(mv.key) > 0;
-                }
+                const int k = i - (a ? sh_tp[a - 1] : 0);
+                keep = gather_one<V>(s, s.seg[(long)a * TC + k], step, mv);
             }
-            const unsigned long long m = __ballot(keep);
-            if (m) {
-                const int lane = __lane_id();
-                int base = 0;
-                if (lane == 0) base = atomicAdd(&sh_kept, __popcll(m));
-                base = __shfl(base, 0);
-                if (keep) cur[n + base + lanes_below(m)] = mv;
-            }
+            append_kept(cur, n, keep, mv, &sh_kept);
         }
         __syncthreads();
-        n += sh_kept;
+        n = sh_kept;
         __syncthreads();
+    } else {
+        // very many tiles: workgroup g takes the records of a run of tiles,
+        // t0 .. t1 - 1
+        const int t0 = (int)((long)T * g / G), nt_g = (int)((long)T * (g + 1) / G) - t0;
+        for (int j0 = 0; j0 < nt_g; j0 += MOVE_THREADS) {
+            const int nt = min(MOVE_THREADS, nt_g - j0);
+            sh_scan[tid] = tid < nt ? s.seg_cnt[t0 + j0 + tid] : 0;
+            __syncthreads();
+            block_scan(sh_scan);
+            const int chunk = sh_scan[MOVE_THREADS - 1];
+            if (tid == 0) sh_kept = 0;
+            __syncthreads();
+            for (int i0 = 0; i0 < chunk; i0 += blockDim.x) {
+                const int i = i0 + tid;
+                Mover mv;
+                bool keep = false;
+                if (i < chunk) {
+                    int a = 0, b = nt - 1;           // first tile whose inclusive count exceeds i
+                    while (a < b) {
+                        const int mid = (a + b) >> 1;
+                        if (sh_scan[mid] > i) b = mid; else a = mid + 1;
+                    }
+                    const int k = i - (a ? sh_scan[a - 1] : 0);
+                    keep = gather_one<V>(s, s.seg[((long)t0 + j0 + a) * TC + k], step, mv);
+                }
+                append_kept(cur, n, keep, mv, &sh_kept);
+            }
+            __syncthreads();
+            n += sh_kept;
+            __syncthreads();
+        }
     }
 
     int total = 1, rounds = 0, bar_r = 0;          // round 0's total comes from its barrier
@@ -459,12 +523,15 @@ __global__ __launch_bounds__(MOVE_THREADS) __attribute__((amdgpu_waves_per_eu(8)
     const int G = (int)(it >> 22) + 1;
     const int step = s.ctr[C_STEP];
     if (step >= s.ctr[C_LIMIT]) return;
+    __shared__ int sh_scan[MOVE_THREADS];
+    __shared__ int sh_tp[GATHER_TILES_MAX];
+    __shared__ int sh_kept;
     switch (s.v) {
-        case 1: move_group<1>(s, g, G, step); break;
-        case 2: move_group<2>(s, g, G, step); break;
-        case 3: move_group<3>(s, g, G, step); break;
-        case 4: move_group<4>(s, g, G, step); break;
-        case 5: move_group<5>(s, g, G, step); break;
+        case 1: move_group<1>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
+        case 2: move_group<2>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
+        case 3: move_group<3>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
+        case 4: move_group<4>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
+        case 5: move_group<5>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
         default: break;
     }
 }

@@ -303,7 +303,9 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
 
     const size_t cells = (size_t)b.Wp * b.Hp;
     const size_t ntiles = (size_t)b.ntx * b.nty;
-    const size_t tcells = ntiles * (size_t)b.tx * b.ty;   // record / mover capacity
+    const size_t tcells = ntiles * (size_t)b.tx * b.ty;   // record capacity
+    // mover lists: every motion workgroup has room for ceil(tiles / G) tiles
+    const size_t lcells = (ntiles + fk::MOVE_GROUP_MAX) * (size_t)b.tx * b.ty;
     const size_t tm = (size_t)(b.ntx + 2) * (b.nty + 2);
     // carve one block: 256-byte aligned sub-buffers
     size_t off = 0;
@@ -311,8 +313,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     const size_t o_S = take(cells * 8), o_res = take(cells * 16), o_G = take(cells * 4),
                  o_occ = take(cells * 4), o_type = take(cells), o_tm = take(tm * 4),
                  o_fb = take(ntiles), o_scnt = take(ntiles * 4),
-                 o_seg = take(tcells * sizeof(fk::MoveRec)), o_ka = take(tcells * sizeof(fk::Mover)),
-                 o_kb = take(tcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
+                 o_seg = take(tcells * sizeof(fk::MoveRec)), o_ka = take(lcells * sizeof(fk::Mover)),
+                 o_kb = take(lcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
                  o_mitems = take(fk::MOVE_GROUP_MAX * 4);
     void *block = nullptr;

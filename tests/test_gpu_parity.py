@@ -245,6 +245,18 @@ def test_maximum_agent_count(ctx):
     ctx.destroy(h)
 
 
+def test_many_tiles_motion_split(ctx):
+    """More tiles than the motion phase splits by records (4,096): a 600 x 600
+    room in 8 x 8 tiles (5,625), where the motion workgroups take runs of
+    tiles instead; plans and positions equal the oracle's."""
+    s = sc.room(n_agents=60000, v=4, size=600)
+    say("many tiles: 600 x 600 in 8 x 8 tiles")
+    sim, h = make_pair(ctx, s, tile=(8, 8))
+    assert ctx.stats(h)["n_tiles"] > 4096
+    step_both(ctx, sim, h, 6, where="many tiles")
+    ctx.destroy(h)
+
+
 def test_plan_twice_then_move(ctx):
     s = sc.corridor()
     sim, h = make_pair(ctx, s)
