@@ -48,6 +48,7 @@ constexpr int ONE_STAGE_S_TILES = 2048;   // ... and the floor field staged in L
 constexpr int MOVE_THREADS = 1024;
 constexpr int MOVE_GROUP_MAX = 64;        // workgroups per scenario in the motion phase
 constexpr int GATHER_TILES_MAX = 4096;    // motion splits records evenly up to this many tiles
+constexpr int DIES = 8;                   // compute dies (XCDs), each with its own L2
 constexpr int MOVE_SOLO_MAX = 256;        // movers left at which one workgroup takes over
 constexpr int MOVE_AGENTS_PER_WG = 1024;  // group size = ceil(agents / this), capped
 constexpr uint32_t SPIN_LIMIT = 1u << 22; // bound on a group-barrier wait (never hangs)
@@ -117,7 +118,7 @@ struct SlotDev {
     unsigned long long *res1;// Wp*Hp, reservations of odd rounds
     int32_t *seg_cnt;        // ntx*nty: agents planned per tile
     MoveRec *seg;            // ntx*nty*tx*ty: their records, tile by tile
-    Mover *mv_a, *mv_b;      // (ntx*nty + MOVE_GROUP_MAX)*tx*ty each: movers of the current / next round
+    Mover *mv_a, *mv_b;      // (ntx*nty + 2 MOVE_GROUP_MAX)*tx*ty each: movers of the current / next round
     int32_t *ctr;            // C_NCTR
     unsigned long long *stat;// S_NSTAT
     float *dbg_w;            // optional debug outputs (null in normal runs)

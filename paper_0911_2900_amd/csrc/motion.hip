@@ -291,13 +291,19 @@ __device__ int commit_list(const SlotDev &s, const unsigned long long *res, cons
     return sh_cnt;
 }
 
-// Room of each workgroup's mover lists (mv_a, mv_b): ceil(tiles / G) tiles'
-// worth, enough for either split of the records (even runs of records, or
-// runs of tiles); the arrays hold (tiles + MOVE_GROUP_MAX) tiles' worth.
+// Room of each workgroup's mover lists (mv_a, mv_b), in tiles' worth: enough
+// for every split of the records below (ceil(tiles / G), or with G a multiple
+// of DIES ceil(ceil(tiles / DIES) / (G / DIES)) if larger); G times it is at
+// most tiles + 2 MOVE_GROUP_MAX, the room of the arrays.
 __device__ __forceinline__ long list_capacity(const SlotDev &s, int G)
 {
     const int T = s.ntx * s.nty;
-    return (long)((T + G - 1) / G) * (s.tx * s.ty);
+    int tiles = (T + G - 1) / G;
+    if (G % DIES == 0) {                                   // the split by dies
+        const int m = G / DIES;
+        tiles = max(tiles, ((T + DIES - 1) / DIES + m - 1) / m);
+    }
+    return (long)tiles * (s.tx * s.ty);
 }
 
 // Workgroup 0 gathers the movers left in every workgroup's list (lists in
@@ -398,21 +404,30 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
     // gather this workgroup's movers from the planned records
     int n = 0;
     if (T <= GATHER_TILES_MAX) {
-        // the scenario's records, numbered tile by tile, split into G equal
-        // runs: every workgroup gets the same count, from neighbouring tiles
-        // (dealing records out in turn instead balances regions, but scatters
-        // every workgroup's memory accesses over the whole grid: slower)
+        // The records, numbered tile by tile, are split into equal runs: every
+        // workgroup gets the same count, from neighbouring tiles (dealing
+        // records out in turn instead balances regions, but scatters every
+        // workgroup's memory accesses over the whole grid: slower).
+        // Workgroups go to the device's DIES dies in turn, as do the tiles of
+        // a single-scenario planning launch; so with G a multiple of DIES,
+        // workgroup g takes only tiles t = g (mod DIES): the occupancy lines
+        // its commits touch are then in the L2 of the die that plans those
+        // tiles next.
+        const bool by_die = G % DIES == 0;
+        const int c = by_die ? g % DIES : 0, stride = by_die ? DIES : 1;
+        const int m = by_die ? G / DIES : G, w = by_die ? g / DIES : g;
+        const int Tc = c < T ? (T - c + stride - 1) / stride : 0;   // tiles c, c + stride, ...
         int carry = 0;
-        for (int j0 = 0; j0 < T; j0 += MOVE_THREADS) {
-            const int nt = min(MOVE_THREADS, T - j0);
-            sh_scan[tid] = tid < nt ? s.seg_cnt[j0 + tid] : 0;
+        for (int j0 = 0; j0 < Tc; j0 += MOVE_THREADS) {
+            const int nt = min(MOVE_THREADS, Tc - j0);
+            sh_scan[tid] = tid < nt ? s.seg_cnt[c + (j0 + tid) * stride] : 0;
             __syncthreads();
             block_scan(sh_scan);
             if (tid < nt) sh_tp[j0 + tid] = sh_scan[tid] + carry;
             carry += sh_scan[MOVE_THREADS - 1];
             __syncthreads();
         }
-        const int r0 = (int)((long)carry * g / G), mine = (int)((long)carry * (g + 1) / G) - r0;
+        const int r0 = (int)((long)carry * w / m), mine = (int)((long)carry * (w + 1) / m) - r0;
         if (tid == 0) sh_kept = 0;
         __syncthreads();
         for (int j0 = 0; j0 < mine; j0 += blockDim.x) {
@@ -420,13 +435,13 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
             Mover mv;
             bool keep = false;
             if (j0 + tid < mine) {
-                int a = 0, b = T - 1;                // first tile whose inclusive count exceeds i
+                int a = 0, b = Tc - 1;               // first tile whose inclusive count exceeds i
                 while (a < b) {
                     const int mid = (a + b) >> 1;
                     if (sh_tp[mid] > i) b = mid; else a = mid + 1;
                 }
                 const int k = i - (a ? sh_tp[a - 1] : 0);
-                keep = gather_one<V>(s, s.seg[(long)a * TC + k], step, mv);
+                keep = gather_one<V>(s, s.seg[((long)c + (long)a * stride) * TC + k], step, mv);
             }
             append_kept(cur, n, keep, mv, &sh_kept);
         }

@@ -304,8 +304,9 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     const size_t cells = (size_t)b.Wp * b.Hp;
     const size_t ntiles = (size_t)b.ntx * b.nty;
     const size_t tcells = ntiles * (size_t)b.tx * b.ty;   // record capacity
-    // mover lists: every motion workgroup has room for ceil(tiles / G) tiles
-    const size_t lcells = (ntiles + fk::MOVE_GROUP_MAX) * (size_t)b.tx * b.ty;
+    // mover lists: the G motion workgroups' lists take at most
+    // tiles + 2 MOVE_GROUP_MAX tiles' worth
+    const size_t lcells = (ntiles + 2 * fk::MOVE_GROUP_MAX) * (size_t)b.tx * b.ty;
     const size_t tm = (size_t)(b.ntx + 2) * (b.nty + 2);
     // carve one block: 256-byte aligned sub-buffers
     size_t off = 0;
