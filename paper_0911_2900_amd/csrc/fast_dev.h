@@ -8,16 +8,17 @@
 //   padded width  Wp = ntx * tx + 2 pad rounded up to a multiple of 32 cells,
 //   padded height Hp = nty * ty + 2 pad,
 //   cell (x, y) of the scenario lives at index (y + pad) * Wp + (x + pad).
-// Per cell:  type u8 (static), G f32 (static exp table, see below),
-//            S f64 (static floor field, read only by the FP64 re-resolve),
-//            occ i32 (agent id or -1), res0/res1 u64 (motion reservations of
-//            even / odd rounds).
+// Per cell:  cell u8 (static: type and corner-cut bits, see cut_bit),
+//            G f32 (static exp table, see below), S f64 (static floor field,
+//            read only by the FP64 re-resolve), occ i32 (agent id or -1),
+//            res0/res1 u64 (motion reservations of even / odd rounds).
 // Per tile:  m i32 (power-of-two scale of the exp table), fallback u8, and the
-//            movers planned on the tile: a count and up to tx*ty records
-//            (id, start, target) written by the planning kernel, read by the
-//            motion kernel; the motion rounds keep two mover lists of the same
-//            size.  Positions live only in occ (the host rebuilds per-agent
-//            arrays from occ and the records when asked).
+//            agents planned on the tile: a count and one record each (id,
+//            start, chosen cell; the chosen cell is the start when the agent
+//            stays), written by the planning kernel, read by the motion
+//            kernel; the motion rounds keep two mover lists.  Positions live
+//            only in occ (the host rebuilds per-agent arrays from occ and the
+//            records when asked).
 //
 // Exp table: G(t) = fl32(exp(m_T(t) ln 2 - k_S S(t))) where T(t) is the tile
 // holding t.  A tile T staging a halo cell t of tile T' rescales it by

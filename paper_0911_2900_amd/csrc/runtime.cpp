@@ -371,7 +371,7 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     cp(o_type, cellb.data(), cells);
     cp(o_tm, b.tile_m.data(), tm * 4);
     cp(o_fb, b.tile_fb.data(), ntiles);
-    if (e == hipSuccess) e = hipMemset(base + o_scnt, 0, ntiles * 4);   // no movers planned yet
+    if (e == hipSuccess) e = hipMemset(base + o_scnt, 0, ntiles * 4);   // nothing planned yet
     cp(o_ctr, ctr.data(), fk::C_NCTR * 4);
     if (e == hipSuccess) e = hipMemset(base + o_stat, 0, fk::S_NSTAT * 8);
     cp(o_items, items.data(), ntiles * 4);
@@ -420,7 +420,7 @@ fast_status destroy_slot(fast_ctx *c, int32_t h)
 }
 
 // Per-agent state rebuilt from the occupancy grid (positions) and the tiles'
-// mover records of the last plan (targets; agents without one stay put).
+// records of the last plan (chosen cells).
 fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_t *desired,
                        int32_t *step, int32_t *n_active)
 {
