@@ -95,20 +95,31 @@ __device__ __forceinline__ Line make_line(uint32_t cxy, uint32_t dxy)
 // waits until the arrivals reach (r / 2 + 1) * G.  A word is touched again only
 // two barriers later, after every workgroup has read it, so the count part
 // minus its value at the previous barrier of the same parity is this round's
-// total.  All data shared between the workgroups moves through agent-scope
-// atomics; the fences of thread 0 order them around the arrival.  A wait
-// longer than SPIN_LIMIT polls marks the scenario as failed (C_ERR) instead of
-// hanging; the function then returns -1.
+// total.
+//
+// Everything one workgroup writes for the others (reservations, occupancy,
+// movers handed over, counts) is written with agent-scope atomics or atomic
+// stores and read with agent-scope loads: each location is coherent across
+// the device's dies by itself.  So the barrier needs no cache write-back or
+// invalidation (a fence at agent scope does both, on the L2 of each die):
+// every thread waits until its own memory operations have completed, then
+// thread 0 arrives.  `acquire`: thread 0 then also invalidates its caches
+// (an agent-scope acquire fence), after which plain loads of the workgroup
+// see what the others wrote.  A wait longer than SPIN_LIMIT polls marks the
+// scenario as failed (C_ERR) instead of hanging; the function then returns -1.
 __device__ int group_sync_count(const SlotDev &s, int G, int r, int n, unsigned long long &seen0,
-                                unsigned long long &seen1)
+                                unsigned long long &seen1, bool acquire = false)
 {
     __shared__ int sh_total;
+    if (G == 1) {
+        __syncthreads();
+        return n;
+    }
+    __builtin_amdgcn_s_waitcnt(0);                 // this thread's stores and atomics are done
     __syncthreads();
-    if (G == 1) return n;
     if (threadIdx.x == 0) {
         unsigned long long *bar = (unsigned long long *)&s.ctr[C_BAR] + (r & 1);
         unsigned long long &seen = (r & 1) ? seen1 : seen0;
-        __threadfence();
         atomicAdd(bar, (1ull << 32) | (unsigned long long)(uint32_t)n);
         const unsigned long long target = (unsigned long long)(r / 2 + 1) * (unsigned long long)G;
         uint32_t spins = 0;
@@ -119,7 +130,7 @@ __device__ int group_sync_count(const SlotDev &s, int G, int r, int n, unsigned 
             if ((w >> 32) >= target) { total = (int)((uint32_t)w - (uint32_t)seen); seen = w; break; }
             if (++spins > SPIN_LIMIT) { atomicOr(&s.ctr[C_ERR], 1); break; }
         }
-        __threadfence();
+        if (acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         sh_total = total;
     }
     __syncthreads();
@@ -219,15 +230,15 @@ __device__ unsigned long long line_reach(const SlotDev &s, const Mover &mv, int 
 }
 
 // Check-and-commit for the workgroup's list (see the protocol above); movers
-// that cannot commit yet are appended to `nxt`.  Returns the number appended.
-// `fenced`: the last group barrier ended with an agent-scope acquire fence,
-// after which plain (cacheable) loads see every reservation of the round and
-// at least the occupancy at its start (commits of this round may or may not
-// be seen, which the protocol allows); without it (workgroup barriers only)
-// the loads go to the coherence point.
+// that cannot commit yet are appended to `nxt` (the workgroup's own list).
+// Returns the number appended.  Reservations and occupancy are read with
+// agent-scope loads, or with plain (cacheable) ones when the last barrier
+// ended with an acquire fence (`acquired`): either way they see every
+// reservation of the round and at least the occupancy at its start (commits
+// of this round may or may not be seen, which the protocol allows).
 template <int V>
 __device__ int commit_list(const SlotDev &s, const unsigned long long *res, const Mover *cur,
-                           Mover *nxt, int n, unsigned long long tagw, bool fenced)
+                           Mover *nxt, int n, unsigned long long tagw, bool acquired)
 {
     __shared__ int sh_cnt;
     const int Wp = s.Wp;
@@ -248,7 +259,7 @@ __device__ int commit_list(const SlotDev &s, const unsigned long long *res, cons
             if (k <= me) L.at(k, x, y);
             cell[k] = y * Wp + x;
             const bool in = k >= 1 && k <= me;
-            if (fenced) {
+            if (acquired) {
                 w[k] = in ? res[cell[k]] : word;
                 o[k] = in ? s.occ[cell[k]] : -1;
             } else {
@@ -306,14 +317,14 @@ __device__ __forceinline__ long list_capacity(const SlotDev &s, int G)
     return (long)tiles * (s.tx * s.ty);
 }
 
-// Workgroup 0 gathers the movers left in every workgroup's list (lists in
-// `from`, laid out as in move_group, counts in ctr[C_SOLO + g]) into `to`,
-// starting at 0.  Other workgroups wrote them before the last group barrier,
-// so they are read with agent-scope loads.  Returns the count.
-__device__ int gather_lists(const SlotDev &s, int G, const Mover *from, Mover *to, int *sh_scan)
+// Workgroup 0 gathers the movers left in every workgroup's list (copies in
+// the handoff area, MOVE_SOLO_MAX per workgroup, counts in ctr[C_SOLO + g])
+// into `to`, starting at 0.  Other workgroups wrote them with agent-scope
+// stores before the last group barrier, so they are read with agent-scope
+// loads.  Returns the count.
+__device__ int gather_lists(const SlotDev &s, int G, Mover *to, int *sh_scan)
 {
     const int tid = threadIdx.x;
-    const long cap = list_capacity(s, G);
     if (tid < G) sh_scan[tid] = ld_agent(&s.ctr[C_SOLO + tid]);
     __syncthreads();
     if (tid == 0)
@@ -327,7 +338,7 @@ __device__ int gather_lists(const SlotDev &s, int G, const Mover *from, Mover *t
             if (sh_scan[mid] > i) b = mid; else a = mid + 1;
         }
         const int k = i - (a ? sh_scan[a - 1] : 0);
-        const Mover *src = from + (long)a * cap + k;
+        const Mover *src = s.hand + (long)a * MOVE_SOLO_MAX + k;
         Mover mv;
         mv.key = __hip_atomic_load(&src->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         mv.cxy = __hip_atomic_load(&src->cxy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -389,8 +400,8 @@ __device__ __forceinline__ void append_kept(Mover *list, int n, bool keep, const
 // sh_scan[MOVE_THREADS], sh_tp[GATHER_TILES_MAX], sh_kept: LDS of the kernel
 // (declared there once, not per v_max).
 template <int V>
-__device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int step, int *sh_scan, int *sh_tp,
-                           int &sh_kept)
+__device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int step, bool alone,
+                                           int *sh_scan, int *sh_tp, int &sh_kept)
 {
     const int tid = threadIdx.x;
     const int T = s.ntx * s.nty, TC = s.tx * s.ty;
@@ -483,12 +494,17 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
 
     int total = 1, rounds = 0, bar_r = 0;          // round 0's total comes from its barrier
     int Gr = G;                                    // workgroups still in the phase
+    // A launch that moves one scenario invalidates the caches of its dies at
+    // each group barrier and reads with cacheable loads; in a batch those
+    // invalidations would evict every other scenario's lines from the dies'
+    // L2s, so batches read with agent-scope loads instead.
+    bool acq = false;                              // the last barrier ended with an acquire
     for (int r = 0; total > 0; ++r) {
         unsigned long long *res = (r & 1) ? s.res1 : s.res0;
         if (r > 0) {
             // round r's movers are the losers of round r - 1 (this workgroup's share)
             n = commit_list<V>(s, (r & 1) ? s.res0 : s.res1, cur, nxt, n,
-                               (unsigned long long)tag << TAG_SHIFT, Gr > 1);
+                               (unsigned long long)tag << TAG_SHIFT, acq);
             Mover *t = cur; cur = nxt; nxt = t;
         }
         if (tag >= TAG_LIMIT) {
@@ -505,18 +521,26 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
         }
         ++tag;
         reserve_list<V>(s, res, cur, n, (unsigned long long)tag << TAG_SHIFT);
+        if (Gr > 1 && n <= MOVE_SOLO_MAX) {         // workgroup 0 may take these over
+            Mover *h = s.hand + (long)g * MOVE_SOLO_MAX;
+            for (int i = tid; i < n; i += blockDim.x) {
+                const Mover mv = cur[i];
+                __hip_atomic_store(&h[i].key, mv.key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&h[i].cxy, mv.cxy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&h[i].dxy, mv.dxy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if (Gr > 1 && tid == 0) st_agent(&s.ctr[C_SOLO + g], n);
-        total = group_sync_count(s, Gr, bar_r++, n, seen0, seen1);
+        total = group_sync_count(s, Gr, bar_r++, n, seen0, seen1, alone);
+        acq = alone && Gr > 1;
         if (total < 0) return;
         rounds += total > 0 ? 1 : 0;
         if (Gr > 1 && total > 0 && total <= MOVE_SOLO_MAX) {
             // the same decision in every workgroup (total is the group's sum)
             if (g != 0) return;
-            const bool in_a = cur == s.mv_a;           // workgroup 0's lists start at offset 0
-            Mover *from = in_a ? s.mv_a : s.mv_b, *to = in_a ? s.mv_b : s.mv_a;
-            n = gather_lists(s, G, from, to, sh_scan);
-            cur = to;
-            nxt = from;
+            n = gather_lists(s, G, s.mv_a, sh_scan);    // workgroup 0's lists start at 0
+            cur = s.mv_a;
+            nxt = s.mv_b;
             Gr = 1;
         }
     }
@@ -527,26 +551,28 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
     }
 }
 
-// mitems[i] = slot | g << 12 | (G - 1) << 22: workgroup g of the G that move
-// the slot's agents.
+// mitems[i] = slot | g << 12 | (G - 1) << 22 | alone << 31: workgroup g of
+// the G that move the slot's agents; alone: the launch moves this scenario
+// only.
 __global__ __launch_bounds__(MOVE_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void move_kernel(const SlotDev *__restrict__ table,
                                                             const uint32_t *__restrict__ mitems)
 {
     const uint32_t it = mitems[blockIdx.x];
     const SlotDev &s = table[it & 0xFFFu];
     const int g = (int)((it >> 12) & 0x3FFu);
-    const int G = (int)(it >> 22) + 1;
+    const int G = (int)((it >> 22) & 0x1FFu) + 1;
+    const bool alone = (it >> 31) != 0;
     const int step = s.ctr[C_STEP];
     if (step >= s.ctr[C_LIMIT]) return;
     __shared__ int sh_scan[MOVE_THREADS];
     __shared__ int sh_tp[GATHER_TILES_MAX];
     __shared__ int sh_kept;
     switch (s.v) {
-        case 1: move_group<1>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
-        case 2: move_group<2>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
-        case 3: move_group<3>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
-        case 4: move_group<4>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
-        case 5: move_group<5>(s, g, G, step, sh_scan, sh_tp, sh_kept); break;
+        case 1: move_group<1>(s, g, G, step, alone, sh_scan, sh_tp, sh_kept); break;
+        case 2: move_group<2>(s, g, G, step, alone, sh_scan, sh_tp, sh_kept); break;
+        case 3: move_group<3>(s, g, G, step, alone, sh_scan, sh_tp, sh_kept); break;
+        case 4: move_group<4>(s, g, G, step, alone, sh_scan, sh_tp, sh_kept); break;
+        case 5: move_group<5>(s, g, G, step, alone, sh_scan, sh_tp, sh_kept); break;
         default: break;
     }
 }

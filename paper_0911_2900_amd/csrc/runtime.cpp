@@ -199,9 +199,10 @@ int motion_group(int n)
     return std::max(1, std::min(g, fk::MOVE_GROUP_MAX));
 }
 
-uint32_t motion_item(int32_t slot, int g, int G)
+// alone: the launch moves this scenario only (see move_kernel).
+uint32_t motion_item(int32_t slot, int g, int G, bool alone = false)
 {
-    return (uint32_t)slot | ((uint32_t)g << 12) | ((uint32_t)(G - 1) << 22);
+    return (uint32_t)slot | ((uint32_t)g << 12) | ((uint32_t)(G - 1) << 22) | (alone ? 1u << 31 : 0u);
 }
 
 // Group sizes for a batch.  Every workgroup of the motion launch must be
@@ -317,7 +318,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
                  o_seg = take(tcells * sizeof(fk::MoveRec)), o_ka = take(lcells * sizeof(fk::Mover)),
                  o_kb = take(lcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
-                 o_mitems = take(fk::MOVE_GROUP_MAX * 4);
+                 o_mitems = take(fk::MOVE_GROUP_MAX * 4),
+                 o_hand = take((size_t)fk::MOVE_GROUP_MAX * fk::MOVE_SOLO_MAX * sizeof(fk::Mover));
     void *block = nullptr;
     st = dev_alloc(c, off, &block);
     if (st) return st;
@@ -345,6 +347,7 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     sd.seg = (fk::MoveRec *)(base + o_seg);
     sd.mv_a = (fk::Mover *)(base + o_ka);
     sd.mv_b = (fk::Mover *)(base + o_kb);
+    sd.hand = (fk::Mover *)(base + o_hand);
     sd.ctr = (int32_t *)(base + o_ctr);
     sd.stat = (unsigned long long *)(base + o_stat);
 
@@ -357,7 +360,7 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     int group = motion_group(b.n);
     if (group > std::max(2, c->move_capacity / 2)) group = std::max(1, c->move_capacity / 2);
     std::vector<uint32_t> mitems((size_t)group);
-    for (int g = 0; g < group; ++g) mitems[g] = motion_item(h, g, group);
+    for (int g = 0; g < group; ++g) mitems[g] = motion_item(h, g, group, true);
 
     hipError_t e = hipSuccess;
     auto cp = [&](size_t o, const void *src, size_t bytes) {
