@@ -355,16 +355,36 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Inclusive prefix sum of sh[0 .. MOVE_THREADS) in place (all threads call).
+// Inclusive prefix sum of sh[0 .. MOVE_THREADS) in place (all threads call;
+// each thread's own element must be in place): a shuffle scan within each
+// wavefront, then one over the wavefront totals, three workgroup barriers in
+// all.
 __device__ __forceinline__ void block_scan(int *sh)
 {
-    const int tid = threadIdx.x;
-    for (int off = 1; off < MOVE_THREADS; off <<= 1) {
-        const int add = tid >= off ? sh[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += add;
-        __syncthreads();
+    constexpr int NW = MOVE_THREADS / 64;
+    __shared__ int wsum[NW];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int x = sh[tid];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    if (wv == 0) {
+        int t = lane < NW ? wsum[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < NW; off <<= 1) {
+            const int y = __shfl_up(t, off);
+            if (lane >= off) t += y;
+        }
+        if (lane < NW) wsum[lane] = t;
+    }
+    __syncthreads();
+    if (wv > 0) x += wsum[wv - 1];
+    sh[tid] = x;
+    __syncthreads();
 }
 
 // The mover of record rec (an agent's plan) with its priority word
@@ -432,7 +452,6 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
         for (int j0 = 0; j0 < Tc; j0 += MOVE_THREADS) {
             const int nt = min(MOVE_THREADS, Tc - j0);
             sh_scan[tid] = tid < nt ? s.seg_cnt[c + (j0 + tid) * stride] : 0;
-            __syncthreads();
             block_scan(sh_scan);
             if (tid < nt) sh_tp[j0 + tid] = sh_scan[tid] + carry;
             carry += sh_scan[MOVE_THREADS - 1];
@@ -466,7 +485,6 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
         for (int j0 = 0; j0 < nt_g; j0 += MOVE_THREADS) {
             const int nt = min(MOVE_THREADS, nt_g - j0);
             sh_scan[tid] = tid < nt ? s.seg_cnt[t0 + j0 + tid] : 0;
-            __syncthreads();
             block_scan(sh_scan);
             const int chunk = sh_scan[MOVE_THREADS - 1];
             if (tid == 0) sh_kept = 0;
