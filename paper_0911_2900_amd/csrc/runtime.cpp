@@ -494,7 +494,8 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     const std::vector<int> G = batch_groups(c, order);
     std::vector<uint32_t> mitems;
     for (size_t i = 0; i < order.size(); ++i)
-        for (int g = 0; g < G[i]; ++g) mitems.push_back(motion_item(order[i], g, G[i]));
+        for (int g = 0; g < G[i]; ++g)
+            mitems.push_back(motion_item(order[i], g, G[i], order.size() == 1));
     Batch b;
     b.members = hs;
     b.v = c->slots[order[0]].dev.v;
