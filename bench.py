@@ -373,6 +373,49 @@ def sweep_n(ctx, torch, warmup: int, steps: int):
     return out
 
 
+def sweep_cu(torch, warmup: int, steps: int):
+    """The room at v_m = 4 with 10,000 / 40,000 / 150,000 agents on streams
+    confined to 8 .. 256 CUs (n / 8 on each XCD): how planning and the whole
+    step speed up with more of the chip, the counterpart of the paper's speed
+    factor over the number of cores (Sec. 3).  A batched planning launch of
+    16 rooms (640,000 agents) shows the same with enough tiles to fill every
+    CU.  Speed-ups are relative to 8 CUs."""
+    from paper_0911_2900_amd import fast
+    from paper_0911_2900_amd import scenarios as sc
+
+    rooms = [sc.room(v=4, scn=k) for k in range(16)]
+    out = []
+    for n_cu in (8, 16, 32, 64, 128, 256):
+        cs = fast.CUStream(n_cu)
+        log(f"{n_cu} CUs: probe reached {cs.n_cus_run}, per XCD {cs.per_xcd}")
+        ctx = fast.Context(stream=cs.torch)
+        try:
+            for n in (10000, 40000, 150000):
+                r = bench_room(ctx, torch, warmup, steps, v=4, n_agents=n)
+                out.append({"cus": n_cu, "cus_reached": cs.n_cus_run, "ctx_cus": ctx.cus(),
+                            "agents": n,
+                            "planning_agent_updates_per_s": r["planned"] / (sum(r["plan_ms"]) / 1e3),
+                            "plan_us": float(np.mean(r["plan_ms"])) * 1e3,
+                            "whole_step_us": r["total_ms"] / steps * 1e3})
+                log(f"{n_cu} CUs, N={n}: {out[-1]}")
+            r = bench_batch_plan(ctx, torch, rooms, "16 x room", 2, steps)
+            out.append({"cus": n_cu, "cus_reached": cs.n_cus_run, "ctx_cus": ctx.cus(),
+                        "agents": r["agents"], "batch": "16 rooms, one planning launch",
+                        "planning_agent_updates_per_s": r["planning_agent_updates_per_s"],
+                        "plan_us": r["roofline"]["avg_launch_us"], "whole_step_us": None})
+            log(f"{n_cu} CUs, 16 rooms: {out[-1]}")
+        finally:
+            ctx.close()
+            cs.close()
+    base = {o["agents"]: o for o in out if o["cus"] == 8}
+    for o in out:
+        b = base[o["agents"]]
+        o["plan_speedup_vs_8"] = b["plan_us"] / o["plan_us"]
+        if o["whole_step_us"] is not None:
+            o["step_speedup_vs_8"] = b["whole_step_us"] / o["whole_step_us"]
+    return out
+
+
 def achievable(ctx, achieved_gbs: float, footprint: float, stream_4g: float) -> dict:
     """The planning launch's algorithmic rate against what the streaming
     kernel reaches beyond the cache (4 GiB) and at the launch's own
@@ -451,6 +494,8 @@ def main():
                     help="only the room at v_m = 4 with 5k .. 150k agents")
     ap.add_argument("--sweep-v", action="store_true",
                     help="only time the room at v_m = 1..5 and print one JSON line")
+    ap.add_argument("--sweep-cu", action="store_true",
+                    help="only the room at v_m = 4 (10k / 40k / 150k agents) on 8 .. 256 CUs")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the oracle on the host (one thread and all threads) per "
                          "workload and print one JSON line")
@@ -479,6 +524,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {n} bytes 5 times")
+        return
+    if args.sweep_cu:
+        print(json.dumps({"sweep_cu": sweep_cu(torch, args.warmup, args.steps)}), flush=True)
         return
     ctx = fast.Context(device=0)
     if args.sweep_v:

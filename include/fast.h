@@ -212,6 +212,44 @@ fast_status fast_timing_read(fast_ctx *ctx, float *ms, int32_t cap, int32_t *n);
 fast_status fast_stream_bandwidth(fast_ctx *ctx, size_t footprint, int32_t reps, double *gb_per_s,
                                   double *us_per_launch);
 
+/* ---- Running on part of the chip (CU scaling) ----------------------------- */
+
+/* Sec. 3 of the paper measures how the step time falls as the planning loop
+ * gets more of the machine's cores (1..8 cores of two quad-core Xeons).  The
+ * calls below give the same study on CUs: a context created on a stream from
+ * fast_cu_stream_create runs every kernel on that stream's CUs only. */
+
+/* Bits of a CU mask (n_words 32-bit words, bit b = CU b, as the HIP runtime
+ * numbers them) that enable n_cus of a device's device_cus CUs, n_cus / 8 on
+ * each of its eight XCDs whether the driver gives mask bit b to XCD
+ * b / (device_cus / 8) or to XCD b mod 8: no XCD is left without CUs for its
+ * share of a launch's workgroups.  Host only.  FAST_E_INVALID unless
+ * device_cus is a multiple of 64, n_words >= device_cus / 32 and n_cus is a
+ * multiple of 8 in 8..device_cus. */
+fast_status fast_cu_mask(int32_t n_cus, int32_t device_cus, uint32_t *mask, int32_t n_words);
+
+/* Creates a HIP stream (returned as a hipStream_t in *stream) whose kernels
+ * run on the n_cus CUs of fast_cu_mask, then launches a probe kernel on it
+ * that records where its workgroups run: *n_cus_run (may be NULL) receives
+ * the distinct CUs it reached, per_xcd (8 entries, may be NULL) how many of
+ * them lie on each XCD.  The caller owns the stream and releases it with
+ * fast_cu_stream_destroy after every context using it is destroyed.
+ * FAST_E_INVALID for a bad device or n_cus (as fast_cu_mask, on the device's
+ * CU count); FAST_E_DEVICE if the runtime refuses the mask. */
+fast_status fast_cu_stream_create(int32_t device, int32_t n_cus, void **stream, int32_t *n_cus_run,
+                                  int32_t *per_xcd);
+
+/* Synchronises and destroys a stream from fast_cu_stream_create. */
+fast_status fast_cu_stream_destroy(void *stream);
+
+/* CUs the context's stream can fill with co-resident workgroups: the
+ * device's count for an ordinary stream; for a CU-masked one eight times the
+ * fewest CUs that a probe launch at fast_ctx_create reached on any XCD (a
+ * dispatch deals its workgroups to the eight XCDs in turn), at most the
+ * mask's bit count and at least 1.  The motion phase sizes its groups of
+ * co-resident workgroups from this count. */
+fast_status fast_ctx_cus(fast_ctx *ctx, int32_t *n_cus);
+
 /* ---- Serving: continuous batching of scenario requests ------------------ */
 
 /* Starts serving on host threads of the context.  Builder threads (half the

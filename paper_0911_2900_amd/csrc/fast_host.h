@@ -63,6 +63,7 @@ extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, i
                                          hipStream_t stream, hipEvent_t start, hipEvent_t stop);
 extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *mitems, int n_items,
                                      hipStream_t stream);
-extern "C" hipError_t fk_move_capacity(int *blocks);
+extern "C" hipError_t fk_move_per_cu(int *per_cu);
+extern "C" hipError_t fk_cu_probe(hipStream_t stream, int n_wg, uint32_t *ids_host);
 extern "C" hipError_t fk_launch_stream(float4 *base, size_t n4, hipStream_t stream,
                                        hipEvent_t start, hipEvent_t stop);

@@ -606,18 +606,10 @@ extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *m
     return hipGetLastError();
 }
 
-// Workgroups of move_kernel that one device holds at once.
-extern "C" hipError_t fk_move_capacity(int *blocks)
+// Motion workgroups one CU holds at once.
+extern "C" hipError_t fk_move_per_cu(int *per_cu)
 {
-    int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fk::move_kernel,
-                                                                fk::MOVE_THREADS, 0);
-    if (e != hipSuccess) return e;
-    e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    *blocks = per_cu * cus;
-    return hipSuccess;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fk::move_kernel, fk::MOVE_THREADS,
+                                                        0);
 }
 

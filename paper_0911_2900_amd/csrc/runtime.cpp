@@ -111,7 +111,8 @@ struct fast_ctx {
     fast_free_fn free_fn = nullptr;
     void *user = nullptr;
     fk::SlotDev *table = nullptr;    // device, FAST_MAX_SLOTS entries
-    int move_capacity = 0;           // motion workgroups the device holds at once
+    int n_cus = 0;                   // CUs the stream's launches reach
+    int move_capacity = 0;           // motion workgroups those CUs hold at once
     std::vector<Slot> slots;
     std::map<std::vector<int32_t>, Batch> batches;
     std::vector<hipEvent_t> timing;  // kernel timing: start / stop pairs of plan launches
@@ -229,6 +230,56 @@ std::vector<int> batch_groups(const fast_ctx *c, const std::vector<int32_t> &hs)
         if (G[i] < motion_group(n)) q.push({(double)n / G[i], i});
     }
     return G;
+}
+
+// Distinct CUs one probe launch of n_wg workgroups occupies on `s`, and how
+// many of them lie on each of the XCDs 0..7 (per_xcd may be NULL).
+hipError_t probe_cus(hipStream_t s, int n_wg, int *seen, int32_t *per_xcd)
+{
+    n_wg = std::max(1, std::min(n_wg, 4096));
+    std::vector<uint32_t> ids((size_t)n_wg);
+    const hipError_t e = fk_cu_probe(s, n_wg, ids.data());
+    if (e != hipSuccess) return e;
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    *seen = (int)ids.size();
+    if (per_xcd) {
+        std::fill(per_xcd, per_xcd + 8, 0);
+        for (uint32_t id : ids)
+            if ((id >> 8) < 8) ++per_xcd[id >> 8];
+    }
+    return hipSuccess;
+}
+
+// CUs that launches on `s` can fill with co-resident workgroups: the whole
+// device unless the stream carries a CU mask with fewer bits (or its mask
+// cannot be read).  Then a probe launch counts the CUs it reaches on each XCD;
+// a dispatch hands its workgroups to the eight XCDs in turn, so the count is
+// eight times the fewest on any XCD (at most the mask's bits, at least 1),
+// and the motion phase never plans on more resident workgroups than that.
+hipError_t stream_cus(hipStream_t s, int device, int *n_cus)
+{
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+    int bits = 0;
+    if (hipExtStreamGetCUMask(s, (uint32_t)mask.size(), mask.data()) == hipSuccess)
+        for (uint32_t w : mask) bits += __builtin_popcount(w);
+    else
+        (void)hipGetLastError();
+    const bool known = bits > 0;
+    if (known && bits >= cus) {
+        *n_cus = cus;
+        return hipSuccess;
+    }
+    int seen = 0;
+    int32_t per_xcd[8];
+    e = probe_cus(s, 4 * (known ? bits : cus), &seen, per_xcd);
+    if (e != hipSuccess) return e;
+    const int fewest = *std::min_element(per_xcd, per_xcd + 8);
+    *n_cus = std::max(1, std::min(known ? bits : cus, 8 * fewest));
+    return hipSuccess;
 }
 
 fast_status check_desc(const fast_scenario_desc *d)
@@ -358,7 +409,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     for (size_t i = 0; i < ntiles; ++i) items[i] = ((uint32_t)h << 20) | (uint32_t)i;
     const int32_t self = h;
     int group = motion_group(b.n);
-    if (group > std::max(2, c->move_capacity / 2)) group = std::max(1, c->move_capacity / 2);
+    const int half = std::max(1, c->move_capacity / 2);
+    if (group > half) group = half;
     std::vector<uint32_t> mitems((size_t)group);
     for (int g = 0; g < group; ++g) mitems[g] = motion_item(h, g, group, true);
 
@@ -797,8 +849,15 @@ fast_status fast_ctx_create(int device, void *hip_stream, size_t hbm_budget, fas
         HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
     }
-    HIP_TRY(fk_move_capacity(&c->move_capacity));
-    hipError_t e = hipMalloc(&c->table, sizeof(fk::SlotDev) * FAST_MAX_SLOTS);
+    int per_cu = 0;
+    hipError_t e = stream_cus(c->stream, device, &c->n_cus);
+    if (e == hipSuccess) e = fk_move_per_cu(&per_cu);
+    if (e != hipSuccess) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        return fail(FAST_E_DEVICE, "CU count of the stream: %s", hipGetErrorString(e));
+    }
+    c->move_capacity = per_cu * c->n_cus;
+    e = hipMalloc(&c->table, sizeof(fk::SlotDev) * FAST_MAX_SLOTS);
     if (e != hipSuccess) {
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         return fail(FAST_E_NOMEM, "slot table: %s", hipGetErrorString(e));
@@ -828,6 +887,73 @@ fast_status fast_ctx_destroy(fast_ctx *c)
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
     delete c;
+    return FAST_OK;
+}
+
+fast_status fast_ctx_cus(fast_ctx *c, int32_t *n_cus)
+{
+    if (!c || !n_cus) return fail(FAST_E_INVALID, "ctx or n_cus is NULL");
+    *n_cus = c->n_cus;
+    return FAST_OK;
+}
+
+fast_status fast_cu_mask(int32_t n_cus, int32_t device_cus, uint32_t *mask, int32_t n_words)
+{
+    if (!mask || device_cus < 64 || device_cus % 64 || n_words < device_cus / 32)
+        return fail(FAST_E_INVALID, "device_cus %d must be a positive multiple of 64 and n_words "
+                    ">= device_cus / 32", device_cus);
+    if (n_cus < 8 || n_cus > device_cus || n_cus % 8)
+        return fail(FAST_E_INVALID, "n_cus %d: a multiple of 8 in 8..%d", n_cus, device_cus);
+    const int per = device_cus / 8, m = n_cus / 8;
+    std::fill(mask, mask + n_words, 0u);
+    // XCD j owns bits j*per .. j*per + per - 1 when the driver hands out the
+    // mask in blocks, and the bits b with b mod 8 == j when it interleaves.
+    // Block j takes whole residue classes mod 8 starting at j (class j, then
+    // j + 1, ...), so each XCD gets m bits under either rule.
+    for (int j = 0; j < 8; ++j) {
+        int taken = 0;
+        for (int i = 0; i < 8 && taken < m; ++i)
+            for (int k = (j + i) % 8; k < per && taken < m; k += 8, ++taken) {
+                const int b = j * per + k;
+                mask[b / 32] |= 1u << (b % 32);
+            }
+    }
+    return FAST_OK;
+}
+
+fast_status fast_cu_stream_create(int32_t device, int32_t n_cus, void **stream, int32_t *n_cus_run,
+                                  int32_t *per_xcd)
+{
+    if (!stream) return fail(FAST_E_INVALID, "stream is NULL");
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(FAST_E_INVALID, "device %d of %d", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+    const fast_status st = fast_cu_mask(n_cus, cus, mask.data(), (int32_t)mask.size());
+    if (st != FAST_OK) return st;
+    hipStream_t s = nullptr;
+    HIP_TRY(hipExtStreamCreateWithCUMask(&s, (uint32_t)mask.size(), mask.data()));
+    int seen = 0;
+    int32_t xcd[8];
+    const hipError_t e = probe_cus(s, 4 * n_cus, &seen, xcd);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return fail(FAST_E_DEVICE, "CU probe: %s", hipGetErrorString(e));
+    }
+    if (n_cus_run) *n_cus_run = seen;
+    if (per_xcd) std::copy(xcd, xcd + 8, per_xcd);
+    *stream = (void *)s;
+    return FAST_OK;
+}
+
+fast_status fast_cu_stream_destroy(void *stream)
+{
+    if (!stream) return fail(FAST_E_INVALID, "stream is NULL");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    HIP_TRY(hipStreamDestroy((hipStream_t)stream));
     return FAST_OK;
 }
 

@@ -81,6 +81,10 @@ def lib() -> ctypes.CDLL:
         "fast_timing_start": [P, I32],
         "fast_timing_read": [P, P, I32, P],
         "fast_stream_bandwidth": [P, ctypes.c_size_t, I32, P, P],
+        "fast_cu_mask": [I32, I32, P, I32],
+        "fast_cu_stream_create": [I32, I32, P, P, P],
+        "fast_cu_stream_destroy": [P],
+        "fast_ctx_cus": [P, P],
         "fast_serve_start": [P, ctypes.c_size_t, I32],
         "fast_serve_submit": [P, P, I32, P],
         "fast_serve_poll": [P, U64, P, P],
@@ -136,6 +140,39 @@ def guard_band(v: int) -> float:
     return lib().fast_guard_band(int(v))
 
 
+def cu_mask(n_cus: int, device_cus: int = 256) -> np.ndarray:
+    """The library's CU mask for n_cus CUs, n_cus / 8 per XCD (uint32 words)."""
+    mask = np.zeros(max(device_cus // 32, 1), dtype=np.uint32)
+    _check(lib().fast_cu_mask(int(n_cus), int(device_cus), _ptr(mask), len(mask)))
+    return mask
+
+
+class CUStream:
+    """A HIP stream whose kernels run on n_cus CUs of the device (n_cus / 8 on
+    each XCD); `torch` is the same stream for PyTorch, `n_cus_run` the CUs a
+    probe launch reached and `per_xcd` how they split over the XCDs.  Pass
+    `torch` as a Context's stream; close() after the contexts are destroyed."""
+
+    def __init__(self, n_cus: int, device: int = 0):
+        import torch
+
+        ptr = ctypes.c_void_p()
+        run = ctypes.c_int32(0)
+        per = np.zeros(8, dtype=np.int32)
+        _check(lib().fast_cu_stream_create(int(device), int(n_cus), ctypes.byref(ptr),
+                                           ctypes.byref(run), _ptr(per)))
+        self.ptr = ptr.value
+        self.n_cus = int(n_cus)
+        self.n_cus_run = run.value
+        self.per_xcd = per.tolist()
+        self.torch = torch.cuda.ExternalStream(self.ptr, device=device)
+
+    def close(self):
+        if self.ptr:
+            _check(lib().fast_cu_stream_destroy(ctypes.c_void_p(self.ptr)))
+            self.ptr = None
+
+
 def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, seed: int = 1,
               scn: int = 0, agent_xy=None, tile=None):
     """Descriptor plus the host arrays it points to (keep both alive)."""
@@ -188,6 +225,12 @@ class Context:
         self.ctx = ctx
         self.n_agents = {}
         self.v = {}
+
+    def cus(self) -> int:
+        """CUs this context's stream reaches (see fast_ctx_cus)."""
+        n = ctypes.c_int32(0)
+        _check(lib().fast_ctx_cus(self.ctx, ctypes.byref(n)))
+        return n.value
 
     # -- scenarios ---------------------------------------------------------
     def init_scenario(self, cell_type, n_agents=0, v=4, k_s=1.2, seed=1, scn=0, agent_xy=None,

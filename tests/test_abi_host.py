@@ -107,3 +107,22 @@ def test_guard_band_covers_the_fp32_rounding_bound(fast):
         assert band > (2 * d + 3) * u
         assert band < 5e-6
     assert fast.guard_band(0) < 0 and fast.guard_band(6) < 0
+
+
+@pytest.mark.parametrize("device_cus", [64, 256, 512])
+def test_cu_mask_is_balanced_under_either_xcd_rule(fast, device_cus):
+    """Every mask gives each of the eight XCDs n / 8 CUs, whether the driver
+    assigns mask bit b to XCD b // (device_cus / 8) or to XCD b mod 8."""
+    per = device_cus // 8
+    for n in range(8, device_cus + 1, 8):
+        m = fast.cu_mask(n, device_cus)
+        bits = np.array([(int(m[b // 32]) >> (b % 32)) & 1 for b in range(device_cus)])
+        assert bits.sum() == n
+        assert [int(bits[per * j: per * (j + 1)].sum()) for j in range(8)] == [n // 8] * 8
+        assert [int(bits[j::8].sum()) for j in range(8)] == [n // 8] * 8
+
+
+def test_cu_mask_rejects_bad_counts(fast):
+    for n, cus in [(0, 256), (4, 256), (12, 256), (264, 256), (8, 96), (8, 0)]:
+        with pytest.raises(fast.FastError):
+            fast.cu_mask(n, cus)

@@ -450,3 +450,52 @@ def test_uniform_batch_rooms(ctx, v, tile):
     launch by the specialised planning kernel."""
     members = [sc.room(n_agents=12000, v=v, scn=20 + k) for k in range(8)]
     _uniform_batch_vs_oracle(ctx, members, tile, 3)
+
+
+# ---- part of the chip: streams confined to n CUs ---------------------------
+
+def test_ordinary_stream_uses_every_cu(ctx):
+    import torch
+    assert ctx.cus() == torch.cuda.get_device_properties(0).multi_processor_count
+
+
+@pytest.mark.parametrize("n", [8, 32, 128])
+def test_cu_stream_reaches_its_cus(ctx, n):
+    """A stream made for n CUs runs a probe launch on exactly n distinct CUs,
+    n / 8 on each XCD."""
+    from paper_0911_2900_amd import fast
+    say(f"CU stream of {n} CUs")
+    cs = fast.CUStream(n)
+    try:
+        say("  reached", cs.n_cus_run, "per XCD", cs.per_xcd)
+        assert cs.n_cus_run == n
+        assert cs.per_xcd == [n // 8] * 8
+    finally:
+        cs.close()
+
+
+@pytest.mark.parametrize("n", [8, 64])
+def test_part_of_the_chip_matches_oracle(ctx, n):
+    """A context on a stream of n CUs sizes its motion groups for those CUs
+    and steps a 20,000-agent room, and a batch of ensemble members, exactly as
+    the oracle does."""
+    from paper_0911_2900_amd import fast
+    say(f"context on {n} CUs")
+    cs = fast.CUStream(n)
+    c = fast.Context(stream=cs.torch)
+    try:
+        assert c.cus() == n
+        s = sc.room(n_agents=20000, v=4)
+        sim, h = make_pair(c, s)
+        step_both(c, sim, h, 8, check_every=3, where=f"room on {n} CUs")
+        c.destroy(h)
+        members = [sc.ensemble_member(k) for k in (3, 4, 6, 7)]
+        pairs = [make_pair(c, m) for m in members]
+        c.run([h for _, h in pairs], 12)
+        for m, (sim, h) in zip(members, pairs):
+            sim.run(12)
+            compare_state(c, sim, h, where=f"{m.name} on {n} CUs")
+            c.destroy(h)
+    finally:
+        c.close()
+        cs.close()
