@@ -373,24 +373,25 @@ def sweep_n(ctx, torch, warmup: int, steps: int):
     return out
 
 
-def sweep_cu(torch, warmup: int, steps: int):
+def sweep_cu(torch, warmup: int, steps: int, cus=(8, 16, 32, 64, 128, 256),
+             agents=(10000, 40000, 150000), batch: bool = True):
     """The room at v_m = 4 with 10,000 / 40,000 / 150,000 agents on streams
     confined to 8 .. 256 CUs (n / 8 on each XCD): how planning and the whole
     step speed up with more of the chip, the counterpart of the paper's speed
     factor over the number of cores (Sec. 3).  A batched planning launch of
     16 rooms (640,000 agents) shows the same with enough tiles to fill every
-    CU.  Speed-ups are relative to 8 CUs."""
+    CU.  Speed-ups are relative to the fewest CUs timed (8 by default)."""
     from paper_0911_2900_amd import fast
     from paper_0911_2900_amd import scenarios as sc
 
-    rooms = [sc.room(v=4, scn=k) for k in range(16)]
+    rooms = [sc.room(v=4, scn=k) for k in range(16)] if batch else []
     out = []
-    for n_cu in (8, 16, 32, 64, 128, 256):
+    for n_cu in cus:
         cs = fast.CUStream(n_cu)
         log(f"{n_cu} CUs: probe reached {cs.n_cus_run}, per XCD {cs.per_xcd}")
         ctx = fast.Context(stream=cs.torch)
         try:
-            for n in (10000, 40000, 150000):
+            for n in agents:
                 r = bench_room(ctx, torch, warmup, steps, v=4, n_agents=n)
                 out.append({"cus": n_cu, "cus_reached": cs.n_cus_run, "ctx_cus": ctx.cus(),
                             "agents": n,
@@ -398,6 +399,8 @@ def sweep_cu(torch, warmup: int, steps: int):
                             "plan_us": float(np.mean(r["plan_ms"])) * 1e3,
                             "whole_step_us": r["total_ms"] / steps * 1e3})
                 log(f"{n_cu} CUs, N={n}: {out[-1]}")
+            if not batch:
+                continue
             r = bench_batch_plan(ctx, torch, rooms, "16 x room", 2, steps)
             out.append({"cus": n_cu, "cus_reached": cs.n_cus_run, "ctx_cus": ctx.cus(),
                         "agents": r["agents"], "batch": "16 rooms, one planning launch",
@@ -407,7 +410,7 @@ def sweep_cu(torch, warmup: int, steps: int):
         finally:
             ctx.close()
             cs.close()
-    base = {o["agents"]: o for o in out if o["cus"] == 8}
+    base = {o["agents"]: o for o in out if o["cus"] == min(cus)}
     for o in out:
         b = base[o["agents"]]
         o["plan_speedup_vs_8"] = b["plan_us"] / o["plan_us"]
@@ -495,7 +498,12 @@ def main():
     ap.add_argument("--sweep-v", action="store_true",
                     help="only time the room at v_m = 1..5 and print one JSON line")
     ap.add_argument("--sweep-cu", action="store_true",
-                    help="only the room at v_m = 4 (10k / 40k / 150k agents) on 8 .. 256 CUs")
+                    help="only the room at v_m = 4 (10k / 40k / 150k agents) and a 16-room "
+                         "planning launch on 8 .. 256 CUs")
+    ap.add_argument("--cus", default="8,16,32,64,128,256",
+                    help="--sweep-cu: CU counts (multiples of 8), comma-separated")
+    ap.add_argument("--sweep-agents", default="10000,40000,150000",
+                    help="--sweep-cu: room agent counts, comma-separated (empty: none)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the oracle on the host (one thread and all threads) per "
                          "workload and print one JSON line")
@@ -526,7 +534,10 @@ def main():
         log(f"copied {n} bytes 5 times")
         return
     if args.sweep_cu:
-        print(json.dumps({"sweep_cu": sweep_cu(torch, args.warmup, args.steps)}), flush=True)
+        cus = [int(x) for x in args.cus.split(",") if x]
+        agents = [int(x) for x in args.sweep_agents.split(",") if x]
+        print(json.dumps({"sweep_cu": sweep_cu(torch, args.warmup, args.steps, cus, agents,
+                                               batch=not args.no_large)}), flush=True)
         return
     ctx = fast.Context(device=0)
     if args.sweep_v:
