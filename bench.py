@@ -419,6 +419,59 @@ def sweep_cu(torch, warmup: int, steps: int, cus=(8, 16, 32, 64, 128, 256),
     return out
 
 
+def bench_fd(ctx, torch, steps: int = 396, per_density: int = 16):
+    """Fundamental-diagram ensemble: the corridor at 11 initial densities
+    (0.5 .. 5.5 P/m^2) x per_density seeds, all run together as one
+    graph-replayed batch for `steps` steps.  Timed twice over steps 2 ..
+    `steps` (the first step captures the graph): without region counts, and
+    with the measurement area's and the upstream region's counts recorded
+    after every step.  The counted run gives the diagram, binned by density,
+    with Weidmann's published fit beside it as context."""
+    from paper_0911_2900_amd import fd
+    from paper_0911_2900_amd import scenarios as sc
+
+    members = sc.fd_ensemble(per_density=per_density)
+    out = {"workload": f"{len(members)} corridors 100x10 cells, v_m=4, {steps} steps, batched",
+           "scenarios": len(members), "agents": int(sum(m.n_agents for m in members))}
+    rho_all, flow_all = [], []
+    for counted in (False, True):
+        hs = [ctx.init_scenario(m.cell_type, 0, m.v, m.k_s, m.seed, m.scn,
+                                agent_xy=m.meta["agent_xy"], tile=None) for m in members]
+        if counted:
+            for m, h in zip(members, hs):
+                ctx.set_regions(h, [m.meta["area"], m.meta["upstream"]], steps)
+        ctx.run(hs, 1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.run(hs, steps - 1)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        key = "counted" if counted else "plain"
+        out[key] = {"ms_per_step": ms / (steps - 1),
+                    "scenario_steps_per_s": len(hs) * (steps - 1) / (ms / 1e3)}
+        if counted:
+            for m, h in zip(members, hs):
+                rho, flow = fd.samples(ctx.regions(h), m.meta["area_m2"], m.meta["width_m"])
+                rho_all.append(rho)
+                flow_all.append(flow)
+        exited = sum(ctx.stats(h)["exited"] for h in hs)
+        out[key]["exited"] = int(exited)
+        for h in hs:
+            ctx.destroy(h)
+        log(f"fd {key}: {out[key]}")
+    out["count_overhead"] = out["counted"]["ms_per_step"] / out["plain"]["ms_per_step"] - 1.0
+    bins = fd.diagram(np.concatenate(rho_all), np.concatenate(flow_all))
+    for b in bins:
+        b["weidmann_flow"] = float(fd.weidmann_flow(np.array([b["rho_mean"]]))[0])
+    out["diagram"] = bins
+    if bins:
+        top = max(bins, key=lambda b: b["flow_mean"])
+        out["capacity"] = {"flow": top["flow_mean"], "at_density": top["rho_mean"]}
+    return out
+
+
 def achievable(ctx, achieved_gbs: float, footprint: float, stream_4g: float) -> dict:
     """The planning launch's algorithmic rate against what the streaming
     kernel reaches beyond the cache (4 GiB) and at the launch's own
@@ -504,6 +557,8 @@ def main():
                     help="--sweep-cu: CU counts (multiples of 8), comma-separated")
     ap.add_argument("--sweep-agents", default="10000,40000,150000",
                     help="--sweep-cu: room agent counts, comma-separated (empty: none)")
+    ap.add_argument("--fd", action="store_true",
+                    help="only the fundamental-diagram ensemble (176 corridors, region counts)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the oracle on the host (one thread and all threads) per "
                          "workload and print one JSON line")
@@ -540,6 +595,10 @@ def main():
                                                batch=not args.no_large)}), flush=True)
         return
     ctx = fast.Context(device=0)
+    if args.fd:
+        print(json.dumps({"fd": bench_fd(ctx, torch)}), flush=True)
+        ctx.close()
+        return
     if args.sweep_v:
         print(json.dumps({"sweep_v": sweep_v(ctx, torch, args.warmup, args.steps)}), flush=True)
         ctx.close()

@@ -198,6 +198,40 @@ fast_status fast_timing_start(fast_ctx *ctx, int32_t max_launches);
  * number timed, and stops timing. */
 fast_status fast_timing_read(fast_ctx *ctx, float *ms, int32_t cap, int32_t *n);
 
+/* ---- Region counts: the measurements behind a fundamental diagram -------- */
+
+/* The paper settles on v_m = 4 because the model then reproduces Weidmann's
+ * fundamental diagram of walking (Sec. 2).  Such a diagram is measured from
+ * counts: agents inside a measurement area give the density, and since agents
+ * only move, the drop in the number upstream of a line (with a closed
+ * upstream end) is the net flow across it.  FAST_MAX_REGIONS rectangles per
+ * scenario at most. */
+#define FAST_MAX_REGIONS 8
+
+/* Gives scenario `handle` n_regions rectangles, rects[4 r .. 4 r + 3] =
+ * (x0, y0, x1, y1) in grid cells, half-open: x0 <= x < x1, y0 <= y < y1.
+ * From now on every motion phase of the scenario (fast_move_step,
+ * fast_move_batch, fast_run) is followed by a count kernel that stores the
+ * number of agents on each rectangle's cells as row k of a series, k being
+ * the scenario's completed steps; rows 0 .. max_step exist, the row of the
+ * current step is filled during this call (which synchronises the context
+ * stream), rows of steps not reached hold -1.  The series lives in device
+ * memory from the context allocator (counted against the budget) and is
+ * freed with the scenario or by a new call; n_regions = 0 removes it.
+ * FAST_E_INVALID for n_regions outside 0..FAST_MAX_REGIONS, an empty
+ * rectangle or one outside the grid, or max_step outside 0..2^24 - 1.  On a
+ * device error the scenario is left without regions. */
+fast_status fast_set_regions(fast_ctx *ctx, int32_t handle, const int32_t *rects, int32_t n_regions,
+                             int32_t max_step);
+
+/* Copies the series of fast_set_regions into counts (row-major,
+ * rows x n_regions int32; capacity = ints available) after synchronising the
+ * context stream; *n_regions and *rows (either may be NULL) give its shape,
+ * 0 x 0 when the scenario has no regions (counts may then be NULL).
+ * FAST_E_INVALID if capacity is smaller than rows * n_regions. */
+fast_status fast_get_regions(fast_ctx *ctx, int32_t handle, int32_t *counts, int64_t capacity,
+                             int32_t *n_regions, int32_t *rows);
+
 /* ---- Bandwidth yardstick ------------------------------------------------- */
 
 /* Measures what a streaming kernel reaches at a given footprint: six arrays

@@ -201,6 +201,19 @@ class Sim:
         if lib().oracle_run(ctypes.byref(self._st), int(steps)) != 0:
             raise RuntimeError("run failed")
 
+    def region_counts(self, rects) -> np.ndarray:
+        """Agents present on each rectangle (x0, y0, x1, y1), half-open: the
+        counts a fundamental diagram is measured from (Sec. 2 ties v_m = 4 to
+        Weidmann's diagram).  Written out as the plain definition: one
+        comparison per agent and rectangle."""
+        rects = np.asarray(rects, dtype=np.int64).reshape(-1, 4)
+        out = np.zeros(len(rects), dtype=np.int64)
+        for r, (x0, y0, x1, y1) in enumerate(rects):
+            for i in range(self.n):
+                if self.alive[i] and x0 <= self.x[i] < x1 and y0 <= self.y[i] < y1:
+                    out[r] += 1
+        return out
+
 
 def num_threads() -> int:
     return lib().oracle_num_threads()

@@ -64,6 +64,11 @@ struct Slot {
     int host_steps = 0;          // steps launched (== device step once the stream drains)
     bool planned = false;        // a plan was launched after the last motion phase
     int n_agents = 0;
+    // region counts (fast_set_regions)
+    fk::RegionDev rhost{};       // host copy of the job
+    fk::RegionDev *rdev = nullptr;  // device: the job, then its series
+    size_t rbytes = 0;
+    int n_regions = 0;
 };
 
 struct Batch {
@@ -74,6 +79,8 @@ struct Batch {
     int32_t *slots = nullptr;
     int n_items = 0, n_mitems = 0, n_slots = 0;
     int v = 0, tx = 0;           // v_max and tile width shared by all members, else 0
+    fk::RegionDev *rjobs = nullptr;  // device: region-count jobs of the members that have them
+    int n_rjobs = 0;
     void *block = nullptr;
     size_t bytes = 0;
     std::vector<int32_t> members;
@@ -469,6 +476,7 @@ fast_status destroy_slot(fast_ctx *c, int32_t h)
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     HIP_TRY(hipStreamSynchronize(c->stream));
     drop_batches_with(c, h);
+    dev_free(c, s->rdev, s->rbytes);
     dev_free(c, s->block, s->bytes);
     *s = Slot();
     return FAST_OK;
@@ -554,8 +562,12 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     b.tx = c->slots[order[0]].dev.tx;
     for (int32_t h : order)
         if (c->slots[h].dev.v != b.v || c->slots[h].dev.tx != b.tx) b.v = b.tx = 0;
+    std::vector<fk::RegionDev> rj;
+    for (int32_t h : order)
+        if (c->slots[h].n_regions) rj.push_back(c->slots[h].rhost);
     const size_t ib = align_up(items.size() * 4, 256), mb = align_up(mitems.size() * 4, 256);
-    b.bytes = ib + mb + order.size() * 4;
+    const size_t ob = align_up(order.size() * 4, 256);
+    b.bytes = ib + mb + ob + rj.size() * sizeof(fk::RegionDev);
     fast_status st = dev_alloc(c, b.bytes, &b.block);
     if (st) return st;
     b.items = (uint32_t *)b.block;
@@ -564,6 +576,10 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     b.n_items = (int)items.size();
     b.n_mitems = (int)mitems.size();
     b.n_slots = (int)order.size();
+    b.rjobs = rj.empty() ? nullptr : (fk::RegionDev *)((char *)b.block + ib + mb + ob);
+    b.n_rjobs = (int)rj.size();
+    if (!rj.empty())
+        HIP_TRY(hipMemcpy(b.rjobs, rj.data(), rj.size() * sizeof(fk::RegionDev), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(b.items, items.data(), items.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(b.mitems, mitems.data(), mitems.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(b.slots, order.data(), order.size() * 4, hipMemcpyHostToDevice));
@@ -580,6 +596,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b)
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
     hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
+    if (e2 == hipSuccess) e2 = fk_launch_count(b->rjobs, b->n_rjobs, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -619,6 +636,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     for (int k = 0; k < steps; ++k) {
         HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
+        HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, c->stream));
     }
     for (int32_t h : hs) c->slots[h].host_steps += steps;
     return FAST_OK;
@@ -992,6 +1010,7 @@ fast_status fast_move_step(fast_ctx *c, int32_t h)
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     if (!s->planned) return fail(FAST_E_STATE, "scenario %d: motion without a plan of this step", h);
     HIP_TRY(fk_launch_move(c->table, s->mitems, s->group, c->stream));
+    if (s->n_regions) HIP_TRY(fk_launch_count(s->rdev, 1, c->stream));
     s->planned = false;
     s->host_steps += 1;
     return FAST_OK;
@@ -1071,10 +1090,90 @@ fast_status fast_move_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     st = get_batch(c, v, &b);
     if (st) return st;
     HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
+    HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, c->stream));
     for (int32_t h : v) {
         c->slots[h].planned = false;
         c->slots[h].host_steps += 1;
     }
+    return FAST_OK;
+}
+
+fast_status fast_set_regions(fast_ctx *c, int32_t h, const int32_t *rects, int32_t n_regions,
+                             int32_t max_step)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    if (n_regions < 0 || n_regions > fk::MAX_REGIONS || (n_regions && !rects))
+        return fail(FAST_E_INVALID, "n_regions %d outside 0..%d (or rects NULL)", n_regions,
+                    fk::MAX_REGIONS);
+    if (n_regions && (max_step < 0 || max_step >= (1 << 24)))
+        return fail(FAST_E_INVALID, "max_step %d outside 0..2^24-1", max_step);
+    const fk::SlotDev &d = s->dev;
+    for (int r = 0; r < n_regions; ++r) {
+        const int32_t *q = rects + 4 * r;
+        if (q[0] < 0 || q[1] < 0 || q[0] >= q[2] || q[1] >= q[3] || q[2] > d.W || q[3] > d.H)
+            return fail(FAST_E_INVALID, "rectangle %d (%d,%d)-(%d,%d) is empty or outside the %dx%d grid",
+                        r, q[0], q[1], q[2], q[3], d.W, d.H);
+    }
+    fk::RegionDev j{};
+    const size_t rows = (size_t)max_step + 1;
+    const size_t bytes = n_regions ? align_up(sizeof j, 256) + rows * n_regions * 4 : 0;
+    void *block = nullptr;
+    if (n_regions) {
+        fast_status st = dev_alloc(c, bytes, &block);
+        if (st) return st;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    drop_batches_with(c, h);                          // their graphs count the old regions
+    dev_free(c, s->rdev, s->rbytes);
+    s->rdev = nullptr;
+    s->rbytes = 0;
+    s->n_regions = 0;
+    s->rhost = fk::RegionDev{};
+    if (!n_regions) return FAST_OK;
+    j.occ = d.occ;
+    j.ctr = d.ctr;
+    j.series = (int32_t *)((char *)block + align_up(sizeof j, 256));
+    j.Wp = d.Wp;
+    j.pad = d.pad;
+    j.n = n_regions;
+    j.rows = (int32_t)rows;
+    std::copy(rects, rects + 4 * n_regions, j.rect);
+    // all on the context stream, in order: -1 for steps not reached, the job,
+    // then the count of the current step
+    hipError_t e = hipMemsetAsync(j.series, 0xFF, rows * n_regions * 4, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(block, &j, sizeof j, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = fk_launch_count((fk::RegionDev *)block, 1, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        dev_free(c, block, bytes);
+        return fail(FAST_E_DEVICE, "region setup: %s", hipGetErrorString(e));
+    }
+    s->rhost = j;
+    s->rdev = (fk::RegionDev *)block;
+    s->rbytes = bytes;
+    s->n_regions = n_regions;
+    return FAST_OK;
+}
+
+fast_status fast_get_regions(fast_ctx *c, int32_t h, int32_t *counts, int64_t capacity,
+                             int32_t *n_regions, int32_t *rows)
+{
+    if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    if (n_regions) *n_regions = s->n_regions;
+    if (rows) *rows = s->n_regions ? s->rhost.rows : 0;
+    if (!s->n_regions || !counts) return FAST_OK;
+    const int64_t total = (int64_t)s->rhost.rows * s->n_regions;
+    if (capacity < total)
+        return fail(FAST_E_INVALID, "counts holds %lld ints; the series has %lld", (long long)capacity,
+                    (long long)total);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(counts, s->rhost.series, (size_t)total * 4, hipMemcpyDeviceToHost));
     return FAST_OK;
 }
 

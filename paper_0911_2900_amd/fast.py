@@ -85,6 +85,8 @@ def lib() -> ctypes.CDLL:
         "fast_cu_stream_create": [I32, I32, P, P, P],
         "fast_cu_stream_destroy": [P],
         "fast_ctx_cus": [P, P],
+        "fast_set_regions": [P, I32, P, I32, I32],
+        "fast_get_regions": [P, I32, P, ctypes.c_int64, P, P],
         "fast_serve_start": [P, ctypes.c_size_t, I32],
         "fast_serve_submit": [P, P, I32, P],
         "fast_serve_poll": [P, U64, P, P],
@@ -276,6 +278,23 @@ class Context:
     def run(self, handles, steps: int):
         hs = np.ascontiguousarray(np.asarray(list(handles), dtype=np.int32))
         _check(lib().fast_run(self.ctx, _ptr(hs), len(hs), int(steps)))
+
+    # -- region counts -----------------------------------------------------
+    def set_regions(self, h: int, rects, max_step: int):
+        """Rectangles (x0, y0, x1, y1), half-open, whose agent counts are
+        recorded after every motion phase for steps 0 .. max_step."""
+        r = np.ascontiguousarray(np.asarray(rects, dtype=np.int32).reshape(-1, 4))
+        _check(lib().fast_set_regions(self.ctx, h, _ptr(r) if len(r) else None, len(r), int(max_step)))
+
+    def regions(self, h: int) -> np.ndarray:
+        """(rows, n_regions) int32: agents per rectangle when the step counter
+        was k (row k), -1 for steps not reached."""
+        n, rows = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().fast_get_regions(self.ctx, h, None, 0, ctypes.byref(n), ctypes.byref(rows)))
+        out = np.zeros((rows.value, n.value), dtype=np.int32)
+        if out.size:
+            _check(lib().fast_get_regions(self.ctx, h, _ptr(out), out.size, None, None))
+        return out
 
     # -- state -------------------------------------------------------------
     def state(self, h: int) -> dict:

@@ -20,6 +20,11 @@ Workloads:
                 clamped to half the free cells; v_m ~ U{1..5}.
   large         16 scenarios of 1000 x 1000 cells with 10 % pillars and four
                 10-cell exits centred on each side; 200,000 agents, v_m = 4.
+  fd_corridor   fundamental-diagram corridor: 100 x 10 free cells (40 m x 4 m)
+                in border walls, the whole right wall an exit, agents on
+                uniformly drawn cells of the first 50 columns at a given
+                density; a 10-column measurement area (x = 61..70) and the
+                region upstream of the line between columns 70 and 71.
 """
 from __future__ import annotations
 
@@ -176,3 +181,32 @@ def random_small(rng: np.random.Generator, W: int, H: int, pillar_frac: float,
     _add_pillars(t, rng, pillar_frac)
     n_free = int((t == FREE).sum())
     return Scenario(f"small_{W}x{H}", t, min(n_agents, max(0, n_free // 2)), v, k_s, seed, scn)
+
+
+CELL_M2 = 0.16                     # one 0.4 m x 0.4 m cell
+
+
+def fd_corridor(density: float, scn: int, length: int = 100, width: int = 10, fill: int = 50,
+                v: int = 4, seed: int = 5) -> Scenario:
+    """Corridor for a fundamental diagram at an initial `density` (persons
+    per m^2) over the first `fill` columns.  meta: agent_xy (n, 2), the
+    rectangles `area` (measurement area, 10 columns from x = 61, full width)
+    and `upstream` (every cell left of the line between x = 70 and x = 71),
+    area_m2 and width_m."""
+    W, H = length + 2, width + 2
+    t = walled_box(W, H)
+    t[1:H - 1, W - 1] = EXIT
+    n = min(int(round(density * fill * width * CELL_M2)), fill * width)
+    rng = np.random.default_rng([seed, scn])
+    cells = rng.choice(fill * width, size=n, replace=False)
+    xy = np.stack([1 + cells % fill, 1 + cells // fill], axis=1).astype(np.int32)
+    meta = {"agent_xy": xy, "area": (61, 1, 71, H - 1), "upstream": (0, 0, 71, H),
+            "area_m2": 10 * width * CELL_M2, "width_m": width * 0.4, "density0": density}
+    return Scenario(f"fd_{density:g}_{scn}", t, n, v, 1.2, seed, scn, meta)
+
+
+def fd_ensemble(densities=(0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0, 5.5),
+                per_density: int = 16) -> list:
+    """fd_corridor members: per_density seeds of each initial density,
+    scenario ids 1000 * (density index) + k."""
+    return [fd_corridor(d, 1000 * i + k) for i, d in enumerate(densities) for k in range(per_density)]

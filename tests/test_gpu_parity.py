@@ -499,3 +499,81 @@ def test_part_of_the_chip_matches_oracle(ctx, n):
     finally:
         c.close()
         cs.close()
+
+
+# ---- region counts (fundamental-diagram measurements) ---------------------
+
+def _fd_pair(ctx, m):
+    xy = m.meta["agent_xy"]
+    sim = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, agent_xy=xy)
+    h = ctx.init_scenario(m.cell_type, 0, m.v, m.k_s, m.seed, m.scn, agent_xy=xy, tile=None)
+    return sim, h
+
+
+def test_region_counts_match_oracle(ctx):
+    """Agents in the measurement area and upstream of the flow line, recorded
+    after every motion phase, equal the oracle's counts step by step: one
+    corridor stepped alone, two in a graph-replayed batch beside a member that
+    has no regions (whose state must stay exact too)."""
+    steps = 80
+    ms = [sc.fd_corridor(d, 900 + i) for i, d in enumerate((1.0, 3.0, 5.5))]
+    pairs = [_fd_pair(ctx, m) for m in ms]
+    other = sc.ensemble_member(3)
+    other_sim, other_h = make_pair(ctx, other)
+    rects = [[m.meta["area"], m.meta["upstream"]] for m in ms]
+    for r, (sim, h) in zip(rects, pairs):
+        ctx.set_regions(h, r, steps)
+    want = [[sim.region_counts(r)] for r, (sim, h) in zip(rects, pairs)]
+    sim0, h0 = pairs[0]
+    for _ in range(steps):
+        ctx.plan(h0)
+        ctx.move(h0)
+        sim0.step_once()
+        want[0].append(sim0.region_counts(rects[0]))
+    ctx.run([pairs[1][1], pairs[2][1], other_h], steps)
+    for i in (1, 2):
+        for _ in range(steps):
+            pairs[i][0].step_once()
+            want[i].append(pairs[i][0].region_counts(rects[i]))
+    for i, (sim, h) in enumerate(pairs):
+        got = ctx.regions(h)
+        say(ms[i].name, "area/upstream at steps 0, 20, 40, 80:", got[[0, 20, 40, 80]].tolist())
+        assert got.shape == (steps + 1, 2)
+        assert np.array_equal(got, np.array(want[i])), f"{ms[i].name}: counts differ"
+        compare_state(ctx, sim, h, where=ms[i].name)
+        ctx.destroy(h)
+    other_sim.run(steps)
+    compare_state(ctx, other_sim, other_h, where="member without regions")
+    ctx.destroy(other_h)
+
+
+def test_region_counts_set_mid_run_and_errors(ctx):
+    s = sc.corridor()
+    sim, h = make_pair(ctx, s)
+    for _ in range(4):
+        ctx.plan(h)
+        ctx.move(h)
+        sim.step_once()
+    rects = [(0, 0, 30, 25), (30, 0, 60, 25), (50, 8, 60, 17)]
+    ctx.set_regions(h, rects, 10)
+    want = {4: sim.region_counts(rects)}
+    ctx.run([h], 8)                      # two steps past the last row
+    for k in range(5, 13):
+        sim.step_once()
+        want[k] = sim.region_counts(rects)
+    got = ctx.regions(h)
+    assert got.shape == (11, 3)
+    assert (got[:4] == -1).all()
+    for k in range(4, 11):
+        assert got[k].tolist() == want[k].tolist(), f"step {k}"
+    from paper_0911_2900_amd import fast
+    for bad in ([(0, 0, 61, 25)], [(5, 5, 5, 9)], [(-1, 0, 3, 3)], [(0, 0, 2, 2)] * 9):
+        with pytest.raises(fast.FastError):
+            ctx.set_regions(h, bad, 10)
+    ctx.set_regions(h, [], 0)
+    assert ctx.regions(h).shape == (0, 0)
+    ctx.run([h], 2)
+    for _ in range(2):
+        sim.step_once()
+    compare_state(ctx, sim, h, where="after regions removed")
+    ctx.destroy(h)
