@@ -557,6 +557,8 @@ def main():
                     help="--sweep-cu: CU counts (multiples of 8), comma-separated")
     ap.add_argument("--sweep-agents", default="10000,40000,150000",
                     help="--sweep-cu: room agent counts, comma-separated (empty: none)")
+    ap.add_argument("--no-fd", action="store_true",
+                    help="leave the fundamental-diagram ensemble out of the default run")
     ap.add_argument("--fd", action="store_true",
                     help="only the fundamental-diagram ensemble (176 corridors, region counts)")
     ap.add_argument("--cpu-table", action="store_true",
@@ -650,6 +652,13 @@ def main():
         log("ensemble ...")
         ens = bench_ensemble(ctx, torch, 5, args.ensemble_steps, args.plain_steps)
         log(f"ensemble: {ens}")
+    fdr = None
+    if not args.no_fd:
+        log("fundamental-diagram ensemble ...")
+        f = bench_fd(ctx, torch)
+        fdr = {k: f[k] for k in ("workload", "scenarios", "agents", "plain", "counted",
+                                 "count_overhead", "capacity") if k in f}
+        log(f"fd: {fdr}")
     ctx.close()
 
     serving = None
@@ -694,6 +703,7 @@ def main():
             "avg_launch_us": avg_plan_ms * 1e3, "achievable": room_ach,
         },
         "ensemble": ens,
+        "fundamental_diagram": fdr,
         "large": large,
         "room_replicas": replicas,
         "serving": serving,
