@@ -66,6 +66,7 @@ extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *m
                                      hipStream_t stream);
 extern "C" hipError_t fk_move_per_cu(int *per_cu);
 extern "C" hipError_t fk_cu_probe(hipStream_t stream, int n_wg, uint32_t *ids_host);
-extern "C" hipError_t fk_launch_count(const fk::RegionDev *jobs, int n_jobs, hipStream_t stream);
+extern "C" hipError_t fk_launch_count(const fk::RegionDev *jobs, int n_jobs, int max_regions,
+                                      hipStream_t stream);
 extern "C" hipError_t fk_launch_stream(float4 *base, size_t n4, hipStream_t stream,
                                        hipEvent_t start, hipEvent_t stop);

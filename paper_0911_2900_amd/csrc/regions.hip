@@ -37,11 +37,13 @@ __global__ __launch_bounds__(COUNT_THREADS) void count_kernel(const RegionDev *j
 
 }  // namespace fk
 
-// One launch over n_jobs scenarios, each with up to MAX_REGIONS rectangles.
-extern "C" hipError_t fk_launch_count(const fk::RegionDev *jobs, int n_jobs, hipStream_t stream)
+// One launch over n_jobs scenarios with at most max_regions rectangles each.
+extern "C" hipError_t fk_launch_count(const fk::RegionDev *jobs, int n_jobs, int max_regions,
+                                      hipStream_t stream)
 {
-    if (n_jobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fk::count_kernel, dim3((unsigned)n_jobs, fk::MAX_REGIONS), dim3(fk::COUNT_THREADS),
-                       0, stream, jobs);
+    if (n_jobs <= 0 || max_regions <= 0) return hipSuccess;
+    if (max_regions > fk::MAX_REGIONS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fk::count_kernel, dim3((unsigned)n_jobs, (unsigned)max_regions),
+                       dim3(fk::COUNT_THREADS), 0, stream, jobs);
     return hipGetLastError();
 }

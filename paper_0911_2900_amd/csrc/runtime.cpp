@@ -80,7 +80,7 @@ struct Batch {
     int n_items = 0, n_mitems = 0, n_slots = 0;
     int v = 0, tx = 0;           // v_max and tile width shared by all members, else 0
     fk::RegionDev *rjobs = nullptr;  // device: region-count jobs of the members that have them
-    int n_rjobs = 0;
+    int n_rjobs = 0, max_regions = 0;
     void *block = nullptr;
     size_t bytes = 0;
     std::vector<int32_t> members;
@@ -564,7 +564,10 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
         if (c->slots[h].dev.v != b.v || c->slots[h].dev.tx != b.tx) b.v = b.tx = 0;
     std::vector<fk::RegionDev> rj;
     for (int32_t h : order)
-        if (c->slots[h].n_regions) rj.push_back(c->slots[h].rhost);
+        if (c->slots[h].n_regions) {
+            rj.push_back(c->slots[h].rhost);
+            b.max_regions = std::max(b.max_regions, c->slots[h].n_regions);
+        }
     const size_t ib = align_up(items.size() * 4, 256), mb = align_up(mitems.size() * 4, 256);
     const size_t ob = align_up(order.size() * 4, 256);
     b.bytes = ib + mb + ob + rj.size() * sizeof(fk::RegionDev);
@@ -596,7 +599,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b)
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
     hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
-    if (e2 == hipSuccess) e2 = fk_launch_count(b->rjobs, b->n_rjobs, c->stream);
+    if (e2 == hipSuccess) e2 = fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -636,7 +639,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     for (int k = 0; k < steps; ++k) {
         HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
-        HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, c->stream));
+        HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream));
     }
     for (int32_t h : hs) c->slots[h].host_steps += steps;
     return FAST_OK;
@@ -1010,7 +1013,7 @@ fast_status fast_move_step(fast_ctx *c, int32_t h)
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     if (!s->planned) return fail(FAST_E_STATE, "scenario %d: motion without a plan of this step", h);
     HIP_TRY(fk_launch_move(c->table, s->mitems, s->group, c->stream));
-    if (s->n_regions) HIP_TRY(fk_launch_count(s->rdev, 1, c->stream));
+    if (s->n_regions) HIP_TRY(fk_launch_count(s->rdev, 1, s->n_regions, c->stream));
     s->planned = false;
     s->host_steps += 1;
     return FAST_OK;
@@ -1090,7 +1093,7 @@ fast_status fast_move_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     st = get_batch(c, v, &b);
     if (st) return st;
     HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
-    HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, c->stream));
+    HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream));
     for (int32_t h : v) {
         c->slots[h].planned = false;
         c->slots[h].host_steps += 1;
@@ -1145,7 +1148,7 @@ fast_status fast_set_regions(fast_ctx *c, int32_t h, const int32_t *rects, int32
     // then the count of the current step
     hipError_t e = hipMemsetAsync(j.series, 0xFF, rows * n_regions * 4, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(block, &j, sizeof j, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = fk_launch_count((fk::RegionDev *)block, 1, c->stream);
+    if (e == hipSuccess) e = fk_launch_count((fk::RegionDev *)block, 1, n_regions, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         dev_free(c, block, bytes);
