@@ -581,11 +581,16 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     b.n_slots = (int)order.size();
     b.rjobs = rj.empty() ? nullptr : (fk::RegionDev *)((char *)b.block + ib + mb + ob);
     b.n_rjobs = (int)rj.size();
+    hipError_t e = hipSuccess;
     if (!rj.empty())
-        HIP_TRY(hipMemcpy(b.rjobs, rj.data(), rj.size() * sizeof(fk::RegionDev), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b.items, items.data(), items.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b.mitems, mitems.data(), mitems.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b.slots, order.data(), order.size() * 4, hipMemcpyHostToDevice));
+        e = hipMemcpy(b.rjobs, rj.data(), rj.size() * sizeof(fk::RegionDev), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b.items, items.data(), items.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b.mitems, mitems.data(), mitems.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b.slots, order.data(), order.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        dev_free(c, b.block, b.bytes);
+        return fail(FAST_E_DEVICE, "batch setup: %s", hipGetErrorString(e));
+    }
     auto res = c->batches.emplace(hs, b);
     *out = &res.first->second;
     return FAST_OK;
@@ -1128,7 +1133,11 @@ fast_status fast_set_regions(fast_ctx *c, int32_t h, const int32_t *rects, int32
         fast_status st = dev_alloc(c, bytes, &block);
         if (st) return st;
     }
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    const hipError_t es = hipStreamSynchronize(c->stream);
+    if (es != hipSuccess) {
+        dev_free(c, block, bytes);
+        return fail(FAST_E_DEVICE, "region setup: %s", hipGetErrorString(es));
+    }
     drop_batches_with(c, h);                          // their graphs count the old regions
     dev_free(c, s->rdev, s->rbytes);
     s->rdev = nullptr;
