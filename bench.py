@@ -436,7 +436,8 @@ def bench_fd(ctx, torch, steps: int = 396, per_density: int = 16):
     rho_all, flow_all = [], []
     for counted in (False, True):
         hs = [ctx.init_scenario(m.cell_type, 0, m.v, m.k_s, m.seed, m.scn,
-                                agent_xy=m.meta["agent_xy"], tile=None) for m in members]
+                                agent_xy=m.meta["agent_xy"], tile="auto", batched=True)
+              for m in members]
         if counted:
             for m, h in zip(members, hs):
                 ctx.set_regions(h, [m.meta["area"], m.meta["upstream"]], steps)
@@ -458,6 +459,7 @@ def bench_fd(ctx, torch, steps: int = 396, per_density: int = 16):
                 flow_all.append(flow)
         exited = sum(ctx.stats(h)["exited"] for h in hs)
         out[key]["exited"] = int(exited)
+        out["tile"] = [ctx.stats(hs[0])["tile_w"], ctx.stats(hs[0])["tile_h"]]
         for h in hs:
             ctx.destroy(h)
         log(f"fd {key}: {out[key]}")
