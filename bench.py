@@ -95,11 +95,15 @@ def window_cells(cell_type: np.ndarray, xy: np.ndarray, v: int) -> int:
     return int(binary_dilation(occ, structure=disc).sum())
 
 
-def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4, n_agents: int = 40000):
+def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4, n_agents: int = 40000,
+               agent_v=None):
     from paper_0911_2900_amd import scenarios as sc
 
     s = sc.room(v=v, n_agents=n_agents)
-    h = ctx.init_from(s)
+    if agent_v is None:
+        h = ctx.init_from(s)
+    else:
+        h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, agent_v=agent_v)
     for _ in range(warmup):
         ctx.plan(h)
         ctx.move(h)
@@ -474,6 +478,25 @@ def bench_fd(ctx, torch, steps: int = 396, per_density: int = 16):
     return out
 
 
+def bench_het(ctx, torch, warmup: int, steps: int):
+    """The room (40,000 agents) with a maximum speed per agent drawn
+    uniformly from 1..5 (v_max = 5): every draw in FP64 with the agent's own
+    disc.  Beside it the same room with v_m = 5 for everybody (FP32 table
+    path)."""
+    vi = np.random.default_rng(11).integers(1, 6, size=40000)
+    out = {}
+    for key, av in (("per_agent_speeds", vi), ("uniform_v5", None)):
+        r = bench_room(ctx, torch, warmup, steps, v=5, agent_v=av)
+        out[key] = {"planning_agent_updates_per_s": r["planned"] / (sum(r["plan_ms"]) / 1e3),
+                    "plan_us": float(np.mean(r["plan_ms"])) * 1e3,
+                    "whole_step_us": r["total_ms"] / steps * 1e3,
+                    "tile": [r["stats"]["tile_w"], r["stats"]["tile_h"]],
+                    "fp64_draws_per_step": r["stats"]["fallback"] / (warmup + steps)}
+        log(f"het {key}: {out[key]}")
+    out["workload"] = "room 400x400, 40,000 agents, speeds U{1..5} (v_max = 5)"
+    return out
+
+
 def achievable(ctx, achieved_gbs: float, footprint: float, stream_4g: float) -> dict:
     """The planning launch's algorithmic rate against what the streaming
     kernel reaches beyond the cache (4 GiB) and at the launch's own
@@ -559,6 +582,8 @@ def main():
                     help="--sweep-cu: CU counts (multiples of 8), comma-separated")
     ap.add_argument("--sweep-agents", default="10000,40000,150000",
                     help="--sweep-cu: room agent counts, comma-separated (empty: none)")
+    ap.add_argument("--het", action="store_true",
+                    help="only the room with a maximum speed per agent (FP64 planning path)")
     ap.add_argument("--no-fd", action="store_true",
                     help="leave the fundamental-diagram ensemble out of the default run")
     ap.add_argument("--fd", action="store_true",
@@ -601,6 +626,10 @@ def main():
     ctx = fast.Context(device=0)
     if args.fd:
         print(json.dumps({"fd": bench_fd(ctx, torch)}), flush=True)
+        ctx.close()
+        return
+    if args.het:
+        print(json.dumps({"het": bench_het(ctx, torch, args.warmup, args.steps)}), flush=True)
         ctx.close()
         return
     if args.sweep_v:

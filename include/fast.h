@@ -100,6 +100,12 @@ typedef struct {
     int32_t tile_w, tile_h;      /* planning tile in cells; 0, 0 = tuned choice;
                                     otherwise powers of two in 8..64 with
                                     tile_w * tile_h <= 1024                          */
+    const uint8_t *agent_v;      /* host, n_agents speeds in 1..v_max (agent i reaches
+                                    dx^2 + dy^2 <= agent_v[i]^2), or NULL: all v_max.
+                                    Such a scenario plans every draw in FP64 (a
+                                    slower path) and is stepped alone: batched calls
+                                    (fast_run, fast_*_batch), serving and
+                                    fast_debug_plan refuse it with FAST_E_INVALID   */
 } fast_scenario_desc;
 
 /* Counters of one scenario. */

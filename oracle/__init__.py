@@ -46,6 +46,7 @@ class _State(ctypes.Structure):
         ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
         ("alive", ctypes.c_void_p), ("desired", ctypes.c_void_p),
         ("occ", ctypes.c_void_p), ("exited", ctypes.c_int64),
+        ("vi", ctypes.c_void_p),
     ]
 
 
@@ -116,7 +117,7 @@ class Sim:
     """Oracle model state: one scenario, stepped on the CPU."""
 
     def __init__(self, cell_type: np.ndarray, v: int, k_s: float, seed: int, scn: int,
-                 n_agents: int | None = None, agent_xy=None):
+                 n_agents: int | None = None, agent_xy=None, agent_v=None):
         self.type, self.S, self.a, self.b = floor_field(cell_type)
         self.H, self.W = self.type.shape
         if agent_xy is None:
@@ -143,6 +144,15 @@ class Sim:
         self._st.x, self._st.y = _ptr(self.x), _ptr(self.y)
         self._st.alive, self._st.desired = _ptr(self.alive), _ptr(self.desired)
         self._st.occ, self._st.exited = _ptr(self.occ), 0
+        # per-agent speeds: agent i reaches only its own disc dx^2 + dy^2 <= v_i^2
+        # inside the (2v+1)^2 window (v = the largest speed)
+        self.agent_v = None
+        if agent_v is not None:
+            self.agent_v = np.ascontiguousarray(np.asarray(agent_v, dtype=np.uint8)).copy()
+            if len(self.agent_v) != self.n or (self.n and (self.agent_v.min() < 1
+                                                           or self.agent_v.max() > v)):
+                raise ValueError("agent_v: one speed in 1..v per agent")
+            self._st.vi = _ptr(self.agent_v) if self.n else None
         if lib().oracle_reset_occ(ctypes.byref(self._st)) != 0:
             raise ValueError("invalid agent positions")
 

@@ -273,6 +273,9 @@ typedef struct {
     int32_t *desired;       /* y*W + x of the planned cell; -1 when not alive      */
     int32_t *occ;           /* W*H: -1 free, else the id of the agent on the cell  */
     int64_t exited;
+    const uint8_t *vi;      /* optional, n: agent i's own maximum speed (1..v); NULL:
+                               every agent has v.  The window stays (2v+1)^2; agent i
+                               reaches the cells of its own disc dx^2 + dy^2 <= vi^2 */
 } oracle_state;
 
 /* Rebuilds occupancy from positions; returns -1 if an agent is off-grid, on
@@ -310,6 +313,7 @@ int32_t oracle_plan_agent(const oracle_state *st, int32_t i, double *w_out,
 {
     if (!st->alive[i]) return -1;
     const int32_t v = st->v, side = 2 * v + 1, W = st->W, H = st->H;
+    const int32_t vr = st->vi ? st->vi[i] : v;    /* the agent's own reach */
     const int32_t cx = st->x[i], cy = st->y[i];
     const int64_t c = (int64_t)cy * W + cx;
     double *w = malloc(sizeof(double) * (size_t)(side * side));
@@ -320,7 +324,7 @@ int32_t oracle_plan_agent(const oracle_state *st, int32_t i, double *w_out,
         for (int32_t dx = -v; dx <= v; ++dx) {
             int32_t slot = (dy + v) * side + (dx + v);
             int32_t tx = cx + dx, ty = cy + dy;
-            int in_reach = dx * dx + dy * dy <= v * v;
+            int in_reach = dx * dx + dy * dy <= vr * vr;
             int in_grid = tx >= 0 && ty >= 0 && tx < W && ty < H;
             double wt = 0.0;
             if (in_reach && in_grid) {

@@ -206,6 +206,11 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
         err = "more agents than eligible cells";
         return FAST_E_INVALID;
     }
+    if (d.agent_v) {
+        b.vi.assign(d.agent_v, d.agent_v + d.n_agents);
+        for (uint8_t s : b.vi)
+            if (s < 1 || s > v) { err = "agent_v values must lie in 1..v_max"; return FAST_E_INVALID; }
+    }
 
     // padded layout
     b.ntx = (W + tx - 1) / tx;

@@ -64,6 +64,7 @@ struct Slot {
     int host_steps = 0;          // steps launched (== device step once the stream drains)
     bool planned = false;        // a plan was launched after the last motion phase
     int n_agents = 0;
+    uint8_t *vi = nullptr;       // device: per-agent speeds (NULL: every agent has v_max)
     // region counts (fast_set_regions)
     fk::RegionDev rhost{};       // host copy of the job
     fk::RegionDev *rdev = nullptr;  // device: the job, then its series
@@ -377,7 +378,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
                  o_kb = take(lcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
                  o_mitems = take(fk::MOVE_GROUP_MAX * 4),
-                 o_hand = take((size_t)fk::MOVE_GROUP_MAX * fk::MOVE_SOLO_MAX * sizeof(fk::Mover));
+                 o_hand = take((size_t)fk::MOVE_GROUP_MAX * fk::MOVE_SOLO_MAX * sizeof(fk::Mover)),
+                 o_vi = take(b.vi.size());
     void *block = nullptr;
     st = dev_alloc(c, off, &block);
     if (st) return st;
@@ -439,6 +441,7 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     cp(o_items, items.data(), ntiles * 4);
     cp(o_self, &self, 4);
     cp(o_mitems, mitems.data(), mitems.size() * 4);
+    cp(o_vi, b.vi.data(), b.vi.size());
     if (e == hipSuccess) e = hipMemcpy(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         dev_free(c, block, off);
@@ -458,6 +461,7 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     s.n_items = (int)ntiles;
     s.n_fb_tiles = b.n_fb;
     s.n_agents = b.n;
+    s.vi = b.vi.empty() ? nullptr : (uint8_t *)(base + o_vi);
     *handle = h;
     return FAST_OK;
 }
@@ -536,6 +540,10 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
 {
     auto it = c->batches.find(hs);
     if (it != c->batches.end()) { *out = &it->second; return FAST_OK; }
+    for (int32_t h : hs)
+        if (c->slots[h].vi)
+            return fail(FAST_E_INVALID, "scenario %d has per-agent speeds: step it alone "
+                        "(fast_plan_step, fast_move_step)", h);
     for (int32_t h : hs)                              // items carry a 20-bit tile index
         if (c->slots[h].n_items > (1 << 20))
             return fail(FAST_E_INVALID, "scenario %d has %d tiles; batched launches take at most 2^20 "
@@ -1005,7 +1013,10 @@ fast_status fast_plan_step(fast_ctx *c, int32_t h)
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     next_timing_pair(c, &e0, &e1);
-    HIP_TRY(fk_launch_plan_one(&s->dev, s->n_items, 0, c->stream, e0, e1));
+    if (s->vi)
+        HIP_TRY(fk_launch_plan_het(&s->dev, s->vi, s->n_items, c->stream, e0, e1));
+    else
+        HIP_TRY(fk_launch_plan_one(&s->dev, s->n_items, 0, c->stream, e0, e1));
     s->planned = true;
     return FAST_OK;
 }
@@ -1236,6 +1247,7 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     std::lock_guard<std::recursive_mutex> g(c->mu);
     Slot *s = get_slot(c, h);
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    if (s->vi) return fail(FAST_E_INVALID, "scenario %d has per-agent speeds: no debug dump", h);
     const int n = std::max(s->n_agents, 1);
     const int side = 2 * s->dev.v + 1;
     const size_t bw = align_up((size_t)n * side * side * 4, 256), bf = align_up((size_t)n, 256),
@@ -1319,6 +1331,7 @@ fast_status fast_serve_submit(fast_ctx *c, const fast_scenario_desc *d, int32_t 
     if (!c || !ticket || steps < 0) return fail(FAST_E_INVALID, "bad arguments to fast_serve_submit");
     fast_status st = check_desc(d);
     if (st) return st;
+    if (d->agent_v) return fail(FAST_E_INVALID, "per-agent speeds are not served (step such a scenario alone)");
     std::unique_ptr<Request> r(new Request());
     r->desc = *d;
     r->cells.assign(d->cell_type, d->cell_type + (size_t)d->width * d->height);

@@ -33,6 +33,7 @@ class ScenarioDesc(ctypes.Structure):
         ("v_max", ctypes.c_int32), ("k_s", ctypes.c_double),
         ("seed", ctypes.c_uint64), ("scenario_id", ctypes.c_uint32),
         ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+        ("agent_v", ctypes.c_void_p),
     ]
 
 
@@ -176,7 +177,7 @@ class CUStream:
 
 
 def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, seed: int = 1,
-              scn: int = 0, agent_xy=None, tile=None):
+              scn: int = 0, agent_xy=None, tile=None, agent_v=None):
     """Descriptor plus the host arrays it points to (keep both alive)."""
     ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
     H, W = ct.shape
@@ -192,7 +193,13 @@ def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, se
     d.v_max, d.k_s = int(v), float(k_s)
     d.seed, d.scenario_id = int(seed), int(scn)
     d.tile_w, d.tile_h = (0, 0) if tile is None else (int(tile[0]), int(tile[1]))
-    return d, (ct, xy)
+    sv = None
+    if agent_v is not None:
+        sv = np.ascontiguousarray(np.asarray(agent_v, dtype=np.uint8))
+        if len(sv) != d.n_agents:
+            raise ValueError("agent_v needs one speed per agent")
+        d.agent_v = _ptr(sv) if len(sv) else None
+    return d, (ct, xy, sv)
 
 
 class Context:
@@ -236,7 +243,7 @@ class Context:
 
     # -- scenarios ---------------------------------------------------------
     def init_scenario(self, cell_type, n_agents=0, v=4, k_s=1.2, seed=1, scn=0, agent_xy=None,
-                      tile="auto", batched=False) -> int:
+                      tile="auto", batched=False, agent_v=None) -> int:
         """tile: (tx, ty); "auto" = the autotuner's table (planned alone, or in
         a batched launch when `batched`), None = the library's own rule."""
         if isinstance(tile, str):
@@ -244,7 +251,7 @@ class Context:
             ct = np.asarray(cell_type)
             n = len(agent_xy) if agent_xy is not None else int(n_agents)
             tile = autotune.choose_tile(int(v), int(ct.shape[1]), int(ct.shape[0]), n, batched)
-        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_xy, tile)
+        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_xy, tile, agent_v)
         h = ctypes.c_int32(-1)
         _check(lib().fast_init_scenario(self.ctx, ctypes.byref(d), ctypes.byref(h)))
         self.n_agents[h.value] = d.n_agents

@@ -577,3 +577,60 @@ def test_region_counts_set_mid_run_and_errors(ctx):
         sim.step_once()
     compare_state(ctx, sim, h, where="after regions removed")
     ctx.destroy(h)
+
+
+# ---- per-agent maximum speeds ------------------------------------------------
+
+def _het_pair(ctx, s, vi, tile=None):
+    sim = oracle.Sim(s.cell_type, s.v, s.k_s, s.seed, s.scn, n_agents=s.n_agents, agent_v=vi)
+    h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=tile, agent_v=vi)
+    return sim, h
+
+
+@pytest.mark.parametrize("v,tile", [(5, None), (3, (16, 16)), (4, (32, 8))])
+def test_per_agent_speeds_match_oracle(ctx, v, tile):
+    """A room of 20,000 agents with speeds drawn from 1..v: every plan and
+    every position equal the oracle's, step by step."""
+    s = sc.room(n_agents=20000, v=v)
+    vi = np.random.default_rng(v).integers(1, v + 1, size=s.n_agents)
+    say(f"per-agent speeds 1..{v}, tile {tile}")
+    sim, h = _het_pair(ctx, s, vi, tile)
+    step_both(ctx, sim, h, 12, check_every=1, where=f"speeds 1..{v}")
+    assert ctx.stats(h)["fallback"] > 0          # every draw on the FP64 path
+    ctx.destroy(h)
+
+
+def test_speeds_all_v_max_match_the_uniform_kernels(ctx):
+    """Speeds that are all v_max give the trajectories of the uniform
+    kernels (two GPU paths, then the oracle at the end)."""
+    s = sc.corridor()
+    sim = oracle.Sim(s.cell_type, s.v, s.k_s, s.seed, s.scn, n_agents=s.n_agents)
+    hu = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=None)
+    hh = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=None,
+                           agent_v=np.full(s.n_agents, s.v))
+    for k in range(60):
+        for h in (hu, hh):
+            ctx.plan(h)
+            ctx.move(h)
+        if k % 10 == 0:
+            a, b = ctx.state(hu), ctx.state(hh)
+            assert np.array_equal(a["xy"], b["xy"]), f"step {k}"
+    sim.run(60)
+    compare_state(ctx, sim, hh, where="speeds all v_max")
+    ctx.destroy(hu)
+    ctx.destroy(hh)
+
+
+def test_per_agent_speeds_refused_where_unsupported(ctx):
+    from paper_0911_2900_amd import fast
+    s = sc.corridor()
+    vi = np.random.default_rng(0).integers(1, 5, size=s.n_agents)
+    h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=None, agent_v=vi)
+    for call in (lambda: ctx.run([h], 1), lambda: ctx.plan_batch([h]), lambda: ctx.debug_plan(h)):
+        with pytest.raises(fast.FastError):
+            call()
+    ctx.destroy(h)
+    for bad in (np.zeros(s.n_agents), np.full(s.n_agents, 5)):
+        with pytest.raises(fast.FastError):
+            ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=None,
+                              agent_v=bad)
