@@ -14,35 +14,58 @@
 
 namespace fk {
 
-// Agent at padded cell gc with reach vr: the chosen padded cell.
+// Agent at padded cell gc with reach vr: the chosen padded cell.  The first
+// pass sums the weights sequentially in raster order and keeps the prefix at
+// the end of every window row; the second starts from the prefix before the
+// first row whose end exceeds tau and sums that row again, cell by cell.  Its
+// prefixes are the very values of the full sequential sum, so the choice is
+// the same, at one row of exps instead of the whole window.
+template <int V>
+__device__ __forceinline__ bool reach_het(const SlotDev &s, int gc, int t, int dx, int dy, int vr)
+{
+    return dx * dx + dy * dy <= vr * vr && (s.cell[t] & CELL_TYPE_MASK) != CELL_WALL &&
+           (s.occ[t] < 0 || t == gc);
+}
+
 template <int V>
 __device__ int draw_het(const SlotDev &s, int gc, float u32, int vr)
 {
+    constexpr int SIDE = 2 * V + 1;
     const double Sc = s.S[gc];
     const double ks = s.k_s;
+    double rowC[SIDE];
     double C = 0.0;
-#pragma unroll 1
-    for (int dy = -V; dy <= V; ++dy)
-#pragma unroll 1
+#pragma unroll
+    for (int r = 0; r < SIDE; ++r) {
+        const int dy = r - V;
+#pragma unroll
         for (int dx = -V; dx <= V; ++dx) {
             const int t = gc + dy * s.Wp + dx;
-            if (dx * dx + dy * dy <= vr * vr && (s.cell[t] & CELL_TYPE_MASK) != CELL_WALL &&
-                (s.occ[t] < 0 || t == gc))
-                C = C + exp(ks * (Sc - s.S[t]));
+            if (reach_het<V>(s, gc, t, dx, dy, vr)) C = C + exp(ks * (Sc - s.S[t]));
         }
+        rowC[r] = C;
+    }
     const double tau = (double)u32 * C;
-    double C2 = 0.0;
+    int row = SIDE - 1;
+    double Cprev = SIDE > 1 ? rowC[SIDE - 2] : 0.0;
+    bool found = false;
+#pragma unroll
+    for (int r = 0; r < SIDE; ++r) {
+        const bool hit = !found && tau < rowC[r];
+        row = hit ? r : row;
+        Cprev = hit ? (r > 0 ? rowC[r - 1] : 0.0) : Cprev;
+        found = found || hit;
+    }
+    const int dy = row - V;
+    double C2 = Cprev;
 #pragma unroll 1
-    for (int dy = -V; dy <= V; ++dy)
-#pragma unroll 1
-        for (int dx = -V; dx <= V; ++dx) {
-            const int t = gc + dy * s.Wp + dx;
-            if (dx * dx + dy * dy <= vr * vr && (s.cell[t] & CELL_TYPE_MASK) != CELL_WALL &&
-                (s.occ[t] < 0 || t == gc)) {
-                C2 = C2 + exp(ks * (Sc - s.S[t]));
-                if (tau < C2) return t;
-            }
+    for (int dx = -V; dx <= V; ++dx) {
+        const int t = gc + dy * s.Wp + dx;
+        if (reach_het<V>(s, gc, t, dx, dy, vr)) {
+            C2 = C2 + exp(ks * (Sc - s.S[t]));
+            if (tau < C2) return t;
         }
+    }
     return gc;   // not reached: the own cell has weight 1 and tau < W
 }
 
