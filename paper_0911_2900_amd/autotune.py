@@ -75,8 +75,18 @@ def _key(v: int, cells: int, density: float) -> dict:
             "density": round(float(density), 3)}
 
 
-def choose_tile(v: int, width: int, height: int, n_agents: int, batched: bool = False):
-    """Tuned tile for a scenario (nearest table entry), or None without a table."""
+# Scenarios with a speed per agent run the FP64 kernel (one wavefront per
+# draw): 16 x 8 tiles measured fastest for it on the 40,000-agent room with
+# speeds 1..5 (30 us per launch; 8 x 8: 37, 32 x 8: 33, 64 x 8: 39, 32 x 32: 58).
+HET_TILE = (16, 8)
+
+
+def choose_tile(v: int, width: int, height: int, n_agents: int, batched: bool = False,
+                het: bool = False):
+    """Tuned tile for a scenario (nearest table entry), or None without a table;
+    het: the scenario has a speed per agent."""
+    if het:
+        return HET_TILE
     if not os.path.exists(TABLE):
         return None
     with open(TABLE) as f:

@@ -3,76 +3,93 @@
 // Sec. 3 of the paper expects richer situations than one speed for everybody
 // to cost more planning work.  Here agent i reaches only the cells of its own
 // disc dx^2 + dy^2 <= v_i^2 (v_i <= the scenario's v_max, which sets the
-// staged window).  Every draw is made in FP64, one lane per agent, in the
-// paper's order: weights exp(k_S (S(c) - S(t))) over the window in raster
-// order (zero outside the reach set), the sequential sum W, tau = u W with
-// the agent's Philox u, and the first cell whose prefix exceeds tau.  The
-// tile's agents are listed by the same staging as the uniform kernels.
+// staged window).  Every draw is made in FP64, one wavefront per agent, and
+// chooses what the paper's order gives: weights exp(k_S (S(c) - S(t))) over
+// the window in raster order (zero outside the reach set), the sequential sum
+// W, tau = u W with the agent's Philox u, and the first cell whose prefix
+// exceeds tau.  The tile's agents are listed by the same staging as the
+// uniform kernels.
 #include <hip/hip_ext.h>
 
 #include "plan_tile.h"
 
 namespace fk {
 
-// Agent at padded cell gc with reach vr: the chosen padded cell.  The first
-// pass sums the weights sequentially in raster order and keeps the prefix at
-// the end of every window row; the second starts from the prefix before the
-// first row whose end exceeds tau and sums that row again, cell by cell.  Its
-// prefixes are the very values of the full sequential sum, so the choice is
-// the same, at one row of exps instead of the whole window.
+// The draw of the agent at padded cell gc with reach vr, by a whole
+// wavefront: lane j takes raster slot j of the (2V+1)^2 window (and slot
+// j + 64 when the window has more than 64 slots) and evaluates its weight;
+// an FP64 wavefront scan gives the prefixes.  As in the uniform kernels' FP64
+// path, a scanned prefix of at most 128 non-negative terms lies within
+// 1.5e-14 W of the sequential one, so when no prefix is within s.near64 W
+// (1e-12 W) of tau every comparison tau < C_j, and with it the choice, is the
+// sequential sum's; otherwise the prefix is rebuilt strictly sequentially,
+// slot by slot (slots outside the reach set add exactly nothing).  Every lane
+// returns the chosen padded cell.
 template <int V>
-__device__ __forceinline__ bool reach_het(const SlotDev &s, int gc, int t, int dx, int dy, int vr)
+__device__ int draw_het_wave(const SlotDev &s, int gc, float u32, int lane, int vr)
 {
-    return dx * dx + dy * dy <= vr * vr && (s.cell[t] & CELL_TYPE_MASK) != CELL_WALL &&
-           (s.occ[t] < 0 || t == gc);
-}
-
-template <int V>
-__device__ int draw_het(const SlotDev &s, int gc, float u32, int vr)
-{
-    constexpr int SIDE = 2 * V + 1;
+    constexpr int SIDE = 2 * V + 1, NS = SIDE * SIDE, NH = (NS + 63) / 64;
+    const double NEAR = s.near64;
     const double Sc = s.S[gc];
     const double ks = s.k_s;
-    double rowC[SIDE];
-    double C = 0.0;
+    const double u = (double)u32;
+    double w[NH], C[NH];
 #pragma unroll
-    for (int r = 0; r < SIDE; ++r) {
-        const int dy = r - V;
-#pragma unroll
-        for (int dx = -V; dx <= V; ++dx) {
+    for (int h = 0; h < NH; ++h) {
+        const int j = lane + 64 * h;
+        w[h] = 0.0;
+        if (j < NS) {
+            // the three reads of the slot are independent (every slot lies in
+            // the padded grid), so they are issued together
+            const int dy = j / SIDE - V, dx = j % SIDE - V;
             const int t = gc + dy * s.Wp + dx;
-            if (reach_het<V>(s, gc, t, dx, dy, vr)) C = C + exp(ks * (Sc - s.S[t]));
+            const uint8_t ct = s.cell[t];
+            const int o = s.occ[t];
+            const double St = s.S[t];
+            const bool reach = dx * dx + dy * dy <= vr * vr && (ct & CELL_TYPE_MASK) != CELL_WALL &&
+                               (o < 0 || t == gc);
+            if (reach) w[h] = exp(ks * (Sc - St));
         }
-        rowC[r] = C;
     }
-    const double tau = (double)u32 * C;
-    int row = SIDE - 1;
-    double Cprev = SIDE > 1 ? rowC[SIDE - 2] : 0.0;
-    bool found = false;
+    C[0] = wave_scan64(w[0]);
+    if constexpr (NH == 2) C[1] = wave_scan64(w[1]) + lane_value(C[0], 63);
+    const double Wt = lane_value(C[NH - 1], (NS - 1) % 64);
+    const double tp = u * Wt;
+    bool near = false;
 #pragma unroll
-    for (int r = 0; r < SIDE; ++r) {
-        const bool hit = !found && tau < rowC[r];
-        row = hit ? r : row;
-        Cprev = hit ? (r > 0 ? rowC[r - 1] : 0.0) : Cprev;
-        found = found || hit;
-    }
-    const int dy = row - V;
-    double C2 = Cprev;
+    for (int h = 0; h < NH; ++h) near = near || (lane + 64 * h < NS && fabs(tp - C[h]) <= NEAR * Wt);
+    unsigned long long m[NH];
+    if (__ballot(near) == 0) {
+#pragma unroll
+        for (int h = 0; h < NH; ++h) m[h] = __ballot(lane + 64 * h < NS && tp < C[h]);
+    } else {
+        double acc = 0.0, my[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) my[h] = 0.0;
 #pragma unroll 1
-    for (int dx = -V; dx <= V; ++dx) {
-        const int t = gc + dy * s.Wp + dx;
-        if (reach_het<V>(s, gc, t, dx, dy, vr)) {
-            C2 = C2 + exp(ks * (Sc - s.S[t]));
-            if (tau < C2) return t;
+        for (int j = 0; j < NS; ++j) {
+            const double wj = NH == 2 && j >= 64 ? lane_value(w[NH - 1], j - 64) : lane_value(w[0], j & 63);
+            acc = acc + wj;
+            if (j < 64) { if (lane == j) my[0] = acc; }
+            else if (lane == j - 64) my[NH - 1] = acc;
         }
+        const double tau = u * acc;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) m[h] = __ballot(lane + 64 * h < NS && tau < my[h]);
     }
-    return gc;   // not reached: the own cell has weight 1 and tau < W
+    int jw = (NS - 1) / 2;                                    // own cell if unreached
+    if (m[0]) jw = __builtin_ctzll(m[0]);
+    else if (NH == 2 && m[NH - 1]) jw = 64 + __builtin_ctzll(m[NH - 1]);
+    return gc + (jw / SIDE - V) * s.Wp + (jw % SIDE - V);
 }
 
-// Workgroup i plans tile i; vi[id] is agent id's speed (1..v_max).
+// Workgroup i plans tile i with HET_THREADS threads; wavefront q draws the
+// tile's agents q, q + HET_THREADS / 64, ...; vi[id] is agent id's speed.
+constexpr int HET_THREADS = 1024;
+
 template <int V, int TX>
-__global__ __launch_bounds__(PLAN_THREADS) void plan_kernel_het(const SlotDev s,
-                                                                const uint8_t *__restrict__ vi)
+__global__ __launch_bounds__(HET_THREADS) void plan_kernel_het(const SlotDev s,
+                                                               const uint8_t *__restrict__ vi)
 {
     __shared__ PlanShared<false> sh;
     using T = TileGeom<V, TX>;
@@ -88,18 +105,18 @@ __global__ __launch_bounds__(PLAN_THREADS) void plan_kernel_het(const SlotDev s,
     stage_commit<V, TX, false>(s, tg, sh, r);                 // lists the tile's agents
     MoveRec *seg = s.seg + (long)tile * (TX * s.ty);
     const int na = sh.n_agents;
-    for (int base = 0; base < na; base += (int)blockDim.x) {
-        const int k = base + (int)threadIdx.x;
-        if (k < na) {
-            const int id = (int)(sh.a_pk[k] >> 12);
-            const int l = (int)(sh.a_pk[k] & 0xFFFu);
-            const int ly = l / P;
-            const int cx = tg.gx0 + (l - ly * P), cy = tg.gy0 + ly;
-            const int gc = cy * s.Wp + cx;
-            const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, s.scn, s.seed_lo,
-                                               s.seed_hi);
-            const float u = (float)(x0 >> 8) * 0x1p-24f;
-            const int t = draw_het<V>(s, gc, u, (int)vi[id]);
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const int nw = (int)(blockDim.x >> 6);
+    for (int k = wave; k < na; k += nw) {
+        const int id = (int)(sh.a_pk[k] >> 12);
+        const int l = (int)(sh.a_pk[k] & 0xFFFu);
+        const int ly = l / P;
+        const int cx = tg.gx0 + (l - ly * P), cy = tg.gy0 + ly;
+        const int gc = cy * s.Wp + cx;
+        const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, s.scn, s.seed_lo, s.seed_hi);
+        const float u = (float)(x0 >> 8) * 0x1p-24f;
+        const int t = draw_het_wave<V>(s, gc, u, lane, (int)vi[id]);
+        if (lane == 0) {
             const int d = t - gc;                               // |dx|, |dy| <= V < Wp / 2
             const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
             gstore_rec(seg + k, (uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy));
@@ -115,7 +132,7 @@ template <int V>
 hipError_t launch_het_v(const SlotDev &s, const uint8_t *vi, dim3 grid, hipStream_t stream,
                         hipEvent_t start, hipEvent_t stop)
 {
-    const dim3 block(PLAN_THREADS);
+    const dim3 block(HET_THREADS);
     switch (s.tx) {
         case 8: hipExtLaunchKernelGGL((plan_kernel_het<V, 8>), grid, block, 0, stream, start, stop, 0, s, vi); break;
         case 16: hipExtLaunchKernelGGL((plan_kernel_het<V, 16>), grid, block, 0, stream, start, stop, 0, s, vi); break;

@@ -250,7 +250,8 @@ class Context:
             from . import autotune
             ct = np.asarray(cell_type)
             n = len(agent_xy) if agent_xy is not None else int(n_agents)
-            tile = autotune.choose_tile(int(v), int(ct.shape[1]), int(ct.shape[0]), n, batched)
+            tile = autotune.choose_tile(int(v), int(ct.shape[1]), int(ct.shape[0]), n, batched,
+                                        het=agent_v is not None)
         d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_xy, tile, agent_v)
         h = ctypes.c_int32(-1)
         _check(lib().fast_init_scenario(self.ctx, ctypes.byref(d), ctypes.byref(h)))

@@ -587,7 +587,7 @@ def _het_pair(ctx, s, vi, tile=None):
     return sim, h
 
 
-@pytest.mark.parametrize("v,tile", [(5, None), (3, (16, 16)), (4, (32, 8))])
+@pytest.mark.parametrize("v,tile", [(5, (16, 8)), (3, (16, 16)), (4, (32, 8))])
 def test_per_agent_speeds_match_oracle(ctx, v, tile):
     """A room of 20,000 agents with speeds drawn from 1..v: every plan and
     every position equal the oracle's, step by step."""
@@ -634,3 +634,15 @@ def test_per_agent_speeds_refused_where_unsupported(ctx):
         with pytest.raises(fast.FastError):
             ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=None,
                               agent_v=bad)
+
+
+def test_per_agent_speeds_sequential_rebuild(ctx, monkeypatch):
+    """FAST_FP64_SEQUENTIAL=1 sends every per-agent-speed draw through the
+    strictly sequential prefix rebuild; plans and positions stay the
+    oracle's."""
+    monkeypatch.setenv("FAST_FP64_SEQUENTIAL", "1")
+    s = sc.room(n_agents=8000, v=5, size=200)
+    vi = np.random.default_rng(17).integers(1, 6, size=s.n_agents)
+    sim, h = _het_pair(ctx, s, vi, (32, 8))
+    step_both(ctx, sim, h, 6, check_every=1, where="sequential rebuild")
+    ctx.destroy(h)
