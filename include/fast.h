@@ -103,9 +103,10 @@ typedef struct {
     const uint8_t *agent_v;      /* host, n_agents speeds in 1..v_max (agent i reaches
                                     dx^2 + dy^2 <= agent_v[i]^2), or NULL: all v_max.
                                     Such a scenario plans every draw in FP64 (a
-                                    slower path) and is stepped alone: batched calls
-                                    (fast_run, fast_*_batch), serving and
-                                    fast_debug_plan refuse it with FAST_E_INVALID   */
+                                    slower path); in a batch it gets a planning
+                                    launch of its own beside the shared one.
+                                    Serving and fast_debug_plan refuse it with
+                                    FAST_E_INVALID                                   */
 } fast_scenario_desc;
 
 /* Counters of one scenario. */

@@ -82,6 +82,7 @@ struct Batch {
     int v = 0, tx = 0;           // v_max and tile width shared by all members, else 0
     fk::RegionDev *rjobs = nullptr;  // device: region-count jobs of the members that have them
     int n_rjobs = 0, max_regions = 0;
+    std::vector<int32_t> het;        // members with per-agent speeds: a planning launch each
     void *block = nullptr;
     size_t bytes = 0;
     std::vector<int32_t> members;
@@ -540,10 +541,6 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
 {
     auto it = c->batches.find(hs);
     if (it != c->batches.end()) { *out = &it->second; return FAST_OK; }
-    for (int32_t h : hs)
-        if (c->slots[h].vi)
-            return fail(FAST_E_INVALID, "scenario %d has per-agent speeds: step it alone "
-                        "(fast_plan_step, fast_move_step)", h);
     for (int32_t h : hs)                              // items carry a 20-bit tile index
         if (c->slots[h].n_items > (1 << 20))
             return fail(FAST_E_INVALID, "scenario %d has %d tiles; batched launches take at most 2^20 "
@@ -554,9 +551,12 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return c->slots[a].n_agents > c->slots[b].n_agents;
     });
+    // members with per-agent speeds are planned by launches of their own
     std::vector<uint32_t> items;
+    std::vector<int32_t> het;
     for (int32_t h : order) {
         const Slot &s = c->slots[h];
+        if (s.vi) { het.push_back(h); continue; }
         for (int i = 0; i < s.n_items; ++i) items.push_back(((uint32_t)h << 20) | (uint32_t)i);
     }
     const std::vector<int> G = batch_groups(c, order);
@@ -566,10 +566,14 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
             mitems.push_back(motion_item(order[i], g, G[i], order.size() == 1));
     Batch b;
     b.members = hs;
-    b.v = c->slots[order[0]].dev.v;
-    b.tx = c->slots[order[0]].dev.tx;
-    for (int32_t h : order)
-        if (c->slots[h].dev.v != b.v || c->slots[h].dev.tx != b.tx) b.v = b.tx = 0;
+    b.het = het;
+    bool first = true;
+    for (int32_t h : order) {
+        const Slot &s = c->slots[h];
+        if (s.vi) continue;
+        if (first) { b.v = s.dev.v; b.tx = s.dev.tx; first = false; }
+        else if (s.dev.v != b.v || s.dev.tx != b.tx) b.v = b.tx = 0;
+    }
     std::vector<fk::RegionDev> rj;
     for (int32_t h : order)
         if (c->slots[h].n_regions) {
@@ -604,6 +608,17 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     return FAST_OK;
 }
 
+// The planning launches of a batch's members with per-agent speeds.
+hipError_t launch_het_members(fast_ctx *c, const Batch *b)
+{
+    for (int32_t h : b->het) {
+        const Slot &s = c->slots[h];
+        const hipError_t e = fk_launch_plan_het(&s.dev, s.vi, s.n_items, c->stream, nullptr, nullptr);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // One time step of a batch captured as a HIP graph: one planning launch over
 // every tile of every member, one motion launch over their workgroup groups.
 fast_status batch_graph(fast_ctx *c, Batch *b)
@@ -611,6 +626,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b)
     if (b->exec) return FAST_OK;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
+    if (e1 == hipSuccess) e1 = launch_het_members(c, b);
     hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
     if (e2 == hipSuccess) e2 = fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
@@ -651,6 +667,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     if (st) return st;
     for (int k = 0; k < steps; ++k) {
         HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr));
+        HIP_TRY(launch_het_members(c, b));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
         HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream));
     }
@@ -1056,8 +1073,9 @@ fast_status fast_plan_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     st = get_batch(c, v, &b);
     if (st) return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    next_timing_pair(c, &e0, &e1);
+    if (b->n_items > 0) next_timing_pair(c, &e0, &e1);   // times the shared planning launch
     HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, e0, e1));
+    HIP_TRY(launch_het_members(c, b));
     for (int32_t h : v) c->slots[h].planned = true;
     return FAST_OK;
 }

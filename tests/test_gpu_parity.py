@@ -621,14 +621,37 @@ def test_speeds_all_v_max_match_the_uniform_kernels(ctx):
     ctx.destroy(hh)
 
 
+def test_per_agent_speeds_in_a_batch(ctx):
+    """A graph-replayed batch of two scenarios with per-agent speeds and two
+    without (their own planning launches beside the shared one), then plain
+    batched steps: every member ends where the oracle does."""
+    members = [sc.ensemble_member(k) for k in (5, 6, 9, 10)]
+    speeds = [np.random.default_rng(40 + i).integers(1, m.v + 1, size=m.n_agents) if i % 2 == 0
+              else None for i, m in enumerate(members)]
+    pairs = []
+    for m, vi in zip(members, speeds):
+        if vi is None:
+            pairs.append(make_pair(ctx, m))
+        else:
+            pairs.append(_het_pair(ctx, m, vi))
+    hs = [h for _, h in pairs]
+    ctx.run(hs, 15)
+    for _ in range(3):
+        ctx.plan_batch(hs)
+        ctx.move_batch(hs)
+    for m, (sim, h) in zip(members, pairs):
+        sim.run(18)
+        compare_state(ctx, sim, h, where=f"{m.name} in a mixed batch")
+        ctx.destroy(h)
+
+
 def test_per_agent_speeds_refused_where_unsupported(ctx):
     from paper_0911_2900_amd import fast
     s = sc.corridor()
     vi = np.random.default_rng(0).integers(1, 5, size=s.n_agents)
     h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=None, agent_v=vi)
-    for call in (lambda: ctx.run([h], 1), lambda: ctx.plan_batch([h]), lambda: ctx.debug_plan(h)):
-        with pytest.raises(fast.FastError):
-            call()
+    with pytest.raises(fast.FastError):
+        ctx.debug_plan(h)
     ctx.destroy(h)
     for bad in (np.zeros(s.n_agents), np.full(s.n_agents, 5)):
         with pytest.raises(fast.FastError):
