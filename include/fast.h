@@ -103,9 +103,9 @@ typedef struct {
     const uint8_t *agent_v;      /* host, n_agents speeds in 1..v_max (agent i reaches
                                     dx^2 + dy^2 <= agent_v[i]^2), or NULL: all v_max.
                                     Such a scenario plans every draw in FP64 (a
-                                    slower path); in a batch it gets a planning
-                                    launch of its own beside the shared one.
-                                    Serving and fast_debug_plan refuse it with
+                                    slower path); in a batch (and when served) it
+                                    gets a planning launch of its own beside the
+                                    shared one.  fast_debug_plan refuses it with
                                     FAST_E_INVALID                                   */
 } fast_scenario_desc;
 

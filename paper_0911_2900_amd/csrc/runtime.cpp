@@ -93,6 +93,7 @@ struct Request {
     fast_scenario_desc desc{};
     std::vector<uint8_t> cells;
     std::vector<int32_t> xy;
+    std::vector<uint8_t> vi;         // per-agent speeds (desc.agent_v points here)
     int steps = 0;
     double t_submit = 0, t_done = 0;
     int state = 0;               // 0 queued, 1 running, 2 done, -1 rejected
@@ -1349,7 +1350,6 @@ fast_status fast_serve_submit(fast_ctx *c, const fast_scenario_desc *d, int32_t 
     if (!c || !ticket || steps < 0) return fail(FAST_E_INVALID, "bad arguments to fast_serve_submit");
     fast_status st = check_desc(d);
     if (st) return st;
-    if (d->agent_v) return fail(FAST_E_INVALID, "per-agent speeds are not served (step such a scenario alone)");
     std::unique_ptr<Request> r(new Request());
     r->desc = *d;
     r->cells.assign(d->cell_type, d->cell_type + (size_t)d->width * d->height);
@@ -1357,6 +1357,10 @@ fast_status fast_serve_submit(fast_ctx *c, const fast_scenario_desc *d, int32_t 
     if (d->agent_xy) {
         r->xy.assign(d->agent_xy, d->agent_xy + (size_t)2 * d->n_agents);
         r->desc.agent_xy = r->xy.data();
+    }
+    if (d->agent_v) {
+        r->vi.assign(d->agent_v, d->agent_v + d->n_agents);
+        r->desc.agent_v = r->vi.data();
     }
     r->steps = steps;
     r->t_submit = now_s();

@@ -358,8 +358,9 @@ class Context:
     def serve_start(self, budget: int = 0, max_active: int = 0):
         _check(lib().fast_serve_start(self.ctx, int(budget), int(max_active)))
 
-    def serve_submit(self, cell_type, n_agents, v, k_s=1.2, seed=1, scn=0, steps=396) -> int:
-        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn)
+    def serve_submit(self, cell_type, n_agents, v, k_s=1.2, seed=1, scn=0, steps=396,
+                     agent_v=None) -> int:
+        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_v=agent_v)
         t = ctypes.c_uint64(0)
         _check(lib().fast_serve_submit(self.ctx, ctypes.byref(d), int(steps), ctypes.byref(t)))
         self.n_agents[("ticket", t.value)] = d.n_agents

@@ -41,14 +41,15 @@ def _oracle_final(m, steps):
     return sim.positions(), sim.alive[: sim.n].astype(bool)
 
 
-def _serve(fast, reqs, budget, max_active, gap_s):
+def _serve(fast, reqs, budget, max_active, gap_s, speeds=None):
     ctx = fast.Context(device=0, torch_alloc=False)
     try:
         ctx.serve_start(budget=budget, max_active=max_active)
         tickets = []
-        for m, steps in reqs:
+        for i, (m, steps) in enumerate(reqs):
             tickets.append(ctx.serve_submit(m.cell_type, m.n_agents, m.v, m.k_s, m.seed, m.scn,
-                                            steps=steps))
+                                            steps=steps,
+                                            agent_v=None if speeds is None else speeds[i]))
             time.sleep(gap_s)                      # later requests arrive while others run
         deadline = time.time() + 120
         lat = {}
@@ -76,6 +77,20 @@ def test_served_results_equal_oracle_alone(fast_mod):
         assert r["step"] == steps
         assert np.array_equal(r["alive"].astype(bool), alive), m.name
         assert np.array_equal(r["xy"], xy), m.name
+
+
+def test_served_per_agent_speeds_equal_oracle(fast_mod):
+    """Requests with a speed per agent, served beside requests without: every
+    final state equals the oracle's run alone."""
+    reqs = _requests(40, 6, 25)
+    speeds = [np.random.default_rng(70 + i).integers(1, m.v + 1, size=m.n_agents) if i % 2 == 0
+              else None for i, (m, _) in enumerate(reqs)]
+    results, lat = _serve(fast_mod, reqs, budget=0, max_active=3, gap_s=0.002, speeds=speeds)
+    for (m, steps), vi, r in zip(reqs, speeds, results):
+        sim = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents, agent_v=vi)
+        sim.run(steps)
+        assert r["step"] == steps
+        assert np.array_equal(r["xy"], sim.positions()), m.name
 
 
 def test_small_budget_forces_queueing_and_stays_exact(fast_mod):
