@@ -47,6 +47,7 @@ class _State(ctypes.Structure):
         ("alive", ctypes.c_void_p), ("desired", ctypes.c_void_p),
         ("occ", ctypes.c_void_p), ("exited", ctypes.c_int64),
         ("vi", ctypes.c_void_p),
+        ("Sf", ctypes.c_void_p), ("fi", ctypes.c_void_p),
     ]
 
 
@@ -60,6 +61,7 @@ def lib():
         P = ctypes.c_void_p
         _lib.oracle_philox4x32_10.argtypes = [P, P, P]
         _lib.oracle_floor_field.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P]
+        _lib.oracle_floor_field_of.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32, P]
         _lib.oracle_place.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32,
                                       ctypes.c_uint64, ctypes.c_uint32, P, P]
         _lib.oracle_reset_occ.argtypes = [P]
@@ -113,11 +115,27 @@ def place(cell_type_after: np.ndarray, S: np.ndarray, n: int, seed: int, scn: in
     return x[:n].copy(), y[:n].copy()
 
 
+def floor_field_of(cell_type_after: np.ndarray, exit_field: np.ndarray, g: int) -> np.ndarray:
+    """Floor field g of a scenario with several fields (reading R9): the exact
+    field from the exit cells whose exit_field value is g, +inf where they do
+    not reach."""
+    t = np.ascontiguousarray(cell_type_after, dtype=np.uint8)
+    ef = np.ascontiguousarray(exit_field, dtype=np.uint8)
+    H, W = t.shape
+    if ef.shape != t.shape:
+        raise ValueError("exit_field must have the grid's shape")
+    S = np.zeros((H, W), dtype=np.float64)
+    if lib().oracle_floor_field_of(W, H, _ptr(t), _ptr(ef), int(g), _ptr(S)) != 0:
+        raise ValueError("floor field failed")
+    return S
+
+
 class Sim:
     """Oracle model state: one scenario, stepped on the CPU."""
 
     def __init__(self, cell_type: np.ndarray, v: int, k_s: float, seed: int, scn: int,
-                 n_agents: int | None = None, agent_xy=None, agent_v=None):
+                 n_agents: int | None = None, agent_xy=None, agent_v=None,
+                 exit_field=None, agent_field=None):
         self.type, self.S, self.a, self.b = floor_field(cell_type)
         self.H, self.W = self.type.shape
         if agent_xy is None:
@@ -153,6 +171,21 @@ class Sim:
                                                            or self.agent_v.max() > v)):
                 raise ValueError("agent_v: one speed in 1..v per agent")
             self._st.vi = _ptr(self.agent_v) if self.n else None
+        # several floor fields (reading R9): agent i follows field agent_field[i]
+        self.Sf = self.agent_field = None
+        if (exit_field is None) != (agent_field is None):
+            raise ValueError("exit_field and agent_field go together")
+        if agent_field is not None:
+            self.agent_field = np.ascontiguousarray(np.asarray(agent_field, dtype=np.uint8)).copy()
+            if len(self.agent_field) != self.n:
+                raise ValueError("agent_field needs one field per agent")
+            G = int(self.agent_field.max()) + 1 if self.n else 1
+            ef = np.asarray(exit_field, dtype=np.uint8)
+            G = max(G, int(ef[self.type == 2].max()) + 1)
+            self.Sf = np.ascontiguousarray(
+                np.stack([floor_field_of(self.type, ef, g) for g in range(G)]))
+            self._st.Sf = _ptr(self.Sf)
+            self._st.fi = _ptr(self.agent_field) if self.n else None
         if lib().oracle_reset_occ(ctypes.byref(self._st)) != 0:
             raise ValueError("invalid agent positions")
 

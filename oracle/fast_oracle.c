@@ -45,6 +45,11 @@
  *  R8  seeded placement: partial Fisher-Yates over the eligible cells (free,
  *      reachable) in raster order with j = k + ((x0 * (M - k)) >> 32), x0 from
  *      Philox at counter (k, 0, scenario, 2).
+ *  R9  several floor fields (route choice, counterflow; Sec. 3 names richer
+ *      situations as the next cost driver): field g is R7's exact field from
+ *      the exit cells tagged g alone, +inf where those exits do not reach;
+ *      agent i weighs its window with its own field in R2; walls stay those
+ *      of R7 (all exits), and R6 removes an agent at any exit cell.
  *
  * Philox4x32-10 follows its published definition: J. K. Salmon, M. A. Moraes,
  * R. O. Dror, D. E. Shaw, "Parallel random numbers: as easy as 1, 2, 3",
@@ -159,20 +164,21 @@ static heap_item heap_pop(heap_item *h, int64_t *n)
  * a_out, b_out : out (may be NULL), exact length a + b*sqrt2; -1 on walls.
  * Returns 0, or -1 on bad input / allocation failure.
  */
-int oracle_floor_field(int32_t W, int32_t H, uint8_t *type, double *S,
-                       int64_t *a_out, int64_t *b_out)
+/* Shortest exact lengths A + B*sqrt2 from the source exits (all exit cells
+ * when ef is NULL, else those with ef[cell] == g) to every cell; -1 where no
+ * source reaches. */
+static int exit_lengths(int32_t W, int32_t H, const uint8_t *type, const uint8_t *ef,
+                        int32_t g, int64_t *A, int64_t *B)
 {
-    if (W <= 0 || H <= 0) return -1;
     int64_t n = (int64_t)W * H;
-    int64_t *A = malloc(sizeof(int64_t) * n), *B = malloc(sizeof(int64_t) * n);
     uint8_t *done = calloc((size_t)n, 1);
     /* each cell is pushed at most once per improvement; 8 improvements bound it */
     heap_item *heap = malloc(sizeof(heap_item) * (size_t)(9 * n + 1));
-    if (!A || !B || !done || !heap) { free(A); free(B); free(done); free(heap); return -1; }
+    if (!done || !heap) { free(done); free(heap); return -1; }
     int64_t hn = 0;
     for (int64_t i = 0; i < n; ++i) {
         A[i] = -1; B[i] = -1;
-        if (type[i] == CELL_EXIT) {
+        if (type[i] == CELL_EXIT && (!ef || ef[i] == g)) {
             A[i] = 0; B[i] = 0;
             heap_item it = { 0, 0, (int32_t)i };
             heap_push(heap, &hn, it);
@@ -210,6 +216,17 @@ int oracle_floor_field(int32_t W, int32_t H, uint8_t *type, double *S,
             }
         }
     }
+    free(done); free(heap);
+    return 0;
+}
+
+int oracle_floor_field(int32_t W, int32_t H, uint8_t *type, double *S,
+                       int64_t *a_out, int64_t *b_out)
+{
+    if (W <= 0 || H <= 0) return -1;
+    int64_t n = (int64_t)W * H;
+    int64_t *A = malloc(sizeof(int64_t) * n), *B = malloc(sizeof(int64_t) * n);
+    if (!A || !B || exit_lengths(W, H, type, NULL, 0, A, B) != 0) { free(A); free(B); return -1; }
     const double sqrt2 = sqrt(2.0);   /* correctly rounded: nearest double to sqrt 2 */
     for (int64_t i = 0; i < n; ++i) {
         if (type[i] == CELL_FREE && A[i] < 0) type[i] = CELL_WALL;   /* unreachable */
@@ -224,7 +241,30 @@ int oracle_floor_field(int32_t W, int32_t H, uint8_t *type, double *S,
             if (b_out) b_out[i] = B[i];
         }
     }
-    free(A); free(B); free(done); free(heap);
+    free(A); free(B);
+    return 0;
+}
+
+/*
+ * Floor field g of a scenario with several fields (route choice, counterflow:
+ * each group of agents heads for its own exits).  The same exact Dijkstra
+ * lengths as R7, from the exit cells with exit_field[cell] == g only; type is
+ * the grid after oracle_floor_field (read, not changed).  Cells that field g
+ * does not reach get +inf, like walls.  Returns 0, or -1 on bad input.
+ */
+int oracle_floor_field_of(int32_t W, int32_t H, const uint8_t *type, const uint8_t *exit_field,
+                          int32_t g, double *S)
+{
+    if (W <= 0 || H <= 0 || !exit_field) return -1;
+    int64_t n = (int64_t)W * H;
+    int64_t *A = malloc(sizeof(int64_t) * n), *B = malloc(sizeof(int64_t) * n);
+    if (!A || !B || exit_lengths(W, H, type, exit_field, g, A, B) != 0) { free(A); free(B); return -1; }
+    const double sqrt2 = sqrt(2.0);
+    for (int64_t i = 0; i < n; ++i) {
+        if (type[i] == CELL_WALL || A[i] < 0) S[i] = INFINITY;
+        else S[i] = (double)B[i] * sqrt2 + (double)A[i];
+    }
+    free(A); free(B);
     return 0;
 }
 
@@ -276,6 +316,10 @@ typedef struct {
     const uint8_t *vi;      /* optional, n: agent i's own maximum speed (1..v); NULL:
                                every agent has v.  The window stays (2v+1)^2; agent i
                                reaches the cells of its own disc dx^2 + dy^2 <= vi^2 */
+    const double *Sf;       /* optional: several floor fields, W*H each, one after
+                               another (oracle_floor_field_of)                      */
+    const uint8_t *fi;      /* optional, n: the field agent i follows; NULL: every
+                               agent follows S                                      */
 } oracle_state;
 
 /* Rebuilds occupancy from positions; returns -1 if an agent is off-grid, on
@@ -316,6 +360,8 @@ int32_t oracle_plan_agent(const oracle_state *st, int32_t i, double *w_out,
     const int32_t vr = st->vi ? st->vi[i] : v;    /* the agent's own reach */
     const int32_t cx = st->x[i], cy = st->y[i];
     const int64_t c = (int64_t)cy * W + cx;
+    /* the floor field agent i follows */
+    const double *S = st->fi ? st->Sf + (int64_t)st->fi[i] * W * H : st->S;
     double *w = malloc(sizeof(double) * (size_t)(side * side));
     if (!w) return -2;
 
@@ -331,7 +377,7 @@ int32_t oracle_plan_agent(const oracle_state *st, int32_t i, double *w_out,
                 int64_t t = (int64_t)ty * W + tx;
                 int free_or_own = st->occ[t] == -1 || t == c;
                 if (st->type[t] != CELL_WALL && free_or_own)
-                    wt = exp(st->k_s * (st->S[c] - st->S[t]));
+                    wt = exp(st->k_s * (S[c] - S[t]));
             }
             w[slot] = wt;
         }

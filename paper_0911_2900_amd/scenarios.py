@@ -183,6 +183,24 @@ def random_small(rng: np.random.Generator, W: int, H: int, pillar_frac: float,
     return Scenario(f"small_{W}x{H}", t, min(n_agents, max(0, n_free // 2)), v, k_s, seed, scn)
 
 
+def counterflow(n_agents: int = 300, v: int = 4, seed: int = 4, scn: int = 0, W: int = 60,
+                H: int = 20) -> Scenario:
+    """Two groups crossing a walled hall: exits in the middle of the left and
+    the right wall; field 0 leads to the right exits, field 1 to the left
+    ones.  meta: exit_field (H, W) uint8 (the field of each exit cell) and
+    agent_field (n,) uint8, an even seeded mix of the two groups."""
+    t = walled_box(W, H)
+    c = H // 2
+    t[c - 2:c + 2, W - 1] = EXIT
+    t[c - 2:c + 2, 0] = EXIT
+    ef = np.zeros((H, W), dtype=np.uint8)
+    ef[c - 2:c + 2, 0] = 1
+    rng = np.random.default_rng([seed, scn, 17])
+    af = rng.permutation(np.arange(n_agents) % 2).astype(np.uint8)
+    return Scenario(f"counterflow_{W}x{H}", t, n_agents, v, 1.2, seed, scn,
+                    meta={"exit_field": ef, "agent_field": af})
+
+
 CELL_M2 = 0.16                     # one 0.4 m x 0.4 m cell
 
 
