@@ -107,6 +107,21 @@ typedef struct {
                                     gets a planning launch of its own beside the
                                     shared one.  fast_debug_plan refuses it with
                                     FAST_E_INVALID                                   */
+    int32_t n_fields;            /* floor fields: 0 or 1 = one field from every exit;
+                                    2..8 = route choice / counterflow (Sec. 3's richer
+                                    situations): field g is the exact floor field
+                                    from the exit cells tagged g alone, and agent i
+                                    weighs its window with field agent_field[i].
+                                    Walls stay those of the all-exit field and an
+                                    agent leaves at any exit cell.  Planned in FP64
+                                    like per-agent speeds (a launch of its own in a
+                                    batch); fast_debug_plan refuses it              */
+    const uint8_t *exit_field;   /* host, width*height, read at exit cells: the field
+                                    (0..n_fields-1) the exit belongs to; every field
+                                    needs an exit.  NULL when n_fields <= 1          */
+    const uint8_t *agent_field;  /* host, n_agents fields in 0..n_fields-1; an agent
+                                    must stand where its field is finite.  NULL when
+                                    n_fields <= 1                                    */
 } fast_scenario_desc;
 
 /* Counters of one scenario. */

@@ -63,14 +63,18 @@ struct QAfter {
 }  // namespace
 
 // Exact floor field on the unpadded grid; unreachable free cells become walls.
-void floor_field(int W, int H, std::vector<uint8_t> &type, std::vector<double> &S)
+// With exit_field given, the field of exit group g alone: only the exits
+// tagged g are sources, type is left as it is, and cells those exits do not
+// reach get +inf.
+void floor_field(int W, int H, std::vector<uint8_t> &type, std::vector<double> &S,
+                 const uint8_t *exit_field, int g)
 {
     const int64_t n = (int64_t)W * H;
     std::vector<Len> L((size_t)n);
     std::vector<char> settled((size_t)n, 0);
     std::priority_queue<QItem, std::vector<QItem>, QAfter> q;
     for (int64_t i = 0; i < n; ++i)
-        if (type[i] == fk::CELL_EXIT) {
+        if (type[i] == fk::CELL_EXIT && (!exit_field || exit_field[i] == g)) {
             L[i].a = 0;
             L[i].b = 0;
             q.push({L[i], (int32_t)i});
@@ -106,8 +110,8 @@ void floor_field(int W, int H, std::vector<uint8_t> &type, std::vector<double> &
     }
     S.assign((size_t)n, INFINITY);
     for (int64_t i = 0; i < n; ++i) {
-        if (type[i] == fk::CELL_FREE && !L[i].reached()) type[i] = fk::CELL_WALL;
-        if (type[i] != fk::CELL_WALL) {
+        if (!exit_field && type[i] == fk::CELL_FREE && !L[i].reached()) type[i] = fk::CELL_WALL;
+        if (type[i] != fk::CELL_WALL && L[i].reached()) {
             const double bs = (double)L[i].b * kSqrt2;
             S[i] = bs + (double)L[i].a;
         }
@@ -211,6 +215,29 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
         for (uint8_t s : b.vi)
             if (s < 1 || s > v) { err = "agent_v values must lie in 1..v_max"; return FAST_E_INVALID; }
     }
+    // several floor fields: one per exit group, agent i follows agent_field[i]
+    const int nf = d.n_fields;
+    std::vector<std::vector<double>> fields;
+    if (nf < 0 || nf > 8) { err = "n_fields must lie in 0..8"; return FAST_E_INVALID; }
+    if (nf >= 2) {
+        if (!d.exit_field || !d.agent_field) { err = "n_fields >= 2 needs exit_field and agent_field"; return FAST_E_INVALID; }
+        std::vector<int> exits((size_t)nf, 0);
+        for (int64_t i = 0; i < (int64_t)W * H; ++i)
+            if (type[i] == fk::CELL_EXIT) {
+                if (d.exit_field[i] >= nf) { err = "exit_field values must lie in 0..n_fields-1"; return FAST_E_INVALID; }
+                ++exits[d.exit_field[i]];
+            }
+        for (int g = 0; g < nf; ++g)
+            if (!exits[g]) { err = "every floor field needs an exit cell"; return FAST_E_INVALID; }
+        fields.resize((size_t)nf);
+        for (int g = 0; g < nf; ++g) floor_field(W, H, type, fields[g], d.exit_field, g);
+        b.fi.assign(d.agent_field, d.agent_field + d.n_agents);
+        for (int i = 0; i < d.n_agents; ++i) {
+            if (b.fi[i] >= nf) { err = "agent_field values must lie in 0..n_fields-1"; return FAST_E_INVALID; }
+            const int64_t c = (int64_t)xy[2 * i + 1] * W + xy[2 * i];
+            if (!std::isfinite(fields[b.fi[i]][c])) { err = "an agent stands where its floor field does not reach"; return FAST_E_INVALID; }
+        }
+    }
 
     // padded layout
     b.ntx = (W + tx - 1) / tx;
@@ -232,6 +259,13 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
             b.type[g] = type[(int64_t)y * W + x];
             b.S[g] = S[(int64_t)y * W + x];
         }
+    if (nf >= 2) {
+        b.Sf.assign((size_t)nf * np, INFINITY);
+        for (int g = 0; g < nf; ++g)
+            for (int y = 0; y < H; ++y)
+                for (int x = 0; x < W; ++x)
+                    b.Sf[(size_t)g * np + (size_t)(y + pad) * b.Wp + (x + pad)] = fields[g][(int64_t)y * W + x];
+    }
     b.n = d.n_agents;
     b.pos.resize((size_t)b.n);
     for (int i = 0; i < b.n; ++i) {

@@ -26,12 +26,15 @@ struct Built {
     std::vector<int32_t> occ;      // padded
     std::vector<int32_t> pos;      // padded cell per agent
     std::vector<uint8_t> vi;       // per-agent speeds (empty: every agent has v)
+    std::vector<uint8_t> fi;       // per-agent floor field (empty: one field for all)
+    std::vector<double> Sf;        // padded floor fields of the exit groups, one after another
     int n = 0;
     int n_fb = 0;
     float eps = 0.0f;
 };
 
-void floor_field(int W, int H, std::vector<uint8_t> &type, std::vector<double> &S);
+void floor_field(int W, int H, std::vector<uint8_t> &type, std::vector<double> &S,
+                 const uint8_t *exit_field = nullptr, int g = 0);
 bool place(int W, int H, const std::vector<uint8_t> &type, int n, uint64_t seed, uint32_t scn,
            std::vector<int32_t> &xy);
 float guard_band(int v);
@@ -67,8 +70,10 @@ extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *m
                                      hipStream_t stream);
 extern "C" hipError_t fk_move_per_cu(int *per_cu);
 extern "C" hipError_t fk_cu_probe(hipStream_t stream, int n_wg, uint32_t *ids_host);
-extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const uint8_t *vi, int n_tiles,
-                                         hipStream_t stream, hipEvent_t start, hipEvent_t stop);
+extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const uint8_t *vi,
+                                         const uint8_t *fi, const double *Sf, long field_cells,
+                                         int n_tiles, hipStream_t stream, hipEvent_t start,
+                                         hipEvent_t stop);
 extern "C" hipError_t fk_launch_count(const fk::RegionDev *jobs, int n_jobs, int max_regions,
                                       hipStream_t stream);
 extern "C" hipError_t fk_launch_stream(float4 *base, size_t n4, hipStream_t stream,

@@ -3,7 +3,9 @@
 // Sec. 3 of the paper expects richer situations than one speed for everybody
 // to cost more planning work.  Here agent i reaches only the cells of its own
 // disc dx^2 + dy^2 <= v_i^2 (v_i <= the scenario's v_max, which sets the
-// staged window).  Every draw is made in FP64, one wavefront per agent, and
+// staged window).  The same kernel plans scenarios with several floor fields
+// (one per exit group): agent i then weighs its window with field fi[i].
+// Every draw is made in FP64, one wavefront per agent, and
 // chooses what the paper's order gives: weights exp(k_S (S(c) - S(t))) over
 // the window in raster order (zero outside the reach set), the sequential sum
 // W, tau = u W with the agent's Philox u, and the first cell whose prefix
@@ -26,11 +28,12 @@ namespace fk {
 // slot by slot (slots outside the reach set add exactly nothing).  Every lane
 // returns the chosen padded cell.
 template <int V>
-__device__ int draw_het_wave(const SlotDev &s, int gc, float u32, int lane, int vr)
+__device__ int draw_het_wave(const SlotDev &s, const double *__restrict__ S, int gc, float u32,
+                             int lane, int vr)
 {
     constexpr int SIDE = 2 * V + 1, NS = SIDE * SIDE, NH = (NS + 63) / 64;
     const double NEAR = s.near64;
-    const double Sc = s.S[gc];
+    const double Sc = S[gc];
     const double ks = s.k_s;
     const double u = (double)u32;
     double w[NH], C[NH];
@@ -45,7 +48,7 @@ __device__ int draw_het_wave(const SlotDev &s, int gc, float u32, int lane, int 
             const int t = gc + dy * s.Wp + dx;
             const uint8_t ct = s.cell[t];
             const int o = s.occ[t];
-            const double St = s.S[t];
+            const double St = S[t];
             const bool reach = dx * dx + dy * dy <= vr * vr && (ct & CELL_TYPE_MASK) != CELL_WALL &&
                                (o < 0 || t == gc);
             if (reach) w[h] = exp(ks * (Sc - St));
@@ -84,12 +87,17 @@ __device__ int draw_het_wave(const SlotDev &s, int gc, float u32, int lane, int 
 }
 
 // Workgroup i plans tile i with HET_THREADS threads; wavefront q draws the
-// tile's agents q, q + HET_THREADS / 64, ...; vi[id] is agent id's speed.
+// tile's agents q, q + HET_THREADS / 64, ...; vi[id] is agent id's speed
+// (vi NULL: every agent has V), fi[id] its floor field, which starts at
+// Sf + fi[id] * field_cells (fi NULL: Sf alone).
 constexpr int HET_THREADS = 1024;
 
 template <int V, int TX>
 __global__ __launch_bounds__(HET_THREADS) void plan_kernel_het(const SlotDev s,
-                                                               const uint8_t *__restrict__ vi)
+                                                               const uint8_t *__restrict__ vi,
+                                                               const uint8_t *__restrict__ fi,
+                                                               const double *__restrict__ Sf,
+                                                               long field_cells)
 {
     __shared__ PlanShared<false> sh;
     using T = TileGeom<V, TX>;
@@ -115,7 +123,9 @@ __global__ __launch_bounds__(HET_THREADS) void plan_kernel_het(const SlotDev s,
         const int gc = cy * s.Wp + cx;
         const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, s.scn, s.seed_lo, s.seed_hi);
         const float u = (float)(x0 >> 8) * 0x1p-24f;
-        const int t = draw_het_wave<V>(s, gc, u, lane, (int)vi[id]);
+        const int vr = vi ? (int)vi[id] : V;
+        const double *S = fi ? Sf + (long)fi[id] * field_cells : Sf;
+        const int t = draw_het_wave<V>(s, S, gc, u, lane, vr);
         if (lane == 0) {
             const int d = t - gc;                               // |dx|, |dy| <= V < Wp / 2
             const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
@@ -129,15 +139,15 @@ __global__ __launch_bounds__(HET_THREADS) void plan_kernel_het(const SlotDev s,
 }
 
 template <int V>
-hipError_t launch_het_v(const SlotDev &s, const uint8_t *vi, dim3 grid, hipStream_t stream,
-                        hipEvent_t start, hipEvent_t stop)
+hipError_t launch_het_v(const SlotDev &s, const uint8_t *vi, const uint8_t *fi, const double *Sf,
+                        long fc, dim3 grid, hipStream_t stream, hipEvent_t start, hipEvent_t stop)
 {
     const dim3 block(HET_THREADS);
     switch (s.tx) {
-        case 8: hipExtLaunchKernelGGL((plan_kernel_het<V, 8>), grid, block, 0, stream, start, stop, 0, s, vi); break;
-        case 16: hipExtLaunchKernelGGL((plan_kernel_het<V, 16>), grid, block, 0, stream, start, stop, 0, s, vi); break;
-        case 32: hipExtLaunchKernelGGL((plan_kernel_het<V, 32>), grid, block, 0, stream, start, stop, 0, s, vi); break;
-        case 64: hipExtLaunchKernelGGL((plan_kernel_het<V, 64>), grid, block, 0, stream, start, stop, 0, s, vi); break;
+        case 8: hipExtLaunchKernelGGL((plan_kernel_het<V, 8>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+        case 16: hipExtLaunchKernelGGL((plan_kernel_het<V, 16>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+        case 32: hipExtLaunchKernelGGL((plan_kernel_het<V, 32>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+        case 64: hipExtLaunchKernelGGL((plan_kernel_het<V, 64>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -145,18 +155,23 @@ hipError_t launch_het_v(const SlotDev &s, const uint8_t *vi, dim3 grid, hipStrea
 
 }  // namespace fk
 
-// Planning launch of one scenario with per-agent speeds vi (device, n_agents).
-extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const uint8_t *vi, int n_tiles,
-                                         hipStream_t stream, hipEvent_t start, hipEvent_t stop)
+// Planning launch of one scenario with per-agent speeds vi and per-agent floor
+// fields fi (device, n_agents each, or NULL), the fields at Sf, field_cells
+// padded cells apart (Sf NULL: the scenario's one field).
+extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const uint8_t *vi,
+                                         const uint8_t *fi, const double *Sf, long field_cells,
+                                         int n_tiles, hipStream_t stream, hipEvent_t start,
+                                         hipEvent_t stop)
 {
     if (n_tiles <= 0) return hipSuccess;
     const dim3 grid(n_tiles);
+    if (!Sf) { Sf = slot->S; fi = nullptr; }
     switch (slot->v) {
-        case 1: return fk::launch_het_v<1>(*slot, vi, grid, stream, start, stop);
-        case 2: return fk::launch_het_v<2>(*slot, vi, grid, stream, start, stop);
-        case 3: return fk::launch_het_v<3>(*slot, vi, grid, stream, start, stop);
-        case 4: return fk::launch_het_v<4>(*slot, vi, grid, stream, start, stop);
-        case 5: return fk::launch_het_v<5>(*slot, vi, grid, stream, start, stop);
+        case 1: return fk::launch_het_v<1>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
+        case 2: return fk::launch_het_v<2>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
+        case 3: return fk::launch_het_v<3>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
+        case 4: return fk::launch_het_v<4>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
+        case 5: return fk::launch_het_v<5>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
         default: return hipErrorInvalidValue;
     }
 }

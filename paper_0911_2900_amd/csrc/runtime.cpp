@@ -65,6 +65,10 @@ struct Slot {
     bool planned = false;        // a plan was launched after the last motion phase
     int n_agents = 0;
     uint8_t *vi = nullptr;       // device: per-agent speeds (NULL: every agent has v_max)
+    uint8_t *fi = nullptr;       // device: per-agent floor field (NULL: one field for all)
+    const double *Sf = nullptr;  // device: the exit groups' floor fields, field_cells apart
+    long field_cells = 0;
+    bool het = false;            // planned by the FP64 per-agent kernel (vi or fi set)
     // region counts (fast_set_regions)
     fk::RegionDev rhost{};       // host copy of the job
     fk::RegionDev *rdev = nullptr;  // device: the job, then its series
@@ -94,6 +98,7 @@ struct Request {
     std::vector<uint8_t> cells;
     std::vector<int32_t> xy;
     std::vector<uint8_t> vi;         // per-agent speeds (desc.agent_v points here)
+    std::vector<uint8_t> ef, fi;     // exit groups and per-agent fields (desc points here)
     int steps = 0;
     double t_submit = 0, t_done = 0;
     int state = 0;               // 0 queued, 1 running, 2 done, -1 rejected
@@ -381,7 +386,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
                  o_mitems = take(fk::MOVE_GROUP_MAX * 4),
                  o_hand = take((size_t)fk::MOVE_GROUP_MAX * fk::MOVE_SOLO_MAX * sizeof(fk::Mover)),
-                 o_vi = take(b.vi.size());
+                 o_vi = take(b.vi.size()), o_fi = take(b.fi.size()),
+                 o_Sf = take(b.Sf.size() * 8);
     void *block = nullptr;
     st = dev_alloc(c, off, &block);
     if (st) return st;
@@ -444,6 +450,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     cp(o_self, &self, 4);
     cp(o_mitems, mitems.data(), mitems.size() * 4);
     cp(o_vi, b.vi.data(), b.vi.size());
+    cp(o_fi, b.fi.data(), b.fi.size());
+    cp(o_Sf, b.Sf.data(), b.Sf.size() * 8);
     if (e == hipSuccess) e = hipMemcpy(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         dev_free(c, block, off);
@@ -464,6 +472,10 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     s.n_fb_tiles = b.n_fb;
     s.n_agents = b.n;
     s.vi = b.vi.empty() ? nullptr : (uint8_t *)(base + o_vi);
+    s.fi = b.fi.empty() ? nullptr : (uint8_t *)(base + o_fi);
+    s.Sf = b.Sf.empty() ? nullptr : (const double *)(base + o_Sf);
+    s.field_cells = (long)cells;
+    s.het = s.vi || s.fi;
     *handle = h;
     return FAST_OK;
 }
@@ -557,7 +569,7 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     std::vector<int32_t> het;
     for (int32_t h : order) {
         const Slot &s = c->slots[h];
-        if (s.vi) { het.push_back(h); continue; }
+        if (s.het) { het.push_back(h); continue; }
         for (int i = 0; i < s.n_items; ++i) items.push_back(((uint32_t)h << 20) | (uint32_t)i);
     }
     const std::vector<int> G = batch_groups(c, order);
@@ -571,7 +583,7 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     bool first = true;
     for (int32_t h : order) {
         const Slot &s = c->slots[h];
-        if (s.vi) continue;
+        if (s.het) continue;
         if (first) { b.v = s.dev.v; b.tx = s.dev.tx; first = false; }
         else if (s.dev.v != b.v || s.dev.tx != b.tx) b.v = b.tx = 0;
     }
@@ -614,7 +626,8 @@ hipError_t launch_het_members(fast_ctx *c, const Batch *b)
 {
     for (int32_t h : b->het) {
         const Slot &s = c->slots[h];
-        const hipError_t e = fk_launch_plan_het(&s.dev, s.vi, s.n_items, c->stream, nullptr, nullptr);
+        const hipError_t e = fk_launch_plan_het(&s.dev, s.vi, s.fi, s.Sf, s.field_cells, s.n_items,
+                                                c->stream, nullptr, nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1031,8 +1044,9 @@ fast_status fast_plan_step(fast_ctx *c, int32_t h)
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     next_timing_pair(c, &e0, &e1);
-    if (s->vi)
-        HIP_TRY(fk_launch_plan_het(&s->dev, s->vi, s->n_items, c->stream, e0, e1));
+    if (s->het)
+        HIP_TRY(fk_launch_plan_het(&s->dev, s->vi, s->fi, s->Sf, s->field_cells, s->n_items,
+                                   c->stream, e0, e1));
     else
         HIP_TRY(fk_launch_plan_one(&s->dev, s->n_items, 0, c->stream, e0, e1));
     s->planned = true;
@@ -1266,7 +1280,8 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     std::lock_guard<std::recursive_mutex> g(c->mu);
     Slot *s = get_slot(c, h);
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
-    if (s->vi) return fail(FAST_E_INVALID, "scenario %d has per-agent speeds: no debug dump", h);
+    if (s->het)
+        return fail(FAST_E_INVALID, "scenario %d has per-agent speeds or fields: no debug dump", h);
     const int n = std::max(s->n_agents, 1);
     const int side = 2 * s->dev.v + 1;
     const size_t bw = align_up((size_t)n * side * side * 4, 256), bf = align_up((size_t)n, 256),
@@ -1361,6 +1376,12 @@ fast_status fast_serve_submit(fast_ctx *c, const fast_scenario_desc *d, int32_t 
     if (d->agent_v) {
         r->vi.assign(d->agent_v, d->agent_v + d->n_agents);
         r->desc.agent_v = r->vi.data();
+    }
+    if (d->n_fields >= 2 && d->exit_field && d->agent_field) {
+        r->ef.assign(d->exit_field, d->exit_field + (size_t)d->width * d->height);
+        r->fi.assign(d->agent_field, d->agent_field + d->n_agents);
+        r->desc.exit_field = r->ef.data();
+        r->desc.agent_field = r->fi.data();
     }
     r->steps = steps;
     r->t_submit = now_s();

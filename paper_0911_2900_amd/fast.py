@@ -34,6 +34,8 @@ class ScenarioDesc(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("scenario_id", ctypes.c_uint32),
         ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
         ("agent_v", ctypes.c_void_p),
+        ("n_fields", ctypes.c_int32), ("exit_field", ctypes.c_void_p),
+        ("agent_field", ctypes.c_void_p),
     ]
 
 
@@ -177,8 +179,11 @@ class CUStream:
 
 
 def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, seed: int = 1,
-              scn: int = 0, agent_xy=None, tile=None, agent_v=None):
-    """Descriptor plus the host arrays it points to (keep both alive)."""
+              scn: int = 0, agent_xy=None, tile=None, agent_v=None, exit_field=None,
+              agent_field=None):
+    """Descriptor plus the host arrays it points to (keep both alive).
+    exit_field (H, W) and agent_field (n,) give several floor fields: exit
+    cells tagged g lead field g, and agent i follows field agent_field[i]."""
     ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
     H, W = ct.shape
     xy = None
@@ -199,7 +204,21 @@ def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, se
         if len(sv) != d.n_agents:
             raise ValueError("agent_v needs one speed per agent")
         d.agent_v = _ptr(sv) if len(sv) else None
-    return d, (ct, xy, sv)
+    ef = af = None
+    if (exit_field is None) != (agent_field is None):
+        raise ValueError("exit_field and agent_field go together")
+    if exit_field is not None:
+        ef = np.ascontiguousarray(np.asarray(exit_field, dtype=np.uint8))
+        af = np.ascontiguousarray(np.asarray(agent_field, dtype=np.uint8))
+        if ef.shape != ct.shape or len(af) != d.n_agents:
+            raise ValueError("exit_field needs the grid's shape, agent_field one entry per agent")
+        nf = int(ef[ct == 2].max()) + 1 if (ct == 2).any() else 1
+        if len(af):
+            nf = max(nf, int(af.max()) + 1)
+        d.n_fields = max(nf, 2)
+        d.exit_field = _ptr(ef)
+        d.agent_field = _ptr(af) if len(af) else None
+    return d, (ct, xy, sv, ef, af)
 
 
 class Context:
@@ -243,7 +262,8 @@ class Context:
 
     # -- scenarios ---------------------------------------------------------
     def init_scenario(self, cell_type, n_agents=0, v=4, k_s=1.2, seed=1, scn=0, agent_xy=None,
-                      tile="auto", batched=False, agent_v=None) -> int:
+                      tile="auto", batched=False, agent_v=None, exit_field=None,
+                      agent_field=None) -> int:
         """tile: (tx, ty); "auto" = the autotuner's table (planned alone, or in
         a batched launch when `batched`), None = the library's own rule."""
         if isinstance(tile, str):
@@ -251,8 +271,9 @@ class Context:
             ct = np.asarray(cell_type)
             n = len(agent_xy) if agent_xy is not None else int(n_agents)
             tile = autotune.choose_tile(int(v), int(ct.shape[1]), int(ct.shape[0]), n, batched,
-                                        het=agent_v is not None)
-        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_xy, tile, agent_v)
+                                        het=agent_v is not None or agent_field is not None)
+        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_xy, tile, agent_v,
+                            exit_field, agent_field)
         h = ctypes.c_int32(-1)
         _check(lib().fast_init_scenario(self.ctx, ctypes.byref(d), ctypes.byref(h)))
         self.n_agents[h.value] = d.n_agents
@@ -262,7 +283,9 @@ class Context:
     def init_from(self, sc, tile="auto", batched=False) -> int:
         """From a paper_0911_2900_amd.scenarios.Scenario."""
         return self.init_scenario(sc.cell_type, sc.n_agents, sc.v, sc.k_s, sc.seed, sc.scn,
-                                  tile=tile, batched=batched)
+                                  tile=tile, batched=batched,
+                                  exit_field=sc.meta.get("exit_field"),
+                                  agent_field=sc.meta.get("agent_field"))
 
     def destroy(self, h: int):
         _check(lib().fast_destroy_scenario(self.ctx, h))
@@ -359,8 +382,9 @@ class Context:
         _check(lib().fast_serve_start(self.ctx, int(budget), int(max_active)))
 
     def serve_submit(self, cell_type, n_agents, v, k_s=1.2, seed=1, scn=0, steps=396,
-                     agent_v=None) -> int:
-        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_v=agent_v)
+                     agent_v=None, exit_field=None, agent_field=None) -> int:
+        d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_v=agent_v,
+                            exit_field=exit_field, agent_field=agent_field)
         t = ctypes.c_uint64(0)
         _check(lib().fast_serve_submit(self.ctx, ctypes.byref(d), int(steps), ctypes.byref(t)))
         self.n_agents[("ticket", t.value)] = d.n_agents

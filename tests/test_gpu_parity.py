@@ -669,3 +669,79 @@ def test_per_agent_speeds_sequential_rebuild(ctx, monkeypatch):
     sim, h = _het_pair(ctx, s, vi, (32, 8))
     step_both(ctx, sim, h, 6, check_every=1, where="sequential rebuild")
     ctx.destroy(h)
+
+
+# ---- several floor fields (one per exit group) ---------------------------------
+
+def _field_pair(ctx, s, tile=None, vi=None):
+    ef, af = s.meta["exit_field"], s.meta["agent_field"]
+    sim = oracle.Sim(s.cell_type, s.v, s.k_s, s.seed, s.scn, n_agents=s.n_agents, agent_v=vi,
+                     exit_field=ef, agent_field=af)
+    h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=tile,
+                          agent_v=vi, exit_field=ef, agent_field=af)
+    return sim, h
+
+
+@pytest.mark.parametrize("v,tile", [(4, (16, 8)), (5, (32, 8)), (2, (16, 16))])
+def test_counterflow_fields_match_oracle(ctx, v, tile):
+    """Two groups crossing a 200 x 80 hall toward opposite walls, each by
+    its own floor field: every plan and position equal the oracle's."""
+    s = sc.counterflow(n_agents=5000, v=v, W=200, H=80)
+    say(f"counterflow v={v}, tile {tile}")
+    sim, h = _field_pair(ctx, s, tile)
+    step_both(ctx, sim, h, 10, check_every=1, where=f"counterflow v={v}")
+    ctx.run([h], 60)
+    sim.run(60)
+    compare_state(ctx, sim, h, where=f"counterflow v={v} after 70 steps")
+    assert ctx.stats(h)["fallback"] > 0          # every draw on the FP64 path
+    ctx.destroy(h)
+
+
+def test_fields_with_per_agent_speeds_match_oracle(ctx):
+    s = sc.counterflow(n_agents=3000, v=5, W=150, H=60, scn=3)
+    vi = np.random.default_rng(8).integers(1, 6, size=s.n_agents)
+    say("counterflow with per-agent speeds")
+    sim, h = _field_pair(ctx, s, (16, 8), vi)
+    step_both(ctx, sim, h, 8, check_every=1, where="fields + speeds")
+    ctx.destroy(h)
+
+
+def test_fields_in_a_batch(ctx):
+    """A counterflow hall planned by its own launch beside two uniform
+    members of one graph-replayed batch."""
+    members = [sc.ensemble_member(5), sc.counterflow(n_agents=1500, v=3, W=100, H=40, scn=9),
+               sc.ensemble_member(6)]
+    say("counterflow in a mixed batch")
+    pairs = [(_field_pair(ctx, m) if "exit_field" in m.meta else make_pair(ctx, m)) for m in members]
+    hs = [h for _, h in pairs]
+    ctx.run(hs, 20)
+    for m, (sim, h) in zip(members, pairs):
+        sim.run(20)
+        compare_state(ctx, sim, h, where=f"{m.name} in a mixed batch")
+        ctx.destroy(h)
+
+
+def test_fields_refused_where_invalid(ctx):
+    from paper_0911_2900_amd import fast
+    s = sc.counterflow(n_agents=100, v=3)
+    ef, af = s.meta["exit_field"], s.meta["agent_field"]
+    h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=None,
+                          exit_field=ef, agent_field=af)
+    with pytest.raises(fast.FastError):
+        ctx.debug_plan(h)
+    ctx.destroy(h)
+    bad_af = af.copy()
+    bad_af[0] = 2                                # field 2 has no exit cell
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, tile=None,
+                          exit_field=ef, agent_field=bad_af)
+    # a room split by a wall: the right group's exits do not reach the left half
+    t = sc.walled_box(30, 12)
+    t[:, 15] = 1
+    t[5:7, 0] = 2
+    t[5:7, 29] = 2
+    e = np.zeros_like(t)
+    e[5:7, 29] = 1
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(t, 0, 3, 1.2, 1, 0, agent_xy=[[3, 3]], tile=None,
+                          exit_field=e, agent_field=[1])

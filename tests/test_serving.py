@@ -49,7 +49,9 @@ def _serve(fast, reqs, budget, max_active, gap_s, speeds=None):
         for i, (m, steps) in enumerate(reqs):
             tickets.append(ctx.serve_submit(m.cell_type, m.n_agents, m.v, m.k_s, m.seed, m.scn,
                                             steps=steps,
-                                            agent_v=None if speeds is None else speeds[i]))
+                                            agent_v=None if speeds is None else speeds[i],
+                                            exit_field=m.meta.get("exit_field"),
+                                            agent_field=m.meta.get("agent_field")))
             time.sleep(gap_s)                      # later requests arrive while others run
         deadline = time.time() + 120
         lat = {}
@@ -88,6 +90,21 @@ def test_served_per_agent_speeds_equal_oracle(fast_mod):
     results, lat = _serve(fast_mod, reqs, budget=0, max_active=3, gap_s=0.002, speeds=speeds)
     for (m, steps), vi, r in zip(reqs, speeds, results):
         sim = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents, agent_v=vi)
+        sim.run(steps)
+        assert r["step"] == steps
+        assert np.array_equal(r["xy"], sim.positions()), m.name
+
+
+def test_served_counterflow_fields_equal_oracle(fast_mod):
+    """Counterflow halls (a floor field per exit group) served between
+    ordinary requests: every final state equals the oracle's run alone."""
+    reqs = _requests(60, 4, 20)
+    reqs[1] = (sc.counterflow(n_agents=800, v=4, W=80, H=30, scn=61), 30)
+    reqs[3] = (sc.counterflow(n_agents=400, v=2, W=50, H=24, scn=63), 40)
+    results, lat = _serve(fast_mod, reqs, budget=0, max_active=2, gap_s=0.002)
+    for (m, steps), r in zip(reqs, results):
+        sim = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents,
+                         exit_field=m.meta.get("exit_field"), agent_field=m.meta.get("agent_field"))
         sim.run(steps)
         assert r["step"] == steps
         assert np.array_equal(r["xy"], sim.positions()), m.name
