@@ -96,10 +96,10 @@ def window_cells(cell_type: np.ndarray, xy: np.ndarray, v: int) -> int:
 
 
 def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4, n_agents: int = 40000,
-               agent_v=None):
+               agent_v=None, scenario=None):
     from paper_0911_2900_amd import scenarios as sc
 
-    s = sc.room(v=v, n_agents=n_agents)
+    s = sc.room(v=v, n_agents=n_agents) if scenario is None else scenario
     if agent_v is None:
         h = ctx.init_from(s)
     else:
@@ -497,6 +497,29 @@ def bench_het(ctx, torch, warmup: int, steps: int):
     return out
 
 
+def bench_fields(ctx, torch, warmup: int, steps: int):
+    """A 400 x 400 counterflow hall, 40,000 agents at v_m = 4 in two groups,
+    each following the floor field of its own exits (left or right wall):
+    every draw in FP64 with the agent's own field.  Beside it the 400 x 400
+    room with one exit and one field (FP32 table path)."""
+    from paper_0911_2900_amd import scenarios as sc
+
+    out = {}
+    for key, scn in (("two_fields", sc.counterflow(n_agents=40000, v=4, W=400, H=400)),
+                     ("one_field_room", None)):
+        r = bench_room(ctx, torch, warmup, steps, v=4, scenario=scn)
+        out[key] = {"planning_agent_updates_per_s": r["planned"] / (sum(r["plan_ms"]) / 1e3),
+                    "plan_us": float(np.mean(r["plan_ms"])) * 1e3,
+                    "whole_step_us": r["total_ms"] / steps * 1e3,
+                    "tile": [r["stats"]["tile_w"], r["stats"]["tile_h"]],
+                    "exited": r["stats"]["exited"],
+                    "fp64_draws_per_step": r["stats"]["fallback"] / (warmup + steps)}
+        log(f"fields {key}: {out[key]}")
+    out["workload"] = ("counterflow hall 400x400, exits 4 cells on the left and right walls, "
+                       "40,000 agents in two even groups, v_m=4, k_S=1.2")
+    return out
+
+
 def achievable(ctx, achieved_gbs: float, footprint: float, stream_4g: float) -> dict:
     """The planning launch's algorithmic rate against what the streaming
     kernel reaches beyond the cache (4 GiB) and at the launch's own
@@ -584,6 +607,9 @@ def main():
                     help="--sweep-cu: room agent counts, comma-separated (empty: none)")
     ap.add_argument("--het", action="store_true",
                     help="only the room with a maximum speed per agent (FP64 planning path)")
+    ap.add_argument("--fields", action="store_true",
+                    help="only the counterflow hall with a floor field per exit group "
+                         "(FP64 planning path)")
     ap.add_argument("--no-fd", action="store_true",
                     help="leave the fundamental-diagram ensemble out of the default run")
     ap.add_argument("--fd", action="store_true",
@@ -630,6 +656,10 @@ def main():
         return
     if args.het:
         print(json.dumps({"het": bench_het(ctx, torch, args.warmup, args.steps)}), flush=True)
+        ctx.close()
+        return
+    if args.fields:
+        print(json.dumps({"fields": bench_fields(ctx, torch, args.warmup, args.steps)}), flush=True)
         ctx.close()
         return
     if args.sweep_v:

@@ -87,12 +87,14 @@ __device__ int draw_het_wave(const SlotDev &s, const double *__restrict__ S, int
 }
 
 // Workgroup i plans tile i with HET_THREADS threads; wavefront q draws the
-// tile's agents q, q + HET_THREADS / 64, ...; vi[id] is agent id's speed
-// (vi NULL: every agent has V), fi[id] its floor field, which starts at
-// Sf + fi[id] * field_cells (fi NULL: Sf alone).
+// tile's agents q, q + HET_THREADS / 64, ...; vi[id] is agent id's speed.
+// FIELDS: agent id follows the floor field at Sf + fi[id] * field_cells and
+// vi may be NULL (every agent has V); otherwise the scenario's one field
+// s.S, with vi set.  Each form is its own kernel, so the single-field form
+// does no per-agent field lookup.
 constexpr int HET_THREADS = 1024;
 
-template <int V, int TX>
+template <int V, int TX, bool FIELDS>
 __global__ __launch_bounds__(HET_THREADS) void plan_kernel_het(const SlotDev s,
                                                                const uint8_t *__restrict__ vi,
                                                                const uint8_t *__restrict__ fi,
@@ -123,9 +125,15 @@ __global__ __launch_bounds__(HET_THREADS) void plan_kernel_het(const SlotDev s,
         const int gc = cy * s.Wp + cx;
         const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, s.scn, s.seed_lo, s.seed_hi);
         const float u = (float)(x0 >> 8) * 0x1p-24f;
-        const int vr = vi ? (int)vi[id] : V;
-        const double *S = fi ? Sf + (long)fi[id] * field_cells : Sf;
-        const int t = draw_het_wave<V>(s, S, gc, u, lane, vr);
+        int t;
+        if constexpr (FIELDS) {
+            // the whole wavefront draws agent k, so its field is uniform
+            const int f = __builtin_amdgcn_readfirstlane((int)fi[id]);
+            const int vr = vi ? (int)vi[id] : V;
+            t = draw_het_wave<V>(s, Sf + (long)f * field_cells, gc, u, lane, vr);
+        } else {
+            t = draw_het_wave<V>(s, s.S, gc, u, lane, (int)vi[id]);
+        }
         if (lane == 0) {
             const int d = t - gc;                               // |dx|, |dy| <= V < Wp / 2
             const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
@@ -143,11 +151,22 @@ hipError_t launch_het_v(const SlotDev &s, const uint8_t *vi, const uint8_t *fi, 
                         long fc, dim3 grid, hipStream_t stream, hipEvent_t start, hipEvent_t stop)
 {
     const dim3 block(HET_THREADS);
+    if (fi) {
+        switch (s.tx) {
+            case 8: hipExtLaunchKernelGGL((plan_kernel_het<V, 8, true>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+            case 16: hipExtLaunchKernelGGL((plan_kernel_het<V, 16, true>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+            case 32: hipExtLaunchKernelGGL((plan_kernel_het<V, 32, true>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+            case 64: hipExtLaunchKernelGGL((plan_kernel_het<V, 64, true>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (!vi) return hipErrorInvalidValue;
     switch (s.tx) {
-        case 8: hipExtLaunchKernelGGL((plan_kernel_het<V, 8>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-        case 16: hipExtLaunchKernelGGL((plan_kernel_het<V, 16>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-        case 32: hipExtLaunchKernelGGL((plan_kernel_het<V, 32>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-        case 64: hipExtLaunchKernelGGL((plan_kernel_het<V, 64>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+        case 8: hipExtLaunchKernelGGL((plan_kernel_het<V, 8, false>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+        case 16: hipExtLaunchKernelGGL((plan_kernel_het<V, 16, false>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+        case 32: hipExtLaunchKernelGGL((plan_kernel_het<V, 32, false>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
+        case 64: hipExtLaunchKernelGGL((plan_kernel_het<V, 64, false>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
