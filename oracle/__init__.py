@@ -116,7 +116,7 @@ def place(cell_type_after: np.ndarray, S: np.ndarray, n: int, seed: int, scn: in
 
 
 def floor_field_of(cell_type_after: np.ndarray, exit_field: np.ndarray, g: int) -> np.ndarray:
-    """Floor field g of a scenario with several fields (reading R9): the exact
+    """Floor field g of a scenario with several fields (reading R13): the exact
     field from the exit cells whose exit_field value is g, +inf where they do
     not reach."""
     t = np.ascontiguousarray(cell_type_after, dtype=np.uint8)
@@ -171,7 +171,7 @@ class Sim:
                                                            or self.agent_v.max() > v)):
                 raise ValueError("agent_v: one speed in 1..v per agent")
             self._st.vi = _ptr(self.agent_v) if self.n else None
-        # several floor fields (reading R9): agent i follows field agent_field[i]
+        # several floor fields (reading R13): agent i follows field agent_field[i]
         self.Sf = self.agent_field = None
         if (exit_field is None) != (agent_field is None):
             raise ValueError("exit_field and agent_field go together")

@@ -45,7 +45,7 @@
  *  R8  seeded placement: partial Fisher-Yates over the eligible cells (free,
  *      reachable) in raster order with j = k + ((x0 * (M - k)) >> 32), x0 from
  *      Philox at counter (k, 0, scenario, 2).
- *  R9  several floor fields (route choice, counterflow; Sec. 3 names richer
+ *  R13 several floor fields (route choice, counterflow; Sec. 3 names richer
  *      situations as the next cost driver): field g is R7's exact field from
  *      the exit cells tagged g alone, +inf where those exits do not reach;
  *      agent i weighs its window with its own field in R2; walls stay those
