@@ -126,3 +126,43 @@ def test_cu_mask_rejects_bad_counts(fast):
     for n, cus in [(0, 256), (4, 256), (12, 256), (264, 256), (8, 96), (8, 0)]:
         with pytest.raises(fast.FastError):
             fast.cu_mask(n, cus)
+
+
+def _c_offsets(struct: str, fields, tmp_path):
+    """offsetof of each field and sizeof of `struct`, from gcc and the header."""
+    src = tmp_path / "layout.c"
+    body = "".join(f'    printf("%zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "fast.h"\nint main(void) {\n'
+                   + body + f'    printf("%zu\\n", sizeof({struct}));\n    return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return [int(x) for x in out]
+
+
+@pytest.mark.parametrize("struct,py", [("fast_scenario_desc", "ScenarioDesc"),
+                                       ("fast_stats", "Stats")])
+def test_binding_structs_match_the_header_layout(fast, tmp_path, struct, py):
+    cls = getattr(fast, py)
+    names = [n for n, _ in cls._fields_]
+    c = _c_offsets(struct, names, tmp_path)
+    import ctypes
+    assert c[:-1] == [getattr(cls, n).offset for n in names]
+    assert c[-1] == ctypes.sizeof(cls)
+
+
+def test_descriptor_takes_floor_field_groups(fast):
+    s = sc.counterflow(n_agents=50, v=3)
+    ef, af = s.meta["exit_field"], s.meta["agent_field"]
+    d, keep = fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=ef, agent_field=af)
+    assert d.n_fields == 2 and d.exit_field and d.agent_field
+    d, _ = fast.make_desc(s.cell_type, s.n_agents, s.v)
+    assert d.n_fields == 0 and not d.exit_field and not d.agent_field
+    with pytest.raises(ValueError):
+        fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=ef)
+    with pytest.raises(ValueError):
+        fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=ef[:, 1:], agent_field=af)
+    with pytest.raises(ValueError):
+        fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=ef, agent_field=af[1:])
