@@ -220,7 +220,10 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
     std::vector<std::vector<double>> fields;
     if (nf < 0 || nf > 8) { err = "n_fields must lie in 0..8"; return FAST_E_INVALID; }
     if (nf >= 2) {
-        if (!d.exit_field || !d.agent_field) { err = "n_fields >= 2 needs exit_field and agent_field"; return FAST_E_INVALID; }
+        if (!d.exit_field || (!d.agent_field && d.n_agents > 0)) {
+            err = "n_fields >= 2 needs exit_field and (with agents) agent_field";
+            return FAST_E_INVALID;
+        }
         std::vector<int> exits((size_t)nf, 0);
         for (int64_t i = 0; i < (int64_t)W * H; ++i)
             if (type[i] == fk::CELL_EXIT) {
@@ -231,7 +234,7 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
             if (!exits[g]) { err = "every floor field needs an exit cell"; return FAST_E_INVALID; }
         fields.resize((size_t)nf);
         for (int g = 0; g < nf; ++g) floor_field(W, H, type, fields[g], d.exit_field, g);
-        b.fi.assign(d.agent_field, d.agent_field + d.n_agents);
+        if (d.n_agents > 0) b.fi.assign(d.agent_field, d.agent_field + d.n_agents);
         for (int i = 0; i < d.n_agents; ++i) {
             if (b.fi[i] >= nf) { err = "agent_field values must lie in 0..n_fields-1"; return FAST_E_INVALID; }
             const int64_t c = (int64_t)xy[2 * i + 1] * W + xy[2 * i];

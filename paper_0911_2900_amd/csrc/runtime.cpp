@@ -1377,10 +1377,12 @@ fast_status fast_serve_submit(fast_ctx *c, const fast_scenario_desc *d, int32_t 
         r->vi.assign(d->agent_v, d->agent_v + d->n_agents);
         r->desc.agent_v = r->vi.data();
     }
-    if (d->n_fields >= 2 && d->exit_field && d->agent_field) {
+    if (d->exit_field) {
         r->ef.assign(d->exit_field, d->exit_field + (size_t)d->width * d->height);
-        r->fi.assign(d->agent_field, d->agent_field + d->n_agents);
         r->desc.exit_field = r->ef.data();
+    }
+    if (d->agent_field && d->n_agents > 0) {
+        r->fi.assign(d->agent_field, d->agent_field + d->n_agents);
         r->desc.agent_field = r->fi.data();
     }
     r->steps = steps;

@@ -745,3 +745,45 @@ def test_fields_refused_where_invalid(ctx):
     with pytest.raises(fast.FastError):
         ctx.init_scenario(t, 0, 3, 1.2, 1, 0, agent_xy=[[3, 3]], tile=None,
                           exit_field=e, agent_field=[1])
+
+
+def _eight_exit_groups(size=240, n_agents=12000, v=5, scn=21):
+    """A walled square hall with eight 3-cell exits, two per wall, each its
+    own group; agents tagged with a seeded field in 0..7."""
+    t = sc.walled_box(size, size)
+    ef = np.zeros_like(t)
+    q = [size // 3, 2 * size // 3]
+    spots = [((0, y), 0) for y in q] + [((size - 1, y), 0) for y in q] + \
+            [((x, 0), 1) for x in q] + [((x, size - 1), 1) for x in q]
+    for g, ((x, y), horiz) in enumerate(spots):
+        if horiz:
+            t[y, x - 1:x + 2] = 2
+            ef[y, x - 1:x + 2] = g
+        else:
+            t[y - 1:y + 2, x] = 2
+            ef[y - 1:y + 2, x] = g
+    af = np.random.default_rng([scn, 8]).integers(0, 8, size=n_agents).astype(np.uint8)
+    return sc.Scenario(f"hall_{size}_8_fields", t, n_agents, v, 1.2, 6, scn,
+                       meta={"exit_field": ef, "agent_field": af})
+
+
+def test_eight_floor_fields_match_oracle(ctx):
+    """The largest number of fields (8), one per exit, at v = 5."""
+    s = _eight_exit_groups()
+    say("eight floor fields")
+    sim, h = _field_pair(ctx, s, (16, 8))
+    step_both(ctx, sim, h, 5, check_every=1, where="eight fields")
+    ctx.run([h], 40)
+    sim.run(40)
+    compare_state(ctx, sim, h, where="eight fields after 45 steps")
+    ctx.destroy(h)
+
+
+def test_fields_with_no_agents(ctx):
+    s = sc.counterflow(n_agents=0, v=3)
+    say("fields, no agents")
+    sim, h = _field_pair(ctx, s)
+    ctx.run([h], 3)
+    st = ctx.stats(h)
+    assert st["step"] == 3 and st["n_active"] == 0
+    ctx.destroy(h)
