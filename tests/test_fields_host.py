@@ -98,3 +98,55 @@ def test_counterflow_groups_leave_by_their_own_side():
     # the last cell before leaving is next to the exit the agent used
     right = last[:, 0] > s.W // 2
     assert np.mean(right[af == 0]) > 0.95 and np.mean(~right[af == 1]) > 0.95
+
+
+def _bellman_ford(after: np.ndarray, sources: np.ndarray) -> np.ndarray:
+    """Shortest walking length from the source cells by repeated relaxation
+    over the 8 neighbours (orthogonal 1, diagonal sqrt 2 when neither
+    orthogonal neighbour is a wall); no priority queue, no exact lengths."""
+    H, W = after.shape
+    D = np.full((H, W), np.inf)
+    D[sources] = 0.0
+    wall = after == 1
+    changed = True
+    while changed:
+        changed = False
+        for y in range(H):
+            for x in range(W):
+                if wall[y, x]:
+                    continue
+                best = D[y, x]
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        ny, nx = y + dy, x + dx
+                        if (dx == 0 and dy == 0) or not (0 <= ny < H and 0 <= nx < W) or wall[ny, nx]:
+                            continue
+                        if dx and dy:
+                            if wall[y, nx] or wall[ny, x]:
+                                continue
+                            step = np.sqrt(2.0)
+                        else:
+                            step = 1.0
+                        best = min(best, D[ny, nx] + step)
+                if best < D[y, x]:
+                    D[y, x] = best
+                    changed = True
+    return D
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_group_fields_equal_brute_force_relaxation(seed):
+    rng = np.random.default_rng(seed)
+    s = sc.random_small(rng, 14, 11, 0.15, 0, 3, n_exits=3)
+    after = oracle.floor_field(s.cell_type)[0]
+    exits = np.argwhere(after == 2)
+    ef = np.zeros_like(after)
+    ef[tuple(exits.T)] = rng.integers(0, 2, size=len(exits))
+    ef[tuple(exits[0])] = 0
+    ef[tuple(exits[-1])] = 1
+    for g in (0, 1):
+        F = oracle.floor_field_of(after, ef, g)
+        B = _bellman_ford(after, (after == 2) & (ef == g))
+        finite = np.isfinite(B)
+        assert np.array_equal(finite, np.isfinite(F))
+        assert np.allclose(F[finite], B[finite], rtol=0, atol=1e-12)
