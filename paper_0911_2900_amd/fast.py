@@ -215,9 +215,10 @@ def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, se
         nf = int(ef[ct == 2].max()) + 1 if (ct == 2).any() else 1
         if len(af):
             nf = max(nf, int(af.max()) + 1)
-        d.n_fields = max(nf, 2)
-        d.exit_field = _ptr(ef)
-        d.agent_field = _ptr(af) if len(af) else None
+        d.n_fields = nf                  # one group is the single-field model
+        if nf >= 2:
+            d.exit_field = _ptr(ef)
+            d.agent_field = _ptr(af) if len(af) else None
     return d, (ct, xy, sv, ef, af)
 
 

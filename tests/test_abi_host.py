@@ -160,6 +160,10 @@ def test_descriptor_takes_floor_field_groups(fast):
     assert d.n_fields == 2 and d.exit_field and d.agent_field
     d, _ = fast.make_desc(s.cell_type, s.n_agents, s.v)
     assert d.n_fields == 0 and not d.exit_field and not d.agent_field
+    # every exit and agent in group 0: the single-field model
+    d, _ = fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=np.zeros_like(ef),
+                          agent_field=np.zeros_like(af))
+    assert d.n_fields == 1 and not d.exit_field and not d.agent_field
     with pytest.raises(ValueError):
         fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=ef)
     with pytest.raises(ValueError):

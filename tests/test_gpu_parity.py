@@ -787,3 +787,18 @@ def test_fields_with_no_agents(ctx):
     st = ctx.stats(h)
     assert st["step"] == 3 and st["n_active"] == 0
     ctx.destroy(h)
+
+
+def test_one_exit_group_runs_the_single_field_model(ctx):
+    """Every exit and agent tagged 0: the binding sends one field, the
+    uniform kernels plan, and the oracle with the group field agrees."""
+    s = sc.counterflow(n_agents=2000, v=4, W=120, H=50, scn=5)
+    s.meta["exit_field"] = np.zeros_like(s.meta["exit_field"])
+    s.meta["agent_field"] = np.zeros_like(s.meta["agent_field"])
+    say("one exit group")
+    sim, h = _field_pair(ctx, s)
+    ctx.run([h], 30)
+    sim.run(30)
+    compare_state(ctx, sim, h, where="one exit group")
+    assert ctx.stats(h)["fallback"] == 0          # FP32 table path
+    ctx.destroy(h)
