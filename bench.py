@@ -28,7 +28,7 @@ Also printed on the same JSON line:
                 one at a time with plain launches.
   serving       the continuous-batching server on Poisson arrivals: p50 / p99
                 latency and scenarios/s, open and closed loop.
-  cpu_baseline  the CPU oracle's planning loop (the paper's OpenMP schedule)
+  cpu_baseline  the CPU oracle's threaded planning loop (chunks as in the paper)
                 on the host's cores, on the first steps of the same run.
 """
 from __future__ import annotations
@@ -148,7 +148,7 @@ def bench_ensemble(ctx, torch, warmup: int, steps: int, plain_steps: int):
     t0 = time.perf_counter()
     hs = [ctx.init_from(m, batched=True) for m in ens]
     init_s = time.perf_counter() - t0
-    ctx.run(hs, warmup)
+    ctx.run(hs, warmup)                    # the first step also captures the step graph
     planned0 = sum(ctx.stats(h)["planned"] for h in hs)
     stream = ctx.stream
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -179,6 +179,9 @@ def bench_ensemble(ctx, torch, warmup: int, steps: int, plain_steps: int):
         "scenarios": n, "cells": int(sum(m.W * m.H for m in ens)),
         "agents": int(sum(m.n_agents for m in ens)),
         "steps": steps,
+        "timed_steps": f"{warmup}..{warmup + steps - 1} of each scenario's 396-step run "
+                       f"(steps 0..{warmup - 1} untimed: graph capture and warmup)",
+        "plain_loop_timed_steps": f"{warmup + steps}..{warmup + steps + plain_steps - 1}",
         "batched_scenario_steps_per_s": n * steps / (batched_ms / 1e3),
         "batched_agent_updates_per_s": planned / (batched_ms / 1e3),
         "plain_loop_scenario_steps_per_s": n * plain_steps / (plain_ms / 1e3),
@@ -317,8 +320,9 @@ def bench_serving(fast, n_req: int, rate: float, steps: int = 396, plain_sample:
 
 
 def cpu_baseline(budget_s: float = 15.0, max_steps: int = 396, v: int = 4):
-    """The oracle as it stands: its OpenMP planning loop (paper Sec. 2
-    schedule) on every host thread, sequential motion, on the room workload."""
+    """The oracle as it stands: its threaded planning loop (threads claim
+    chunks of N / threads agents, at most 32767, as in paper Sec. 2) on every
+    host thread, sequential motion, on the room workload."""
     import oracle
     from paper_0911_2900_amd import scenarios as sc
 
@@ -330,7 +334,7 @@ def cpu_baseline(budget_s: float = 15.0, max_steps: int = 396, v: int = 4):
     while steps < max_steps and time.perf_counter() - t_all < budget_s:
         n = sim.n_alive()
         t0 = time.perf_counter()
-        sim.plan_omp(cores)
+        sim.plan_threads(cores)
         plan_s += time.perf_counter() - t0
         planned += n
         sim.move()
@@ -339,8 +343,8 @@ def cpu_baseline(budget_s: float = 15.0, max_steps: int = 396, v: int = 4):
     return {
         "value": planned / plan_s, "unit": "agent-updates/s", "cores": cores, "kind": "oracle",
         "sample": f"first {steps} steps of the 400x400 room, 40,000 agents, v_m={v}: FP64 "
-                  f"planning loop with schedule(dynamic, max(min(N/cores, 32767), 1)) on "
-                  f"{cores} threads (timed), sequential motion (untimed)",
+                  f"planning loop, threads claiming chunks of max(min(N/threads, 32767), 1) "
+                  f"agents, on {cores} threads (timed), sequential motion (untimed)",
         "whole_steps_s": time.perf_counter() - t_all,
     }
 
@@ -532,7 +536,7 @@ def achievable(ctx, achieved_gbs: float, footprint: float, stream_4g: float) -> 
 
 
 def cpu_table(budget_steps: int = 5):
-    """The oracle on the host: one thread, and its OpenMP planning loop on
+    """The oracle on the host: one thread, and its threaded planning loop on
     every host thread, per workload (planning agent-updates/s and whole steps
     per second; the room, ensemble and 1000 x 1000 rows time the first
     `budget_steps` steps, the corridor its full 396)."""
@@ -553,7 +557,7 @@ def cpu_table(budget_steps: int = 5):
                     if threads == 1:
                         sim.plan()
                     else:
-                        sim.plan_omp(threads)
+                        sim.plan_threads(threads)
                     plan_s += time.perf_counter() - t1
                     planned += n
                     sim.move()
@@ -579,7 +583,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=386)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--ensemble-steps", type=int, default=60)
+    ap.add_argument("--ensemble-steps", type=int, default=395,
+                    help="batched ensemble steps timed after one untimed step (395: the rest "
+                         "of the 396-step run)")
     ap.add_argument("--plain-steps", type=int, default=4)
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-large", action="store_true")
@@ -711,7 +717,7 @@ def main():
     ens = None
     if not args.no_ensemble:
         log("ensemble ...")
-        ens = bench_ensemble(ctx, torch, 5, args.ensemble_steps, args.plain_steps)
+        ens = bench_ensemble(ctx, torch, 1, args.ensemble_steps, args.plain_steps)
         log(f"ensemble: {ens}")
     fdr = None
     if not args.no_fd:
@@ -747,7 +753,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "room 400x400 cells, 10-cell exit, 40,000 agents, v_m=4, k_S=1.2, "
-                        "k_other=0; steps 0..395 of the 396-step run (warmup first)",
+                        f"k_other=0; timed steps {args.warmup}..{args.warmup + args.steps - 1} "
+                        f"of a 396-step run (steps 0..{args.warmup - 1} untimed warmup)",
             "agents": 40000, "grid": [400, 400], "v_m": 4, "k_S": 1.2,
             "tile": [r["stats"]["tile_w"], r["stats"]["tile_h"]],
             "parallelism": "1 GPU",

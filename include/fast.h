@@ -172,7 +172,8 @@ fast_status fast_plan_step(fast_ctx *ctx, int32_t handle);
  * of the same step (FAST_E_STATE otherwise). */
 fast_status fast_move_step(fast_ctx *ctx, int32_t handle);
 
-/* `steps` full time steps (plan then move) of each of the n scenarios, which
+/* `steps` full time steps of each of the n scenarios (Sec. 2: a run is 396
+ * steps of one simulated second, each a planning phase then a motion phase),
  * run as one batch: each step is one planning launch over the tiles of all
  * scenarios and one motion launch, replayed from a captured HIP graph.  Every
  * scenario keeps its own step counter.  n >= 1, steps >= 0. */
@@ -188,7 +189,9 @@ fast_status fast_plan_batch(fast_ctx *ctx, const int32_t *handles, int32_t n);
  * form of fast_move_step); each must have been planned for this step. */
 fast_status fast_move_batch(fast_ctx *ctx, const int32_t *handles, int32_t n);
 
-/* Copies the state back (synchronises the stream).  Any pointer may be NULL.
+/* Copies the state back (synchronises the stream): the agents' cells after
+ * the last motion phase and the desired cells of the last planning phase
+ * (Sec. 1's two phases).  Any pointer may be NULL.
  * xy: 2*n_agents (x, y), (-1, -1) for agents that left; alive: n_agents;
  * desired: n_agents cells y*width + x of the last plan (-1 when gone). */
 fast_status fast_get_state(fast_ctx *ctx, int32_t handle, int32_t *xy, uint8_t *alive,
@@ -197,14 +200,25 @@ fast_status fast_get_state(fast_ctx *ctx, int32_t handle, int32_t *xy, uint8_t *
 /* Counters of a scenario (synchronises the stream). */
 fast_status fast_get_stats(fast_ctx *ctx, int32_t handle, fast_stats *out);
 
-/* Debug planning phase: as fast_plan_step, and also returns, per agent id,
- * w32[id * (2v+1)^2 + slot] = the FP32 weight e_t / e_c of each raster slot
- * (0 outside the reach set; the FP64 weight rounded to FP32 on fallback
- * tiles), flag[id] = 1 if the draw was re-resolved in FP64 (2 on a fallback
- * tile), margin[id] = distance of u*W to the nearest CDF boundary over W.
- * Host buffers sized for n_agents; any may be NULL.  Synchronises. */
+/* Debug planning phase: as fast_plan_step, and also returns, per agent id:
+ *   w32[id * (2v+1)^2 + slot]   the weight of each raster slot of the window
+ *       (Sec. 1's planning weight exp(k_S (S(c) - S(t))), 0 outside the reach
+ *       set) divided by the largest weight of the agent's reach set, so that
+ *       every value lies in [0, 1] and FP32 holds it: the kernel's table
+ *       values e_t / e_max on ordinary tiles, the FP64 ratio rounded to FP32
+ *       on range-fallback tiles (the draw depends on these ratios only);
+ *   flag[id] = 1 if the draw was re-resolved in FP64 (2 on a fallback tile);
+ *   margin[id] = distance of u*W to the nearest CDF boundary the draw
+ *       examined, over W (FP32; -1 on fallback tiles);
+ *   cdf32[id * (2v+1)^2 + slot]   the FP32 CDF the draw searches, at every
+ *       slot of the reach disc, in the kernel's scale (row prefix plus the
+ *       in-row running sum); the window's last slot, a corner outside every
+ *       disc, holds the FP32 total W.  All zero on fallback tiles, which have
+ *       no FP32 CDF.
+ * Host buffers sized for n_agents; any may be NULL.  Refuses scenarios with
+ * per-agent speeds or several fields (FAST_E_INVALID).  Synchronises. */
 fast_status fast_debug_plan(fast_ctx *ctx, int32_t handle, float *w32, uint8_t *flag,
-                            float *margin);
+                            float *margin, float *cdf32);
 
 /* ---- Kernel timing ------------------------------------------------------ */
 

@@ -29,7 +29,7 @@ def build(force: bool = False) -> str:
     """Compile fast_oracle.c with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
                "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
@@ -68,7 +68,7 @@ def lib():
         _lib.oracle_plan_agent.argtypes = [P, ctypes.c_int32, P, P, P, P]
         _lib.oracle_plan_agent.restype = ctypes.c_int32
         _lib.oracle_plan_step.argtypes = [P]
-        _lib.oracle_plan_step_omp.argtypes = [P, ctypes.c_int32]
+        _lib.oracle_plan_step_threads.argtypes = [P, ctypes.c_int32]
         _lib.oracle_move_step.argtypes = [P]
         _lib.oracle_run.argtypes = [P, ctypes.c_int32]
         _lib.oracle_count_alive.argtypes = [P]
@@ -224,8 +224,10 @@ class Sim:
         if lib().oracle_plan_step(ctypes.byref(self._st)) != 0:
             raise RuntimeError("plan failed")
 
-    def plan_omp(self, cores: int):
-        if lib().oracle_plan_step_omp(ctypes.byref(self._st), int(cores)) != 0:
+    def plan_threads(self, threads: int):
+        """The planning phase on `threads` host threads claiming chunks of
+        agents (the CPU baseline's loop); same draws as plan()."""
+        if lib().oracle_plan_step_threads(ctypes.byref(self._st), int(threads)) != 0:
             raise RuntimeError("plan failed")
 
     def move(self):

@@ -16,9 +16,10 @@
  *    agents (v_m = 1..5), 396 steps of one simulated second; the only parallel
  *    loop calls choose_desired_cell(i) for every agent i.
  *
- * Everything below is double precision, single threaded (apart from the
- * OpenMP copy of the paper's planning loop, which gives the same draws), and
- * written to be read against the model rather than to be fast.
+ * Everything below is double precision, single threaded (apart from a
+ * threaded copy of the planning loop for the CPU baseline, which gives the
+ * same draws), and written to be read against the model rather than to be
+ * fast.
  *
  * The paper does not restate the model's formulas; where it is silent this
  * file takes these readings (each function names the one it implements):
@@ -61,9 +62,9 @@
 #include <stdlib.h>
 #include <string.h>
 
-#ifdef _OPENMP
-#include <omp.h>
-#endif
+#include <pthread.h>
+#include <stdatomic.h>
+#include <unistd.h>
 
 enum { CELL_FREE = 0, CELL_WALL = 1, CELL_EXIT = 2 };
 
@@ -420,29 +421,59 @@ int oracle_plan_step(oracle_state *st)
 }
 
 /*
- * The same planning phase with the paper's OpenMP loop (Sec. 2): a team of
- * `cores` threads and a dynamic schedule with chunks of
- * max(min(N / cores, 32767), 1) agents.  Same draws as oracle_plan_step.
- * Used only to time the CPU baseline.
+ * The same planning phase on `threads` host threads, used only to time a CPU
+ * baseline that parallelises the way Sec. 2 describes: the agents are cut into
+ * consecutive chunks, and a thread that runs out of work claims the next
+ * unclaimed chunk.  A chunk holds N / threads agents, capped at 32767 and at
+ * least one (the chunk size Sec. 2 uses).  Every draw depends on its agent
+ * and the shared snapshot only, so the result equals oracle_plan_step's.
  */
-int oracle_plan_step_omp(oracle_state *st, int32_t cores)
+typedef struct {
+    oracle_state *st;
+    int32_t chunk;
+    atomic_int next;      /* first agent of the next unclaimed chunk */
+    atomic_int failed;
+} claim_pool;
+
+static void *claim_and_plan(void *arg)
 {
-    int32_t n = st->n;
-    if (cores < 1) cores = 1;
-    int32_t blocksize = n / cores;
-    if (blocksize > 32767) blocksize = 32767;
-    if (blocksize < 1) blocksize = 1;
-    int bad = 0;
-#pragma omp parallel num_threads(cores)
-    {
-#pragma omp for schedule(dynamic, blocksize)
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t d = oracle_plan_agent(st, i, NULL, NULL, NULL, NULL);
-            if (d == -2) bad = 1;
-            st->desired[i] = d;
+    claim_pool *p = arg;
+    const int32_t n = p->st->n;
+    for (;;) {
+        const int32_t lo = atomic_fetch_add(&p->next, p->chunk);
+        if (lo >= n) break;
+        const int32_t hi = n - lo > p->chunk ? lo + p->chunk : n;
+        for (int32_t i = lo; i < hi; ++i) {
+            const int32_t d = oracle_plan_agent(p->st, i, NULL, NULL, NULL, NULL);
+            if (d == -2) atomic_store(&p->failed, 1);
+            p->st->desired[i] = d;
         }
     }
-    return bad ? -1 : 0;
+    return NULL;
+}
+
+enum { MAX_PLAN_THREADS = 256 };
+
+int oracle_plan_step_threads(oracle_state *st, int32_t threads)
+{
+    if (threads < 1) threads = 1;
+    if (threads > MAX_PLAN_THREADS) threads = MAX_PLAN_THREADS;
+    claim_pool p;
+    p.st = st;
+    p.chunk = st->n / threads;
+    if (p.chunk > 32767) p.chunk = 32767;
+    if (p.chunk < 1) p.chunk = 1;
+    atomic_init(&p.next, 0);
+    atomic_init(&p.failed, 0);
+    pthread_t helper[MAX_PLAN_THREADS];
+    int32_t started = 0;
+    for (int32_t k = 1; k < threads; ++k) {     /* the calling thread is the first worker */
+        if (pthread_create(&helper[started], NULL, claim_and_plan, &p) != 0) break;
+        ++started;
+    }
+    claim_and_plan(&p);
+    for (int32_t k = 0; k < started; ++k) pthread_join(helper[k], NULL);
+    return atomic_load(&p.failed) ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -537,11 +568,9 @@ int32_t oracle_count_alive(const oracle_state *st)
     return c;
 }
 
+/* Host threads online (the CPU baseline may be told to use fewer). */
 int32_t oracle_num_threads(void)
 {
-#ifdef _OPENMP
-    return omp_get_max_threads();
-#else
-    return 1;
-#endif
+    const long n = sysconf(_SC_NPROCESSORS_ONLN);
+    return n > 0 ? (int32_t)n : 1;
 }

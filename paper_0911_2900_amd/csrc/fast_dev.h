@@ -126,6 +126,7 @@ struct SlotDev {
     float *dbg_w;            // optional debug outputs (null in normal runs)
     uint8_t *dbg_flag;
     float *dbg_margin;
+    float *dbg_cdf;
 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), word 0 of the output

@@ -110,13 +110,16 @@ __device__ __forceinline__ bool reach_ok(const SlotDev &s, int gc, int t, int dx
 }
 
 // (The loops stay rolled: this path is rare, and unrolled FP64 exp code would
-// raise the register count of the whole planning kernel.)
+// raise the register count of the whole planning kernel.)  The debug form
+// also writes each slot's weight over the largest weight of the reach set,
+// rounded to FP32 (every such ratio lies in [0, 1], so FP32 holds it whatever
+// the range of the weights themselves).
 template <int V, bool DEBUG>
 __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
 {
     const double Sc = s.S[gc];
     const double ks = s.k_s;
-    double C = 0.0;
+    double C = 0.0, wmax = 0.0;
 #pragma unroll 1
     for (int dy = -V; dy <= V; ++dy)
 #pragma unroll 1
@@ -125,11 +128,20 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
             if (reach_ok<V>(s, gc, t, dx, dy)) {
                 const double w = exp(ks * (Sc - s.S[t]));
                 C = C + w;
-                if (DEBUG && s.dbg_w)
-                    s.dbg_w[(size_t)id * (2 * V + 1) * (2 * V + 1) + (dy + V) * (2 * V + 1) + dx + V] =
-                        (float)w;
+                wmax = fmax(wmax, w);
             }
         }
+    if (DEBUG && s.dbg_w) {
+#pragma unroll 1
+        for (int dy = -V; dy <= V; ++dy)
+#pragma unroll 1
+            for (int dx = -V; dx <= V; ++dx) {
+                const int t = gc + dy * s.Wp + dx;
+                if (reach_ok<V>(s, gc, t, dx, dy))
+                    s.dbg_w[(size_t)id * (2 * V + 1) * (2 * V + 1) + (dy + V) * (2 * V + 1) + dx + V] =
+                        (float)(exp(ks * (Sc - s.S[t])) / wmax);
+            }
+    }
     const double tau = (double)u32 * C;
     double C2 = 0.0;
 #pragma unroll 1
@@ -678,16 +690,39 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             }
             const bool flag = near || (ks > 2 * as);
 
-            if (DEBUG) {
+            if constexpr (DEBUG) {
+                // weights over the largest weight of the reach set (the CDF
+                // depends on ratios only, and these all lie in [0, 1]); the
+                // FP32 CDF at every disc slot exactly as the draw forms it
+                // (row prefix Pr plus the sequential in-row sum), and the
+                // total W in the window's last slot, a corner outside the disc
+                float emax = ec;
+                for (int dy = -V; dy <= V; ++dy)
+                    for (int dx = -V; dx <= V; ++dx)
+                        if (dx * dx + dy * dy <= V * V && !(dx == 0 && dy == 0))
+                            emax = fmaxf(emax, sh.Em[l + dy * P + dx]);
                 if (s.dbg_w) {
                     float *wd = s.dbg_w + (size_t)id * SIDE * SIDE;
                     for (int dy = -V; dy <= V; ++dy)
                         for (int dx = -V; dx <= V; ++dx) {
                             float wv = 0.0f;
                             if (dx * dx + dy * dy <= V * V)
-                                wv = (dx == 0 && dy == 0) ? 1.0f : sh.Em[l + dy * P + dx] / ec;
+                                wv = ((dx == 0 && dy == 0) ? ec : sh.Em[l + dy * P + dx]) / emax;
                             wd[(dy + V) * SIDE + dx + V] = wv;
                         }
+                }
+                if (s.dbg_cdf) {
+                    float *cd = s.dbg_cdf + (size_t)id * SIDE * SIDE;
+                    for (int r = 0; r < SIDE; ++r) {
+                        const int a = (int)((row_half_widths(V) >> (4 * r)) & 15u);
+                        float q = 0.0f;
+                        for (int d = 0; d <= 2 * a; ++d) {
+                            const int dx = d - a, dy = r - V;
+                            q = q + ((dx == 0 && dy == 0) ? ec : sh.Em[l + dy * P + dx]);
+                            cd[r * SIDE + (V - a) + d] = Pr[r] + q;
+                        }
+                    }
+                    cd[SIDE * SIDE - 1] = Wsum;
                 }
                 if (s.dbg_flag) s.dbg_flag[id] = flag ? 1 : 0;
                 if (s.dbg_margin) s.dbg_margin[id] = margin / Wsum;

@@ -1274,7 +1274,8 @@ fast_status fast_get_stats(fast_ctx *c, int32_t h, fast_stats *out)
     return FAST_OK;
 }
 
-fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, float *margin)
+fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, float *margin,
+                            float *cdf32)
 {
     if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
     std::lock_guard<std::recursive_mutex> g(c->mu);
@@ -1285,25 +1286,29 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     const int n = std::max(s->n_agents, 1);
     const int side = 2 * s->dev.v + 1;
     const size_t bw = align_up((size_t)n * side * side * 4, 256), bf = align_up((size_t)n, 256),
-                 bm = (size_t)n * 4;
+                 bm = align_up((size_t)n * 4, 256), bc = (size_t)n * side * side * 4;
+    const size_t total = bw + bf + bm + bc;
     void *block = nullptr;
-    fast_status st = dev_alloc(c, bw + bf + bm, &block);
+    fast_status st = dev_alloc(c, total, &block);
     if (st) return st;
     fk::SlotDev sd = s->dev;
     sd.dbg_w = (float *)block;
     sd.dbg_flag = (uint8_t *)((char *)block + bw);
     sd.dbg_margin = (float *)((char *)block + bw + bf);
-    hipError_t e = hipMemsetAsync(block, 0, bw + bf + bm, c->stream);
+    sd.dbg_cdf = (float *)((char *)block + bw + bf + bm);
+    hipError_t e = hipMemsetAsync(block, 0, total, c->stream);
     if (e == hipSuccess) e = fk_launch_plan_one(&sd, s->n_items, 1, c->stream, nullptr, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) {
         s->planned = true;
         const int na = s->n_agents;
-        if (w32 && na) e = hipMemcpy(w32, sd.dbg_w, (size_t)na * side * side * 4, hipMemcpyDeviceToHost);
+        const size_t wb = (size_t)na * side * side * 4;
+        if (w32 && na) e = hipMemcpy(w32, sd.dbg_w, wb, hipMemcpyDeviceToHost);
         if (e == hipSuccess && flag && na) e = hipMemcpy(flag, sd.dbg_flag, (size_t)na, hipMemcpyDeviceToHost);
         if (e == hipSuccess && margin && na) e = hipMemcpy(margin, sd.dbg_margin, (size_t)na * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && cdf32 && na) e = hipMemcpy(cdf32, sd.dbg_cdf, wb, hipMemcpyDeviceToHost);
     }
-    dev_free(c, block, bw + bf + bm);
+    dev_free(c, block, total);
     if (e != hipSuccess) return fail(FAST_E_DEVICE, "debug plan: %s", hipGetErrorString(e));
     return FAST_OK;
 }

@@ -80,7 +80,7 @@ def lib() -> ctypes.CDLL:
         "fast_move_batch": [P, P, I32],
         "fast_get_state": [P, I32, P, P, P, P, P],
         "fast_get_stats": [P, I32, P],
-        "fast_debug_plan": [P, I32, P, P, P],
+        "fast_debug_plan": [P, I32, P, P, P, P],
         "fast_timing_start": [P, I32],
         "fast_timing_read": [P, P, I32, P],
         "fast_stream_bandwidth": [P, ctypes.c_size_t, I32, P, P],
@@ -212,10 +212,11 @@ def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, se
         af = np.ascontiguousarray(np.asarray(agent_field, dtype=np.uint8))
         if ef.shape != ct.shape or len(af) != d.n_agents:
             raise ValueError("exit_field needs the grid's shape, agent_field one entry per agent")
-        nf = int(ef[ct == 2].max()) + 1 if (ct == 2).any() else 1
-        if len(af):
-            nf = max(nf, int(af.max()) + 1)
-        d.n_fields = nf                  # one group is the single-field model
+        tags = np.union1d(np.unique(ef[ct == 2]), np.unique(af))
+        # one tag in use (whatever its value) is the single-field model;
+        # otherwise field g is the group tagged g
+        nf = int(tags.max()) + 1 if len(tags) > 1 else 1
+        d.n_fields = nf
         if nf >= 2:
             d.exit_field = _ptr(ef)
             d.agent_field = _ptr(af) if len(af) else None
@@ -347,14 +348,16 @@ class Context:
         return st.as_dict()
 
     def debug_plan(self, h: int):
+        """(w, flag, margin, cdf) of one debug planning phase (see fast.h)."""
         n, v = self.n_agents[h], self.v[h]
         side = 2 * v + 1
         m = max(n, 1)
         w = np.zeros((m, side * side), dtype=np.float32)
         flag = np.zeros(m, dtype=np.uint8)
         margin = np.zeros(m, dtype=np.float32)
-        _check(lib().fast_debug_plan(self.ctx, h, _ptr(w), _ptr(flag), _ptr(margin)))
-        return w[:n], flag[:n], margin[:n]
+        cdf = np.zeros((m, side * side), dtype=np.float32)
+        _check(lib().fast_debug_plan(self.ctx, h, _ptr(w), _ptr(flag), _ptr(margin), _ptr(cdf)))
+        return w[:n], flag[:n], margin[:n], cdf[:n]
 
     # -- kernel timing -----------------------------------------------------
     def timing_start(self, max_launches: int):

@@ -164,6 +164,13 @@ def test_descriptor_takes_floor_field_groups(fast):
     d, _ = fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=np.zeros_like(ef),
                           agent_field=np.zeros_like(af))
     assert d.n_fields == 1 and not d.exit_field and not d.agent_field
+    # one tag other than 0 on every exit and agent: still the single-field model
+    d, _ = fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=np.ones_like(ef),
+                          agent_field=np.ones_like(af))
+    assert d.n_fields == 1 and not d.exit_field and not d.agent_field
+    # two tags in use: field g is the group tagged g (group 0 must then have exits)
+    d, _ = fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=ef + 1, agent_field=af + 1)
+    assert d.n_fields == 3 and d.exit_field and d.agent_field
     with pytest.raises(ValueError):
         fast.make_desc(s.cell_type, s.n_agents, s.v, exit_field=ef)
     with pytest.raises(ValueError):

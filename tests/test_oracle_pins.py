@@ -537,12 +537,16 @@ def test_deterministic_runs():
     assert np.array_equal(a.occ, b.occ)
 
 
-def test_omp_plan_gives_same_draws():
-    s = sc.room(n_agents=3000, size=80)
+@pytest.mark.parametrize("n,threads", [(3000, 4), (3000, 7), (5, 16), (1, 3)])
+def test_threaded_plan_gives_same_draws(n, threads):
+    """The CPU baseline's threaded loop (chunks claimed from a counter) plans
+    every agent exactly once, with the serial loop's draws."""
+    s = sc.room(n_agents=n, size=80)
     a = oracle.Sim(s.cell_type, s.v, s.k_s, s.seed, s.scn, n_agents=s.n_agents)
     a.plan()
     d1 = a.desired.copy()
-    a.plan_omp(4)
+    a.desired[:] = -7
+    a.plan_threads(threads)
     assert np.array_equal(d1, a.desired)
 
 
