@@ -179,6 +179,25 @@ fast_status fast_move_step(fast_ctx *ctx, int32_t handle);
  * scenario keeps its own step counter.  n >= 1, steps >= 0. */
 fast_status fast_run(fast_ctx *ctx, const int32_t *handles, int32_t n, int32_t steps);
 
+/* For callers that cannot allocate device memory during the call: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same `steps` time steps of the n scenarios as fast_run, with the same
+ * results bit for bit, run as plain launches (one planning launch, one motion
+ * launch and, when a member has regions, one count launch per step) whose
+ * work items -- the planning launch's tile items, the motion launch's
+ * workgroup items, the region-count jobs -- live in the library's static
+ * device scratch instead of a per-batch allocation.  The call allocates no
+ * device memory: the items are built on the host into a pinned staging buffer
+ * the context set up at creation and copied into the scratch on the context
+ * stream.  Limit: the items must fit the scratch, 1 MiB per GPU (about
+ * 250,000 tiles over all members); larger batches return FAST_E_INVALID with
+ * the size they need.  Every call on one GPU uses that GPU's single scratch,
+ * which keeps the last call's items: calls from contexts on different streams
+ * of the same GPU that overlap in time race on it (calls on one context are
+ * ordered by its stream).  Errors as fast_run (FAST_E_STATE for a member
+ * planned without its motion phase). */
+fast_status fast_run_noalloc(fast_ctx *ctx, const int32_t *handles, int32_t n, int32_t steps);
+
 /* One planning phase of each of the n scenarios in a single launch over all
  * their tiles (the batched form of fast_plan_step).  The batched calls
  * (fast_run, fast_plan_batch, fast_move_batch) return FAST_E_INVALID for a

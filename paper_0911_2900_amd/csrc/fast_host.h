@@ -44,6 +44,12 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
 
 }  // namespace fh
 
+namespace fk {
+// Bytes of the static work-item scratch (scratch.hip) of the allocation-free
+// batched run: 1 MiB per GPU.
+constexpr size_t SCRATCH_BYTES = (size_t)1 << 20;
+}  // namespace fk
+
 // Batched planning: v, tx = the v_max and tile width shared by every item's
 // scenario (the specialised kernels), or 0, 0 for a mixed batch.
 extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *items, int n_items,
@@ -76,5 +82,6 @@ extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const uint8_t 
                                          hipEvent_t stop);
 extern "C" hipError_t fk_launch_count(const fk::RegionDev *jobs, int n_jobs, int max_regions,
                                       hipStream_t stream);
+extern "C" hipError_t fk_scratch_ptr(int device, void **out);
 extern "C" hipError_t fk_launch_stream(float4 *base, size_t n4, hipStream_t stream,
                                        hipEvent_t start, hipEvent_t stop);

@@ -92,6 +92,18 @@ struct Batch {
     std::vector<int32_t> members;
 };
 
+// The work items of a batch, built on the host: the planning launch's tile
+// items (the larger scenarios first, so their tiles start early on the
+// hardware queue; members with per-agent speeds are planned by launches of
+// their own), the motion launch's workgroup items, and the region-count jobs.
+struct BatchItems {
+    std::vector<int32_t> order;
+    std::vector<uint32_t> items, mitems;
+    std::vector<int32_t> het;
+    std::vector<fk::RegionDev> rj;
+    int v = 0, tx = 0, max_regions = 0;
+};
+
 struct Request {
     uint64_t ticket = 0;
     fast_scenario_desc desc{};
@@ -132,6 +144,14 @@ struct fast_ctx {
     std::map<std::vector<int32_t>, Batch> batches;
     std::vector<hipEvent_t> timing;  // kernel timing: start / stop pairs of plan launches
     int timing_used = 0;
+    // allocation-free batched runs (fast_run_noalloc): the device address of
+    // the library's static scratch on this context's device, a pinned host
+    // staging buffer of the same size (set up here, at creation), the event
+    // after which the staging buffer may be rewritten, and the item lists
+    void *scratch = nullptr;
+    void *stage = nullptr;
+    hipEvent_t staged = nullptr;
+    BatchItems nb;
     std::recursive_mutex mu;         // guards everything above
 
     // serving
@@ -550,53 +570,66 @@ fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_
     return FAST_OK;
 }
 
-fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
+fast_status batch_items(fast_ctx *c, const std::vector<int32_t> &hs, BatchItems &p)
 {
-    auto it = c->batches.find(hs);
-    if (it != c->batches.end()) { *out = &it->second; return FAST_OK; }
     for (int32_t h : hs)                              // items carry a 20-bit tile index
         if (c->slots[h].n_items > (1 << 20))
             return fail(FAST_E_INVALID, "scenario %d has %d tiles; batched launches take at most 2^20 "
                         "per scenario (choose a larger tile)", h, c->slots[h].n_items);
-    // work items: all tiles of all members; the larger scenarios first so
-    // their tiles start early on the hardware queue
-    std::vector<int32_t> order(hs);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    p.order.assign(hs.begin(), hs.end());
+    std::stable_sort(p.order.begin(), p.order.end(), [&](int32_t a, int32_t b) {
         return c->slots[a].n_agents > c->slots[b].n_agents;
     });
-    // members with per-agent speeds are planned by launches of their own
-    std::vector<uint32_t> items;
-    std::vector<int32_t> het;
-    for (int32_t h : order) {
+    p.items.clear();
+    p.het.clear();
+    for (int32_t h : p.order) {
         const Slot &s = c->slots[h];
-        if (s.het) { het.push_back(h); continue; }
-        for (int i = 0; i < s.n_items; ++i) items.push_back(((uint32_t)h << 20) | (uint32_t)i);
+        if (s.het) { p.het.push_back(h); continue; }
+        for (int i = 0; i < s.n_items; ++i) p.items.push_back(((uint32_t)h << 20) | (uint32_t)i);
     }
-    const std::vector<int> G = batch_groups(c, order);
-    std::vector<uint32_t> mitems;
-    for (size_t i = 0; i < order.size(); ++i)
+    const std::vector<int> G = batch_groups(c, p.order);
+    p.mitems.clear();
+    for (size_t i = 0; i < p.order.size(); ++i)
         for (int g = 0; g < G[i]; ++g)
-            mitems.push_back(motion_item(order[i], g, G[i], order.size() == 1));
-    Batch b;
-    b.members = hs;
-    b.het = het;
+            p.mitems.push_back(motion_item(p.order[i], g, G[i], p.order.size() == 1));
+    p.v = p.tx = 0;
     bool first = true;
-    for (int32_t h : order) {
+    for (int32_t h : p.order) {
         const Slot &s = c->slots[h];
         if (s.het) continue;
-        if (first) { b.v = s.dev.v; b.tx = s.dev.tx; first = false; }
-        else if (s.dev.v != b.v || s.dev.tx != b.tx) b.v = b.tx = 0;
+        if (first) { p.v = s.dev.v; p.tx = s.dev.tx; first = false; }
+        else if (s.dev.v != p.v || s.dev.tx != p.tx) p.v = p.tx = 0;
     }
-    std::vector<fk::RegionDev> rj;
-    for (int32_t h : order)
+    p.rj.clear();
+    p.max_regions = 0;
+    for (int32_t h : p.order)
         if (c->slots[h].n_regions) {
-            rj.push_back(c->slots[h].rhost);
-            b.max_regions = std::max(b.max_regions, c->slots[h].n_regions);
+            p.rj.push_back(c->slots[h].rhost);
+            p.max_regions = std::max(p.max_regions, c->slots[h].n_regions);
         }
+    return FAST_OK;
+}
+
+fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
+{
+    auto it = c->batches.find(hs);
+    if (it != c->batches.end()) { *out = &it->second; return FAST_OK; }
+    BatchItems p;
+    fast_status st = batch_items(c, hs, p);
+    if (st) return st;
+    const std::vector<int32_t> &order = p.order;
+    const std::vector<uint32_t> &items = p.items, &mitems = p.mitems;
+    const std::vector<fk::RegionDev> &rj = p.rj;
+    Batch b;
+    b.members = hs;
+    b.het = p.het;
+    b.v = p.v;
+    b.tx = p.tx;
+    b.max_regions = p.max_regions;
     const size_t ib = align_up(items.size() * 4, 256), mb = align_up(mitems.size() * 4, 256);
     const size_t ob = align_up(order.size() * 4, 256);
     b.bytes = ib + mb + ob + rj.size() * sizeof(fk::RegionDev);
-    fast_status st = dev_alloc(c, b.bytes, &b.block);
+    st = dev_alloc(c, b.bytes, &b.block);
     if (st) return st;
     b.items = (uint32_t *)b.block;
     b.mitems = (uint32_t *)((char *)b.block + ib);
@@ -622,9 +655,9 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
 }
 
 // The planning launches of a batch's members with per-agent speeds.
-hipError_t launch_het_members(fast_ctx *c, const Batch *b)
+hipError_t launch_het_members(fast_ctx *c, const std::vector<int32_t> &het)
 {
-    for (int32_t h : b->het) {
+    for (int32_t h : het) {
         const Slot &s = c->slots[h];
         const hipError_t e = fk_launch_plan_het(&s.dev, s.vi, s.fi, s.Sf, s.field_cells, s.n_items,
                                                 c->stream, nullptr, nullptr);
@@ -640,7 +673,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b)
     if (b->exec) return FAST_OK;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
-    if (e1 == hipSuccess) e1 = launch_het_members(c, b);
+    if (e1 == hipSuccess) e1 = launch_het_members(c, b->het);
     hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
     if (e2 == hipSuccess) e2 = fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
@@ -681,7 +714,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     if (st) return st;
     for (int k = 0; k < steps; ++k) {
         HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr));
-        HIP_TRY(launch_het_members(c, b));
+        HIP_TRY(launch_het_members(c, b->het));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
         HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream));
     }
@@ -922,10 +955,23 @@ fast_status fast_ctx_create(int device, void *hip_stream, size_t hbm_budget, fas
         return fail(FAST_E_DEVICE, "CU count of the stream: %s", hipGetErrorString(e));
     }
     c->move_capacity = per_cu * c->n_cus;
+    e = fk_scratch_ptr(device, &c->scratch);         // device current (hipSetDevice above)
+    if (e != hipSuccess) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        return fail(FAST_E_DEVICE, "address of the static scratch: %s", hipGetErrorString(e));
+    }
     e = hipMalloc(&c->table, sizeof(fk::SlotDev) * FAST_MAX_SLOTS);
     if (e != hipSuccess) {
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         return fail(FAST_E_NOMEM, "slot table: %s", hipGetErrorString(e));
+    }
+    e = hipHostMalloc(&c->stage, fk::SCRATCH_BYTES, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (c->stage) (void)hipHostFree(c->stage);
+        (void)hipFree(c->table);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        return fail(FAST_E_NOMEM, "staging buffer of the allocation-free run: %s", hipGetErrorString(e));
     }
     *out = c.release();
     return FAST_OK;
@@ -949,6 +995,8 @@ fast_status fast_ctx_destroy(fast_ctx *c)
         for (hipEvent_t e : c->timing) (void)hipEventDestroy(e);
         c->timing.clear();
         (void)hipFree(c->table);
+        (void)hipEventDestroy(c->staged);
+        (void)hipHostFree(c->stage);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
     delete c;
@@ -1077,6 +1125,49 @@ fast_status fast_run(fast_ctx *c, const int32_t *hs, int32_t n, int32_t steps)
     return run_batch(c, v, steps);
 }
 
+fast_status fast_run_noalloc(fast_ctx *c, const int32_t *hs, int32_t n, int32_t steps)
+{
+    if (!c || steps < 0) return fail(FAST_E_INVALID, "bad arguments to fast_run_noalloc");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    std::vector<int32_t> v;
+    fast_status st = check_handles(c, hs, n, v);
+    if (st) return st;
+    for (int32_t h : v)
+        if (c->slots[h].planned)
+            return fail(FAST_E_STATE, "scenario %d has a plan without its motion phase", h);
+    if (steps == 0) return FAST_OK;
+    BatchItems &p = c->nb;
+    st = batch_items(c, v, p);
+    if (st) return st;
+    // scratch layout: planning items | motion items | region-count jobs
+    const size_t ib = align_up(p.items.size() * 4, 256), mb = align_up(p.mitems.size() * 4, 256);
+    const size_t rb = p.rj.size() * sizeof(fk::RegionDev);
+    if (ib + mb + rb > fk::SCRATCH_BYTES)
+        return fail(FAST_E_INVALID, "the batch's work items take %zu bytes (%zu tiles, %zu motion "
+                    "workgroups, %zu region jobs); the allocation-free run holds at most %zu",
+                    ib + mb + rb, p.items.size(), p.mitems.size(), p.rj.size(),
+                    (size_t)fk::SCRATCH_BYTES);
+    // the previous call's copy out of the staging buffer has finished
+    HIP_TRY(hipEventSynchronize(c->staged));
+    char *stage = (char *)c->stage, *dev = (char *)c->scratch;
+    std::memcpy(stage, p.items.data(), p.items.size() * 4);
+    std::memcpy(stage + ib, p.mitems.data(), p.mitems.size() * 4);
+    if (rb) std::memcpy(stage + ib + mb, p.rj.data(), rb);
+    HIP_TRY(hipMemcpyAsync(dev, stage, ib + mb + rb, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipEventRecord(c->staged, c->stream));
+    const uint32_t *items = (const uint32_t *)dev, *mitems = (const uint32_t *)(dev + ib);
+    const fk::RegionDev *rjobs = rb ? (const fk::RegionDev *)(dev + ib + mb) : nullptr;
+    for (int k = 0; k < steps; ++k) {
+        HIP_TRY(fk_launch_plan(c->table, items, (int)p.items.size(), p.v, p.tx, c->stream, nullptr,
+                               nullptr));
+        HIP_TRY(launch_het_members(c, p.het));
+        HIP_TRY(fk_launch_move(c->table, mitems, (int)p.mitems.size(), c->stream));
+        HIP_TRY(fk_launch_count(rjobs, (int)p.rj.size(), p.max_regions, c->stream));
+    }
+    for (int32_t h : v) c->slots[h].host_steps += steps;
+    return FAST_OK;
+}
+
 fast_status fast_plan_batch(fast_ctx *c, const int32_t *hs, int32_t n)
 {
     if (!c) return fail(FAST_E_INVALID, "ctx is NULL");
@@ -1090,7 +1181,7 @@ fast_status fast_plan_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (b->n_items > 0) next_timing_pair(c, &e0, &e1);   // times the shared planning launch
     HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, e0, e1));
-    HIP_TRY(launch_het_members(c, b));
+    HIP_TRY(launch_het_members(c, b->het));
     for (int32_t h : v) c->slots[h].planned = true;
     return FAST_OK;
 }

@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
         "fast_plan_step": [P, I32],
         "fast_move_step": [P, I32],
         "fast_run": [P, P, I32, I32],
+        "fast_run_noalloc": [P, P, I32, I32],
         "fast_plan_batch": [P, P, I32],
         "fast_move_batch": [P, P, I32],
         "fast_get_state": [P, I32, P, P, P, P, P],
@@ -312,7 +313,12 @@ class Context:
         hs = np.ascontiguousarray(np.asarray(list(handles), dtype=np.int32))
         _check(lib().fast_run(self.ctx, _ptr(hs), len(hs), int(steps)))
 
+    def run_noalloc(self, handles, steps: int):
+        hs = np.ascontiguousarray(np.asarray(list(handles), dtype=np.int32))
+        _check(lib().fast_run_noalloc(self.ctx, _ptr(hs), len(hs), int(steps)))
+
     # -- region counts -----------------------------------------------------
+
     def set_regions(self, h: int, rects, max_step: int):
         """Rectangles (x0, y0, x1, y1), half-open, whose agent counts are
         recorded after every motion phase for steps 0 .. max_step."""
