@@ -212,7 +212,10 @@ fast_status fast_move_batch(fast_ctx *ctx, const int32_t *handles, int32_t n);
  * the last motion phase and the desired cells of the last planning phase
  * (Sec. 1's two phases).  Any pointer may be NULL.
  * xy: 2*n_agents (x, y), (-1, -1) for agents that left; alive: n_agents;
- * desired: n_agents cells y*width + x of the last plan (-1 when gone). */
+ * desired: n_agents cells y*width + x chosen by the last planning phase while
+ * its motion phase has not run yet (-1 for agents that left, and for every
+ * agent once that motion phase has run: the device keeps each plan only as
+ * the chosen window slot of the agent's start cell). */
 fast_status fast_get_state(fast_ctx *ctx, int32_t handle, int32_t *xy, uint8_t *alive,
                            int32_t *desired, int32_t *step, int32_t *n_active);
 

@@ -9,16 +9,19 @@
 //   padded height Hp = nty * ty + 2 pad,
 //   cell (x, y) of the scenario lives at index (y + pad) * Wp + (x + pad).
 // Per cell:  cell u8 (static: type and corner-cut bits, see cut_bit),
-//            G f32 (static exp table, see below), S f64 (static floor field,
-//            read only by the FP64 re-resolve), occ i32 (agent id or -1),
-//            res0/res1 u64 (motion reservations of even / odd rounds).
+//            D u32 (the exp table entry G(t) of the cell as FP32 bits, with
+//            bit 31 set while an agent stands on it: the planning phase's one
+//            per-cell read), S f64 (static floor field, read only by the FP64
+//            re-resolve), occ i32 (agent id or -1), res0/res1 u64 (motion
+//            reservations of even / odd rounds).
 // Per tile:  m i32 (power-of-two scale of the exp table), fallback u8, and the
-//            agents planned on the tile: a count and one record each (id,
-//            start, chosen cell; the chosen cell is the start when the agent
-//            stays), written by the planning kernel, read by the motion
-//            kernel; the motion rounds keep two mover lists.  Positions live
-//            only in occ (the host rebuilds per-agent arrays from occ and the
-//            records when asked).
+//            agents planned on the tile: a count and one 4-byte record each
+//            (the agent's cell inside the tile and the window slot it chose,
+//            see plan_rec), written by the planning kernel, read by the
+//            motion kernel, which finds the agent's id in occ; the motion
+//            rounds keep two mover lists.  Positions live only in occ (the
+//            host rebuilds per-agent arrays from occ and the records when
+//            asked).
 //
 // Exp table: G(t) = fl32(exp(m_T(t) ln 2 - k_S S(t))) where T(t) is the tile
 // holding t.  A tile T staging a halo cell t of tile T' rescales it by
@@ -45,7 +48,6 @@ constexpr int MAX_TILE_CELLS = 1024;   // tx * ty
 constexpr int MAX_STAGE = 2368;        // (tx + 2 pad) * (ty + 2v) over the allowed tiles
 constexpr int PLAN_THREADS = 256;
 constexpr int ONE_MAX_THREADS = 1024;     // single-scenario planning launches: up to one thread per tile cell
-constexpr int ONE_STAGE_S_TILES = 2048;   // ... and the floor field staged in LDS up to this many tiles
 constexpr int MOVE_THREADS = 1024;
 constexpr int MOVE_GROUP_MAX = 64;        // workgroups per scenario in the motion phase
 constexpr int GATHER_TILES_MAX = 4096;    // motion splits records evenly up to this many tiles
@@ -89,10 +91,18 @@ struct Mover {
 constexpr unsigned long long KEY_MASK = (1ull << 52) - 1ull;
 constexpr int MEFF_SHIFT = 52, HP_SHIFT = 55, EXIT_BIT = 60;
 
-// A planned agent: id and packed start / chosen cells (equal when it stays).
-struct MoveRec {
-    uint32_t id, cxy, dxy;
-};
+// A planned agent's record: bits 0..9 its cell inside the tile (row-major,
+// ly * tx + lx), bits 10..16 the slot of its (2 v_max + 1)^2 window that it
+// chose (raster order: (dy + v_max) * (2 v_max + 1) + dx + v_max; the middle
+// slot when it stays).  The agent's id is occ of that cell until the motion
+// phase runs.
+constexpr int REC_SLOT_SHIFT = 10;
+__host__ __device__ inline uint32_t plan_rec(int lcell, int slot)
+{
+    return (uint32_t)lcell | ((uint32_t)slot << REC_SLOT_SHIFT);
+}
+// Bit 31 of a D entry: the cell is occupied.
+constexpr uint32_t D_OCC = 0x80000000u;
 // uint64 statistics per slot
 enum : int { S_FLAGGED = 0, S_FALLBACK = 1, S_PLANNED = 2, S_NSTAT = 4 };
 
@@ -110,7 +120,7 @@ struct SlotDev {
     double near64;           // FP64 re-resolve: scanned prefixes this close to tau (relative
                              // to W) send the draw to the sequential sum
     const uint8_t *cell;     // Wp*Hp: type | corner-cut bits (see cut_bit)
-    const float *G;          // Wp*Hp
+    uint32_t *D;             // Wp*Hp: exp table bits | D_OCC while occupied
     const double *S;         // Wp*Hp
     const int32_t *tile_m;   // (ntx+2)*(nty+2), a ring of zeros around
     const uint8_t *tile_fb;  // ntx*nty
@@ -118,7 +128,7 @@ struct SlotDev {
     unsigned long long *res0;// Wp*Hp, reservations of even rounds
     unsigned long long *res1;// Wp*Hp, reservations of odd rounds
     int32_t *seg_cnt;        // ntx*nty: agents planned per tile
-    MoveRec *seg;            // ntx*nty*tx*ty: their records, tile by tile
+    uint32_t *seg;           // ntx*nty*tx*ty: their records (plan_rec), tile by tile
     Mover *mv_a, *mv_b;      // (ntx*nty + 2 MOVE_GROUP_MAX)*tx*ty each: movers of the current / next round
     Mover *hand;             // MOVE_GROUP_MAX*MOVE_SOLO_MAX: movers handed to workgroup 0
     int32_t *ctr;            // C_NCTR

@@ -291,11 +291,14 @@ __device__ int commit_list(const SlotDev &s, const unsigned long long *res, cons
         const bool gone = reached == me && me > 0 && ((mv.key >> EXIT_BIT) & 1ull);
         if (gone) {
             st_agent(&s.occ[c], -1);
+            atomicAnd(&s.D[c], ~D_OCC);
             atomicAdd(&s.ctr[C_EXITED], 1);
             atomicSub(&s.ctr[C_NACTIVE], 1);
         } else if (at != c) {
             st_agent(&s.occ[c], -1);
+            atomicAnd(&s.D[c], ~D_OCC);
             st_agent(&s.occ[at], id);
+            atomicOr(&s.D[at], D_OCC);
         }
     }
     __syncthreads();
@@ -387,18 +390,28 @@ __device__ __forceinline__ void block_scan(int *sh)
     __syncthreads();
 }
 
-// The mover of record rec (an agent's plan) with its priority word
-// [~x0:32][~id:20] (larger = earlier) and reach bits; false if it never
-// moves: an agent that stays, or a mover blocked at its first cell, is at
-// every other mover's turn still where it started, which is what they see
-// without it taking part.
+// The mover of record rec of tile `tile` (an agent's plan: its cell in the
+// tile and the window slot it chose) with its priority word [~x0:32][~id:20]
+// (larger = earlier) and reach bits; the id is the occupant of the start cell
+// (nothing has moved yet).  False if it never moves: an agent that stays, or
+// a mover blocked at its first cell, is at every other mover's turn still
+// where it started, which is what they see without it taking part.
 template <int V>
-__device__ __forceinline__ bool gather_one(const SlotDev &s, const MoveRec &rec, int step, Mover &mv)
+__device__ __forceinline__ bool gather_one(const SlotDev &s, uint32_t rec, int tile, int step, Mover &mv)
 {
-    if (rec.dxy == rec.cxy) return false;
-    mv.key = order_key(s, rec.id, step);
-    mv.cxy = rec.cxy;
-    mv.dxy = rec.dxy;
+    constexpr int SIDE = 2 * V + 1;
+    const int slot = (int)(rec >> REC_SLOT_SHIFT);
+    if (slot == V * SIDE + V) return false;
+    const int lc = (int)(rec & ((1u << REC_SLOT_SHIFT) - 1u));
+    const int tlog = __builtin_ctz((unsigned)s.tx);
+    const int tile_y = tile / s.ntx, tile_x = tile - tile_y * s.ntx;
+    const int cx = tile_x * s.tx + s.pad + (lc & (s.tx - 1));
+    const int cy = tile_y * s.ty + s.pad + (lc >> tlog);
+    const int dy = slot / SIDE - V, dx = slot - (dy + V) * SIDE - V;
+    const int id = s.occ[cy * s.Wp + cx];
+    mv.key = order_key(s, (uint32_t)id, step);
+    mv.cxy = (uint32_t)cx | ((uint32_t)cy << 16);
+    mv.dxy = (uint32_t)(cx + dx) | ((uint32_t)(cy + dy) << 16);
     mv.key |= line_reach<V>(s, mv, step);
     return mover_reach(mv.key) > 0;
 }
@@ -471,7 +484,8 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
                     if (sh_tp[mid] > i) b = mid; else a = mid + 1;
                 }
                 const int k = i - (a ? sh_tp[a - 1] : 0);
-                keep = gather_one<V>(s, s.seg[((long)c + (long)a * stride) * TC + k], step, mv);
+                const int tile = c + a * stride;
+                keep = gather_one<V>(s, s.seg[(long)tile * TC + k], tile, step, mv);
             }
             append_kept(cur, n, keep, mv, &sh_kept);
         }
@@ -500,7 +514,8 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
                         if (sh_scan[mid] > i) b = mid; else a = mid + 1;
                     }
                     const int k = i - (a ? sh_scan[a - 1] : 0);
-                    keep = gather_one<V>(s, s.seg[((long)t0 + j0 + a) * TC + k], step, mv);
+                    const int tile = t0 + j0 + a;
+                    keep = gather_one<V>(s, s.seg[(long)tile * TC + k], tile, step, mv);
                 }
                 append_kept(cur, n, keep, mv, &sh_kept);
             }

@@ -15,9 +15,9 @@ namespace fk {
 __global__ __launch_bounds__(PLAN_THREADS) __attribute__((amdgpu_waves_per_eu(7)))
 void plan_kernel(const SlotDev *__restrict__ table, const uint32_t *__restrict__ items)
 {
-    __shared__ PlanShared<false> sh;
+    __shared__ PlanShared sh;
     const uint32_t it = items[blockIdx.x];
-    plan_dispatch<false, false>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
+    plan_dispatch<false>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
 }
 
 }  // namespace fk

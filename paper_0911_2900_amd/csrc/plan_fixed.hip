@@ -32,18 +32,17 @@ template <int V, int TX>
 __global__ __launch_bounds__(PLAN_THREADS) __attribute__((amdgpu_waves_per_eu(FIXED_WAVES)))
 void plan_kernel_fixed(const SlotDev *__restrict__ table, const uint32_t *__restrict__ items)
 {
-    __shared__ PlanShared<false> sh;
+    __shared__ PlanShared sh;
     const uint32_t it = items[blockIdx.x];
-    plan_tile<V, TX, false, false>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
+    plan_tile<V, TX, false>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
 }
 
-// One scenario, descriptor by value, workgroup i plans tile i (SS: the floor
-// field window is staged in LDS too).
-template <int V, int TX, bool SS>
+// One scenario, descriptor by value, workgroup i plans tile i.
+template <int V, int TX>
 __global__ __launch_bounds__(ONE_MAX_THREADS) void plan_kernel_one_fixed(const SlotDev s)
 {
-    __shared__ PlanShared<SS> sh;
-    plan_tile<V, TX, false, SS>(s, (int)blockIdx.x, sh);
+    __shared__ PlanShared sh;
+    plan_tile<V, TX, false>(s, (int)blockIdx.x, sh);
 }
 
 }  // namespace fk
@@ -66,44 +65,24 @@ extern "C" hipError_t FK_CAT(fk_launch_plan_fixed_v, PLAN_V)(int tx, const fk::S
     return hipGetLastError();
 }
 
-namespace {
-
-template <int TX>
-void launch_one_v(bool ss, dim3 grid, dim3 block, hipStream_t stream, hipEvent_t start,
-                hipEvent_t stop, const fk::SlotDev &s)
-{
-    if (ss)
-        hipExtLaunchKernelGGL((fk::plan_kernel_one_fixed<PLAN_V, TX, true>), grid, block, 0, stream, start,
-                              stop, 0, s);
-    else
-        hipExtLaunchKernelGGL((fk::plan_kernel_one_fixed<PLAN_V, TX, false>), grid, block, 0, stream, start,
-                              stop, 0, s);
-}
-
-}  // namespace
-
 // Single-scenario launch.  A scenario of a few hundred tiles cannot fill the
-// device, so its launch lasts as long as its slowest tile: up to
-// ONE_STAGE_S_TILES tiles it takes one thread per tile cell (256 .. 1,024; a
-// crowded tile needs one pass over its agents) and stages the floor field, so
-// the rare FP64 re-resolve reads LDS only; larger scenarios take 256 threads
-// and read the floor field from global memory.
+// device, so its launch lasts as long as its slowest tile: it takes one thread
+// per tile cell (256 .. 1,024), so that a crowded tile needs one pass over its
+// agents.
 extern "C" hipError_t FK_CAT(fk_launch_plan_one_fixed_v, PLAN_V)(const fk::SlotDev *slot,
                                                                   int n_tiles, hipStream_t stream,
                                                                   hipEvent_t start, hipEvent_t stop)
 {
     if (n_tiles <= 0) return hipSuccess;
-    const bool ss = n_tiles <= fk::ONE_STAGE_S_TILES;
     const int cells = slot->tx * slot->ty;
-    const int threads = !ss ? fk::PLAN_THREADS
-                        : cells < fk::PLAN_THREADS ? fk::PLAN_THREADS
+    const int threads = cells < fk::PLAN_THREADS ? fk::PLAN_THREADS
                         : cells > fk::ONE_MAX_THREADS ? fk::ONE_MAX_THREADS : cells;
     const dim3 grid(n_tiles), block(threads);
     switch (slot->tx) {
-        case 8: launch_one_v<8>(ss, grid, block, stream, start, stop, *slot); break;
-        case 16: launch_one_v<16>(ss, grid, block, stream, start, stop, *slot); break;
-        case 32: launch_one_v<32>(ss, grid, block, stream, start, stop, *slot); break;
-        case 64: launch_one_v<64>(ss, grid, block, stream, start, stop, *slot); break;
+        case 8: hipExtLaunchKernelGGL((fk::plan_kernel_one_fixed<PLAN_V, 8>), grid, block, 0, stream, start, stop, 0, *slot); break;
+        case 16: hipExtLaunchKernelGGL((fk::plan_kernel_one_fixed<PLAN_V, 16>), grid, block, 0, stream, start, stop, 0, *slot); break;
+        case 32: hipExtLaunchKernelGGL((fk::plan_kernel_one_fixed<PLAN_V, 32>), grid, block, 0, stream, start, stop, 0, *slot); break;
+        case 64: hipExtLaunchKernelGGL((fk::plan_kernel_one_fixed<PLAN_V, 64>), grid, block, 0, stream, start, stop, 0, *slot); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -26,7 +26,7 @@ namespace fk {
 // (1e-12 W) of tau every comparison tau < C_j, and with it the choice, is the
 // sequential sum's; otherwise the prefix is rebuilt strictly sequentially,
 // slot by slot (slots outside the reach set add exactly nothing).  Every lane
-// returns the chosen padded cell.
+// returns the chosen raster slot of the window.
 template <int V>
 __device__ int draw_het_wave(const SlotDev &s, const double *__restrict__ S, int gc, float u32,
                              int lane, int vr)
@@ -83,7 +83,7 @@ __device__ int draw_het_wave(const SlotDev &s, const double *__restrict__ S, int
     int jw = (NS - 1) / 2;                                    // own cell if unreached
     if (m[0]) jw = __builtin_ctzll(m[0]);
     else if (NH == 2 && m[NH - 1]) jw = 64 + __builtin_ctzll(m[NH - 1]);
-    return gc + (jw / SIDE - V) * s.Wp + (jw % SIDE - V);
+    return jw;
 }
 
 // Workgroup i plans tile i with HET_THREADS threads; wavefront q draws the
@@ -101,44 +101,35 @@ __global__ __launch_bounds__(HET_THREADS) void plan_kernel_het(const SlotDev s,
                                                                const double *__restrict__ Sf,
                                                                long field_cells)
 {
-    __shared__ PlanShared<false> sh;
+    __shared__ PlanShared sh;
     using T = TileGeom<V, TX>;
     constexpr int P = T::P;
     const int tile = (int)blockIdx.x;
-    const int step = s.ctr[C_STEP];
-    const int limit = s.ctr[C_LIMIT];
     const T tg(s, tile);
-    StageRegs<false> r;
-    stage_issue<V, TX, false>(s, tg, r);
-    if (step >= limit) return;                                // scenario finished
+    int step = 0;
+    if (!stage_tile<V, TX>(s, tg, tile, sh.Em, sh.L, step)) return;   // lists the tile's agents
     if (tile == 0 && threadIdx.x < 4) s.ctr[C_BAR + threadIdx.x] = 0;   // fresh motion barriers
-    stage_commit<V, TX, false>(s, tg, sh, r);                 // lists the tile's agents
-    MoveRec *seg = s.seg + (long)tile * (TX * s.ty);
-    const int na = sh.n_agents;
+    uint32_t *seg = s.seg + (long)tile * (TX * tg.ty);
+    const int na = sh.L.n_agents;
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     const int nw = (int)(blockDim.x >> 6);
     for (int k = wave; k < na; k += nw) {
-        const int id = (int)(sh.a_pk[k] >> 12);
-        const int l = (int)(sh.a_pk[k] & 0xFFFu);
-        const int ly = l / P;
-        const int cx = tg.gx0 + (l - ly * P), cy = tg.gy0 + ly;
-        const int gc = cy * s.Wp + cx;
+        const int id = (int)(sh.L.a_pk[k] >> 12);
+        const int l = (int)(sh.L.a_pk[k] & 0xFFFu);
+        const int ly = l / P, lx = l - ly * P;
+        const int gc = (tg.gy0 + ly) * s.Wp + tg.gx0 + lx;
         const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, s.scn, s.seed_lo, s.seed_hi);
         const float u = (float)(x0 >> 8) * 0x1p-24f;
-        int t;
+        int slot;
         if constexpr (FIELDS) {
             // the whole wavefront draws agent k, so its field is uniform
             const int f = __builtin_amdgcn_readfirstlane((int)fi[id]);
             const int vr = vi ? (int)vi[id] : V;
-            t = draw_het_wave<V>(s, Sf + (long)f * field_cells, gc, u, lane, vr);
+            slot = draw_het_wave<V>(s, Sf + (long)f * field_cells, gc, u, lane, vr);
         } else {
-            t = draw_het_wave<V>(s, s.S, gc, u, lane, (int)vi[id]);
+            slot = draw_het_wave<V>(s, s.S, gc, u, lane, (int)vi[id]);
         }
-        if (lane == 0) {
-            const int d = t - gc;                               // |dx|, |dy| <= V < Wp / 2
-            const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
-            gstore_rec(seg + k, (uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy));
-        }
+        if (lane == 0) seg[k] = plan_rec((ly - V) * TX + (lx - T::Hc), slot);
     }
     if (threadIdx.x == 0) {
         s.seg_cnt[tile] = na;

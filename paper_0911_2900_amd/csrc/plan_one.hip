@@ -11,8 +11,8 @@ namespace fk {
 
 __global__ __launch_bounds__(PLAN_THREADS) void plan_kernel_debug(const SlotDev s)
 {
-    __shared__ PlanShared<false> sh;
-    plan_dispatch<true, false>(s, (int)blockIdx.x, sh);
+    __shared__ PlanShared sh;
+    plan_dispatch<true>(s, (int)blockIdx.x, sh);
 }
 
 }  // namespace fk

@@ -117,6 +117,7 @@ __device__ __forceinline__ bool reach_ok(const SlotDev &s, int gc, int t, int dx
 template <int V, bool DEBUG>
 __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
 {
+    constexpr int SIDE = 2 * V + 1;
     const double Sc = s.S[gc];
     const double ks = s.k_s;
     double C = 0.0, wmax = 0.0;
@@ -138,7 +139,7 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
             for (int dx = -V; dx <= V; ++dx) {
                 const int t = gc + dy * s.Wp + dx;
                 if (reach_ok<V>(s, gc, t, dx, dy))
-                    s.dbg_w[(size_t)id * (2 * V + 1) * (2 * V + 1) + (dy + V) * (2 * V + 1) + dx + V] =
+                    s.dbg_w[(size_t)id * SIDE * SIDE + (dy + V) * SIDE + dx + V] =
                         (float)(exp(ks * (Sc - s.S[t])) / wmax);
             }
     }
@@ -151,10 +152,10 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
             const int t = gc + dy * s.Wp + dx;
             if (reach_ok<V>(s, gc, t, dx, dy)) {
                 C2 = C2 + exp(ks * (Sc - s.S[t]));
-                if (tau < C2) return t;
+                if (tau < C2) return (dy + V) * SIDE + dx + V;
             }
         }
-    return gc;   // not reached: the own cell has weight 1 and tau < W
+    return V * SIDE + V;   // not reached: the own cell has weight 1 and tau < W
 }
 
 // Half widths of the disc's rows, 4 bits per row, row 0 (dy = -V) lowest.
@@ -234,18 +235,21 @@ __device__ __forceinline__ double lane_value(double x, int j)
 //
 // Reachability is read from the tile's staged window (Em, agent cell l, pitch
 // P): on a fast tile a cell is zero there exactly when it is a wall, padding
-// or occupied, so only the floor field needs reads: from LDS with SS (Sw, the
-// same layout as Em), else from global memory.
-template <int V, bool SS>
+// or occupied, so only the floor field is read, from global memory (the draws
+// that come here are rare).  Returns the chosen raster slot of the window.
+template <int V>
 __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, const float *Em,
-                              const double *Sw, int l, int P)
+                              int l, int P)
 {
+    // The lane index passes through an empty asm here, inside the rare branch
+    // that calls this: otherwise the compiler hoists the lane-dependent set-up
+    // below (slot decoding, one compare per slot) out of the agent loop, and
+    // every wavefront pays for it whether or not it has a flagged draw.
+    asm volatile("" : "+v"(lane));
+    constexpr int SIDE = 2 * V + 1;
     const double NEAR = s.near64;
-    auto S_at = [&](int dx, int dy) -> double {
-        if constexpr (SS) return Sw[l + dy * P + dx];
-        else return s.S[gc + dy * s.Wp + dx];
-    };
-    const double Sc = S_at(0, 0);
+    const double *__restrict__ S = s.S;
+    const double Sc = S[gc];
     const double ks = s.k_s;
     const double u = (double)u32;
     if constexpr (disc_count(V) <= 64) {
@@ -254,7 +258,7 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
         int dx = 0, dy = 0;
         disc_slot<V>(lane, dx, dy);
         if (lane < ND && ((dx == 0 && dy == 0) || Em[l + dy * P + dx] != 0.0f))
-            w = exp(ks * (Sc - S_at(dx, dy)));
+            w = exp(ks * (Sc - S[gc + dy * s.Wp + dx]));
         const double Cp = wave_scan64(w);
         const double Wp = lane_value(Cp, ND - 1);
         const double tp = u * Wp;
@@ -275,9 +279,8 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
         const int jw = m ? __builtin_ctzll(m) : (ND - 1) / 2;   // own cell if unreached
         int wx, wy;
         disc_slot<V>(jw, wx, wy);
-        return gc + wy * s.Wp + wx;
+        return (wy + V) * SIDE + wx + V;
     } else {
-        constexpr int SIDE = 2 * V + 1;
         constexpr int NS = SIDE * SIDE;           // 121
         double w[2] = {0.0, 0.0};
 #pragma unroll
@@ -287,7 +290,7 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
                 const int dy = j / SIDE - V, dx = j % SIDE - V;
                 const bool own = dx == 0 && dy == 0;
                 if (dx * dx + dy * dy <= V * V && (own || Em[l + dy * P + dx] != 0.0f))
-                    w[h] = exp(ks * (Sc - S_at(dx, dy)));
+                    w[h] = exp(ks * (Sc - S[gc + dy * s.Wp + dx]));
             }
         }
         const double C0 = wave_scan64(w[0]);
@@ -311,32 +314,26 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
             m0 = __ballot(tau < myC0);
             m1 = __ballot(in1 && tau < myC1);
         }
-        int j;
-        if (m0) j = __builtin_ctzll(m0);
-        else if (m1) j = 64 + __builtin_ctzll(m1);
-        else j = V * SIDE + V;                   // not reached
-        return gc + (j / SIDE - V) * s.Wp + (j % SIDE - V);
+        if (m0) return __builtin_ctzll(m0);
+        if (m1) return 64 + __builtin_ctzll(m1);
+        return V * SIDE + V;                     // not reached
     }
 }
 
 // ---------------------------------------------------------------------------
 // Planning kernel.
 // ---------------------------------------------------------------------------
-struct PlanSharedBase {
-    alignas(16) float Em[MAX_STAGE];    // masked exp table window, pitch P = tx + 2 round4(v)
+// A staged tile's agent list and bookkeeping (LDS).
+struct TileLists {
     uint32_t a_pk[MAX_TILE_CELLS];      // agents of the tile: id << 12 | LDS cell (id < 2^20)
     float a_ec[MAX_TILE_CELLS];         // e_c of their own cell
-    int32_t m_nb[9];
-    int n_agents, n_flag;
+    int32_t m_nb[9];                    // exponents of the 3 x 3 tiles around it
+    int n_agents, n_flag, fb;
 };
-template <bool SS>
-struct PlanShared : PlanSharedBase {};
-template <>
-struct PlanShared<true> : PlanSharedBase {
-    alignas(16) double Sw[MAX_STAGE];   // floor-field window, same layout as Em
+struct PlanShared {
+    alignas(16) float Em[MAX_STAGE];    // masked exp table window, pitch P = tx + 2 round4(v)
+    TileLists L;
 };
-
-__device__ __forceinline__ uint32_t pack_xy(int x, int y) { return (uint32_t)x | ((uint32_t)y << 16); }
 
 __device__ __forceinline__ int lanes_below(unsigned long long mask)
 {
@@ -357,10 +354,11 @@ __device__ __forceinline__ uint32_t plan_draw_word(uint32_t id, uint32_t step, u
     return philox_word0(id, step, scn, STREAM_PLAN, k0, k1);
 }
 
-// Geometry of one tile's staging: tile (tile_x, tile_y), the padded origin of
-// its window, and the 16-byte chunks of the window this thread stages (one
-// interior chunk, up to two halo chunks: V rows above and below, then hc4
-// chunks left and right of the interior).
+// Geometry of one tile's window: (TX + 2 Hc) x (ty + 2V) cells in 4-cell
+// chunks, chunk j = row * cpr + cc (row-major), so that chunk j sits at LDS
+// float 4j of the window's table.  The tile's own cells are rows V .. V+ty-1,
+// chunk columns hc4 .. hc4+cw-1; interior chunk i (row-major over the tile,
+// cw per row) is window chunk in_chunk(i).
 template <int V, int TX>
 struct TileGeom {
     static constexpr int SIDE = 2 * V + 1;
@@ -370,41 +368,43 @@ struct TileGeom {
     static constexpr int hc4 = Hc >> 2;
     static constexpr int cw = TX >> 2;                        // interior chunks per row
     static constexpr int cw_log = __builtin_ctz(cw);
-    int n_in, n_top, n_halo, tile_x, tile_y, gx0, gy0, ly_in, cc_in, ly_h[2], cc_h[2];
+    int ty, tile_x, tile_y, gx0, gy0, n_win, n_in, n_halo;
 
     __device__ __forceinline__ TileGeom(const SlotDev &s, int tile)
     {
-        const int tid = threadIdx.x, nthr = blockDim.x;
-        n_in = cw * s.ty;                                     // interior chunks (<= nthr)
-        n_top = V * cpr;
-        n_halo = 2 * n_top + s.ty * 2 * hc4;
+        ty = s.ty;
         tile_y = tile / s.ntx;
         tile_x = tile - tile_y * s.ntx;
-        gx0 = tile_x * TX;
-        gy0 = tile_y * s.ty + Hc - V;
-        ly_in = V + (tid >> cw_log);
-        cc_in = hc4 + (tid & (cw - 1));
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int h = tid + j * nthr;
-            int ly, cc;
-            if (h < 2 * n_top) {                              // rows above, then rows below
-                const int hh = h < n_top ? h : h - n_top;
-                ly = (int)((unsigned)hh / cpr);
-                cc = hh - ly * cpr;
-                if (h >= n_top) ly += V + s.ty;
-            } else {                                          // left / right columns
-                const int hh = h - 2 * n_top;
-                const int rr = (int)((unsigned)hh / (2 * hc4));
-                const int c = hh - rr * 2 * hc4;
-                ly = V + rr;
-                cc = c < hc4 ? c : c + cw;
-            }
-            ly_h[j] = ly;
-            cc_h[j] = cc;
-        }
+        gx0 = tile_x * TX;                                    // padded column of window column 0
+        gy0 = tile_y * ty + Hc - V;                           // padded row of window row 0
+        n_win = cpr * (ty + 2 * V);
+        n_in = cw * ty;                                       // <= 256
+        n_halo = n_win - n_in;
+    }
+    static __device__ __forceinline__ int in_chunk(int i)
+    {
+        return (V + (i >> cw_log)) * cpr + hc4 + (i & (cw - 1));
+    }
+    // halo chunk h: the V rows above, the V rows below, then the hc4 chunks
+    // left and right of each interior row
+    __device__ __forceinline__ int halo_chunk(int h) const
+    {
+        constexpr int n_top = V * cpr;
+        if (h < 2 * n_top) return h < n_top ? h : h + ty * cpr;
+        const int hh = h - 2 * n_top;
+        const int rr = (int)((unsigned)hh / (2 * hc4));
+        const int c = hh - rr * 2 * hc4;
+        return (V + rr) * cpr + (c < hc4 ? c : c + cw);
     }
 };
+
+// A buffer resource over `bytes` bytes from p, for loads that go straight to
+// LDS (gfx950: buffer_load_dwordx4 ... lds).  Loads past `bytes` read zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t lds_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
 // A load through a global (not generic) address: the access is a global_load,
 // counted by vmcnt only, so waits for LDS results do not also wait for it.
@@ -413,186 +413,169 @@ __device__ __forceinline__ T gload(const T *p)
 {
     return *(const __attribute__((address_space(1))) T *)p;
 }
-// 16-byte forms (through the native vector types: the HIP vector classes
-// cannot be copied out of another address space).
 __device__ __forceinline__ int4 gload_i4(const int32_t *p)
 {
     typedef int v4 __attribute__((ext_vector_type(4)));
     const v4 v = *(const __attribute__((address_space(1))) v4 *)p;
     return make_int4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ float4 gload_f4(const float *p)
-{
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    const v4 v = *(const __attribute__((address_space(1))) v4 *)p;
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ double2 gload_d2(const double *p)
-{
-    typedef double v2 __attribute__((ext_vector_type(2)));
-    const v2 v = *(const __attribute__((address_space(1))) v2 *)p;
-    return double2{v.x, v.y};
-}
-// A planned record, stored through a global address.
-__device__ __forceinline__ void gstore_rec(MoveRec *p, uint32_t id, uint32_t cxy, uint32_t dxy)
-{
-    typedef uint32_t v3 __attribute__((ext_vector_type(3)));
-    v3 v;
-    v.x = id;
-    v.y = cxy;
-    v.z = dxy;
-    *(__attribute__((address_space(1))) v3 *)p = v;
-}
+__device__ __forceinline__ float fmask(uint32_t d) { return fmaxf(__uint_as_float(d), 0.0f); }
 
-// What a thread loads from global memory to stage one tile.
-template <bool SS>
+// What a thread loads into registers to stage a tile: its interior chunk of
+// occupancy (agent ids), and for threads 0..8 / 9 a neighbour tile's exponent
+// / the fallback flag.
 struct StageRegs {
-    int4 o_in, o_h0, o_h1;
-    float4 g_in, g_h0, g_h1;
-    double4 s_in, s_h0, s_h1;                                 // floor field (SS only)
-    int mnb;                                                  // scale exponent of a neighbour tile
-    int fb;                                                   // the tile is a fallback tile
+    int4 oc;
+    int mnb, fb;
 };
 
-// Issues every global load of a tile's staging (16-byte chunks of occupancy,
-// exp table and, with SS, floor field; the 3x3 tile scale exponents; the
-// fallback flag) without waiting for any of them.
-template <int V, int TX, bool SS>
-__device__ __forceinline__ void stage_issue(const SlotDev &s, const TileGeom<V, TX> &tg,
-                                            StageRegs<SS> &r)
-{
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int tstride = s.ntx + 2;
-    const int *tm = &s.tile_m[(tg.tile_y + tid / 3) * tstride + tg.tile_x + tid % 3];
-    const uint8_t *tf = &s.tile_fb[tg.tile_y * s.ntx + tg.tile_x];
-    r.mnb = tid < 9 ? (SS ? *tm : gload(tm)) : 0;
-    r.fb = SS ? *tf : gload(tf);
-    r.o_in = r.o_h0 = r.o_h1 = make_int4(-1, -1, -1, -1);
-    r.g_in = r.g_h0 = r.g_h1 = make_float4(0.f, 0.f, 0.f, 0.f);
-    // Launches that stage the floor field (single scenarios, descriptor by
-    // value: the compiler already knows the arrays are global) use plain
-    // loads; the others read descriptors from memory, where plain loads would
-    // be generic (flat) ones, counted against the LDS wait counter too.
-    auto load = [&](int g, int4 &o, float4 &gv, double4 &d) {
-        if constexpr (SS) {
-            o = *(const int4 *)(s.occ + g);
-            gv = *(const float4 *)(s.G + g);
-            const double2 x = *(const double2 *)(s.S + g), y = *(const double2 *)(s.S + g + 2);
-            d = double4{x.x, x.y, y.x, y.y};
-        } else {
-            o = gload_i4(s.occ + g);
-            gv = gload_f4(s.G + g);
-        }
-    };
-    if (tid < tg.n_in) load((tg.gy0 + tg.ly_in) * s.Wp + tg.gx0 + 4 * tg.cc_in, r.o_in, r.g_in, r.s_in);
-    if (tid < tg.n_halo)
-        load((tg.gy0 + tg.ly_h[0]) * s.Wp + tg.gx0 + 4 * tg.cc_h[0], r.o_h0, r.g_h0, r.s_h0);
-    if (tid + nthr < tg.n_halo)
-        load((tg.gy0 + tg.ly_h[1]) * s.Wp + tg.gx0 + 4 * tg.cc_h[1], r.o_h1, r.g_h1, r.s_h1);
-}
-
-// Writes the staged tile into LDS (halo chunks rescaled to the tile's
-// exponent, occupied cells masked) and lists the tile's agents.  Only thread 0
-// may have touched the LDS counters since the workgroup's last barrier.
-template <int V, int TX, bool SS>
-__device__ __forceinline__ void stage_commit(const SlotDev &s, const TileGeom<V, TX> &tg,
-                                             PlanShared<SS> &sh, const StageRegs<SS> &r)
+// Issues every load of tile `tile`'s staging without waiting for any: the
+// window of D goes straight from memory into the LDS table Em (one 16-byte
+// chunk per lane, no registers), the rest into registers.
+template <int V, int TX>
+__device__ __forceinline__ void stage_issue(const SlotDev &s, const TileGeom<V, TX> &tg, int tile,
+                                            float *Em, StageRegs &r)
 {
     using T = TileGeom<V, TX>;
-    constexpr int P = T::P, hc4 = T::hc4, cw = T::cw;
+    constexpr int cpr = T::cpr;
     const int tid = threadIdx.x, nthr = blockDim.x, lane = __lane_id();
-    const int ci = tid, n_in = tg.n_in, n_halo = tg.n_halo, ly_in = tg.ly_in, cc_in = tg.cc_in;
-    const int *ly_h = tg.ly_h, *cc_h = tg.cc_h;
-    if (tid < 9) sh.m_nb[tid] = r.mnb;
-    if (tid == 0) { sh.n_agents = 0; sh.n_flag = 0; }
-    __syncthreads();                                          // m_nb, counters ready
-    const int mT = sh.m_nb[4];
-
-    // halo chunks: rescale to this tile's exponent, mask occupied cells
-    auto stage_S = [&](int l0, const double4 &d) {
-        if constexpr (SS) {
-            *(double2 *)&sh.Sw[l0] = double2{d.x, d.y};
-            *(double2 *)&sh.Sw[l0 + 2] = double2{d.z, d.w};
+    const int wbase = tid - lane;
+    const int Wp = s.Wp;
+    const int base = tg.gy0 * Wp + tg.gx0;                    // padded cell of window (0, 0)
+    const __amdgpu_buffer_rsrc_t rD = lds_rsrc(s.D, (uint32_t)((size_t)Wp * s.Hp * 4));
+    for (int j0 = 0; j0 < tg.n_win; j0 += nthr) {
+        const int j = j0 + tid;
+        if (j < tg.n_win) {
+            const int row = (int)((unsigned)j / cpr), cc = j - row * cpr;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rD, (lds_ptr_t)(&Em[4 * (j0 + wbase)]), 16, (uint32_t)(base + row * Wp + 4 * cc) * 4u,
+                0, 0, 0);
         }
-    };
-    auto stage_halo = [&](int ly, int cc, int4 o, float4 gv) {
-        const int nby = (ly >= V) + (ly >= V + s.ty);
-        const int nbx = (cc >= hc4) + (cc >= hc4 + cw);       // a chunk lies inside one tile column
-        const int dm = mT - sh.m_nb[nby * 3 + nbx];
-        *(float4 *)&sh.Em[ly * P + 4 * cc] =
-            make_float4(o.x < 0 ? ldexpf(gv.x, dm) : 0.f, o.y < 0 ? ldexpf(gv.y, dm) : 0.f,
-                        o.z < 0 ? ldexpf(gv.z, dm) : 0.f, o.w < 0 ? ldexpf(gv.w, dm) : 0.f);
-    };
-    if (tid < n_halo) {
-        stage_halo(ly_h[0], cc_h[0], r.o_h0, r.g_h0);
-        stage_S(ly_h[0] * P + 4 * cc_h[0], r.s_h0);
     }
-    if (tid + nthr < n_halo) {
-        stage_halo(ly_h[1], cc_h[1], r.o_h1, r.g_h1);
-        stage_S(ly_h[1] * P + 4 * cc_h[1], r.s_h1);
-    }
+    r.oc = make_int4(-1, -1, -1, -1);
+    if (tid < tg.n_in)
+        r.oc = gload_i4(s.occ + base + (V + (tid >> T::cw_log)) * Wp + T::Hc + 4 * (tid & (T::cw - 1)));
+    const int tstride = s.ntx + 2;
+    r.mnb = 0;
+    r.fb = 0;
+    if (tid < 9) r.mnb = gload(&s.tile_m[(tg.tile_y + tid / 3) * tstride + tg.tile_x + tid % 3]);
+    if (tid == 9) r.fb = gload(&s.tile_fb[tile]);
+}
 
-    // interior chunk: already in the tile's scale; its occupied cells are the
-    // tile's agents (one LDS atomic per wavefront to list them)
+// Turns a tile's loaded window into table values in place -- occupied cells
+// (bit 31 set, a negative float) become 0, halo chunks are rescaled by
+// 2^(m_T - m_T') to this tile's exponent -- and lists the tile's agents with
+// their id and own-cell value.  Every load of the tile's stage_issue must
+// have completed.  Ends with a workgroup barrier.
+template <int V, int TX>
+__device__ __forceinline__ void stage_commit(const TileGeom<V, TX> &tg, float *Em, TileLists &L,
+                                             const StageRegs &r)
+{
+    using T = TileGeom<V, TX>;
+    constexpr int cpr = T::cpr;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = __lane_id();
+    if (tid < 9) L.m_nb[tid] = r.mnb;
+    if (tid == 9) L.fb = r.fb;
+    if (tid == 0) { L.n_agents = 0; L.n_flag = 0; }
+    __syncthreads();                                          // raw window, exponents, counters
+
+    // interior chunks: mask in place, list the agents (lane-major order: the
+    // list follows the cells in raster order, so a wavefront's agents gather
+    // from consecutive LDS banks)
     {
-        const int4 o_in = r.o_in;
-        const float4 g_in = r.g_in;
-        const bool live = ci < n_in;
-        const int l0 = ly_in * P + 4 * cc_in;
+        const bool live = tid < tg.n_in;
+        const int j = T::in_chunk(live ? tid : 0);
+        uint4 d = make_uint4(0, 0, 0, 0);
         if (live) {
-            *(float4 *)&sh.Em[l0] = make_float4(o_in.x < 0 ? g_in.x : 0.f, o_in.y < 0 ? g_in.y : 0.f,
-                                                o_in.z < 0 ? g_in.z : 0.f, o_in.w < 0 ? g_in.w : 0.f);
-            stage_S(l0, r.s_in);
+            d = *(const uint4 *)&Em[4 * j];
+            *(float4 *)&Em[4 * j] = make_float4(fmask(d.x), fmask(d.y), fmask(d.z), fmask(d.w));
         }
-        const int ov[4] = {o_in.x, o_in.y, o_in.z, o_in.w};
-        const float gv[4] = {g_in.x, g_in.y, g_in.z, g_in.w};
+        const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
+        const int ov[4] = {r.oc.x, r.oc.y, r.oc.z, r.oc.w};
         unsigned long long m[4];
         int tot = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) { m[k] = __ballot(live && ov[k] >= 0); tot += __popcll(m[k]); }
+        for (int k = 0; k < 4; ++k) { m[k] = __ballot(live && (dv[k] & D_OCC)); tot += __popcll(m[k]); }
         if (tot) {
-            // lane-major order: the list follows the cells in raster order, so
-            // a wavefront's agents gather from consecutive LDS banks
-            int base = 0;
-            if (lane == 0) base = atomicAdd(&sh.n_agents, tot);
-            int idx = __shfl(base, 0);
+            int idx0 = 0;
+            if (lane == 0) idx0 = atomicAdd(&L.n_agents, tot);
+            int idx = __shfl(idx0, 0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) idx += lanes_below(m[k]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (live && ov[k] >= 0) {
-                    sh.a_pk[idx] = ((uint32_t)ov[k] << 12) | (uint32_t)(l0 + k);
-                    sh.a_ec[idx] = gv[k];
+                if (live && (dv[k] & D_OCC)) {
+                    L.a_pk[idx] = ((uint32_t)ov[k] << 12) | (uint32_t)(4 * j + k);
+                    L.a_ec[idx] = __uint_as_float(dv[k] & ~D_OCC);
                     ++idx;
                 }
             }
         }
     }
+    // halo chunks: mask and rescale in place
+    const int mT = L.m_nb[4];
+    for (int h = tid; h < tg.n_halo; h += nthr) {
+        const int j = tg.halo_chunk(h);
+        const int row = (int)((unsigned)j / cpr), cc = j - row * cpr;
+        const int nby = (row >= V) + (row >= V + tg.ty);
+        const int nbx = (cc >= T::hc4) + (cc >= T::hc4 + T::cw);   // a chunk lies inside one tile column
+        const int dm = mT - L.m_nb[nby * 3 + nbx];
+        const uint4 d = *(const uint4 *)&Em[4 * j];
+        *(float4 *)&Em[4 * j] = make_float4(ldexpf(fmask(d.x), dm), ldexpf(fmask(d.y), dm),
+                                             ldexpf(fmask(d.z), dm), ldexpf(fmask(d.w), dm));
+    }
     __syncthreads();
+}
+
+// The step counter of scenario s and whether its kernels still act.
+__device__ __forceinline__ bool scenario_live(const SlotDev &s, int &step)
+{
+    step = gload(&s.ctr[C_STEP]);
+    return step < gload(&s.ctr[C_LIMIT]);
+}
+
+// Stages tile `tile` of scenario s (stage_issue, then stage_commit).  Returns
+// false, having waited for its loads, when the scenario has finished its
+// steps.
+template <int V, int TX>
+__device__ __forceinline__ bool stage_tile(const SlotDev &s, const TileGeom<V, TX> &tg, int tile,
+                                           float *Em, TileLists &L, int &step)
+{
+    const bool live = scenario_live(s, step);
+    StageRegs r;
+    stage_issue<V, TX>(s, tg, tile, Em, r);
+    __builtin_amdgcn_s_waitcnt(0);                            // loads into LDS and registers done
+    if (!live) return false;                                  // scenario finished: nothing to do
+    stage_commit<V, TX>(tg, Em, L, r);
+    return true;
 }
 
 // The draws of a staged tile: one lane per agent (FP32 from the LDS table,
 // flagged draws re-resolved in FP64 by their wavefront), or every draw in
-// FP64 on a fallback tile.  The record of the tile's k-th agent (id, cell,
-// chosen cell; the chosen cell is its own when it stays) goes to slot k of
-// the tile's segment, and the segment count is the tile's agent count.  Ends
-// with a workgroup barrier after which only thread 0 touches the LDS counters.
-template <int V, int TX, bool DEBUG, bool SS>
+// FP64 on a fallback tile.  The record of the tile's k-th agent (its cell in
+// the tile and the window slot it chose; the middle slot when it stays) goes
+// to slot k of the tile's segment, and the segment count is the tile's agent
+// count.  Ends with a workgroup barrier after which only thread 0 touches the
+// LDS counters.
+template <int V, int TX, bool DEBUG>
 __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, TX> &tg, int tile,
-                                            PlanShared<SS> &sh, int step, bool fallback)
+                                            const float *Em, TileLists &sh, int step)
 {
     using T = TileGeom<V, TX>;
     constexpr int SIDE = T::SIDE, P = T::P, Hc = T::Hc;
-    (void)Hc;
     const int tid = threadIdx.x, nthr = blockDim.x, lane = __lane_id();
-    const int gx0 = tg.gx0, gy0 = tg.gy0;
-    MoveRec *seg = s.seg + (long)tile * (TX * s.ty);
+    uint32_t *seg = s.seg + (long)tile * (TX * tg.ty);
     const int na = sh.n_agents;
     const uint32_t kseed0 = s.seed_lo, kseed1 = s.seed_hi;
     const uint32_t scn = s.scn;          // held in registers: the loops below store to memory
     const float eps = s.eps;
+    // the tile-local cell of LDS cell l (window row ly, column lx)
+    auto lcell_of = [&](int l) {
+        const int ly = (int)((unsigned)l / P);
+        return (ly - V) * TX + (l - ly * P - Hc);
+    };
 
-    if (fallback) {
+    if (sh.fb) {
         // every draw of this tile in FP64, one lane per agent
         for (int base = 0; base < na; base += nthr) {
             const int k = base + tid;
@@ -600,15 +583,12 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const int id = (int)(sh.a_pk[k] >> 12);
                 const int l = (int)(sh.a_pk[k] & 0xFFFu);
                 const int ly = (int)((unsigned)l / P);
-                const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
-                const int gc = cy * s.Wp + cx;
+                const int gc = (tg.gy0 + ly) * s.Wp + tg.gx0 + (l - ly * P);
                 const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0,
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const int t = resolve64_lane<V, DEBUG>(s, gc, id, u);
-                const int d = t - gc;                       // |dx|, |dy| <= V < Wp / 2
-                const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
-                gstore_rec(seg + k, (uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy));
+                const int slot = resolve64_lane<V, DEBUG>(s, gc, id, u);
+                seg[k] = plan_rec(lcell_of(l), slot);
                 if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
                 if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
             }
@@ -629,10 +609,8 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             const int id = (int)(sh.a_pk[k] >> 12);
             const int l = (int)(sh.a_pk[k] & 0xFFFu);
             const float ec = sh.a_ec[k];
-            const int ly = (int)((unsigned)l / P);
-            const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
 
-            const Window<V, P> win(sh.Em, l - V * P - V);     // origin (dy, dx) = (-V, -V)
+            const Window<V, P> win(Em, l - V * P - V);     // origin (dy, dx) = (-V, -V)
             float Rs[SIDE], row0[SIDE], row1[SIDE];
             load_row<V, P, 0>(win, ec, row0);
             load_row<V, P, 1>(win, ec, row1);
@@ -700,14 +678,14 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 for (int dy = -V; dy <= V; ++dy)
                     for (int dx = -V; dx <= V; ++dx)
                         if (dx * dx + dy * dy <= V * V && !(dx == 0 && dy == 0))
-                            emax = fmaxf(emax, sh.Em[l + dy * P + dx]);
+                            emax = fmaxf(emax, Em[l + dy * P + dx]);
                 if (s.dbg_w) {
                     float *wd = s.dbg_w + (size_t)id * SIDE * SIDE;
                     for (int dy = -V; dy <= V; ++dy)
                         for (int dx = -V; dx <= V; ++dx) {
                             float wv = 0.0f;
                             if (dx * dx + dy * dy <= V * V)
-                                wv = ((dx == 0 && dy == 0) ? ec : sh.Em[l + dy * P + dx]) / emax;
+                                wv = ((dx == 0 && dy == 0) ? ec : Em[l + dy * P + dx]) / emax;
                             wd[(dy + V) * SIDE + dx + V] = wv;
                         }
                 }
@@ -718,7 +696,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                         float q = 0.0f;
                         for (int d = 0; d <= 2 * a; ++d) {
                             const int dx = d - a, dy = r - V;
-                            q = q + ((dx == 0 && dy == 0) ? ec : sh.Em[l + dy * P + dx]);
+                            q = q + ((dx == 0 && dy == 0) ? ec : Em[l + dy * P + dx]);
                             cd[r * SIDE + (V - a) + d] = Pr[r] + q;
                         }
                     }
@@ -727,10 +705,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 if (s.dbg_flag) s.dbg_flag[id] = flag ? 1 : 0;
                 if (s.dbg_margin) s.dbg_margin[id] = margin / Wsum;
             }
-            if (!flag) {
-                const int ddx = ks - as, ddy = rs - V;
-                gstore_rec(seg + k, (uint32_t)id, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy));
-            }
+            if (!flag) seg[k] = plan_rec(lcell_of(l), rs * SIDE + (ks - as + V));
             flagged = flag;
         }
 
@@ -746,19 +721,12 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const int fid = (int)(sh.a_pk[kk] >> 12);
                 const int l = (int)(sh.a_pk[kk] & 0xFFFu);
                 const int ly = (int)((unsigned)l / P);
-                const int cx = gx0 + (l - ly * P), cy = gy0 + ly;
-                const int gc = cy * s.Wp + cx;
+                const int gc = (tg.gy0 + ly) * s.Wp + tg.gx0 + (l - ly * P);
                 const uint32_t x0 = plan_draw_word((uint32_t)fid, (uint32_t)step, scn, kseed0,
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const double *Sw = nullptr;
-                if constexpr (SS) Sw = sh.Sw;
-                const int t = resolve64_wave<V, SS>(s, gc, u, lane, sh.Em, Sw, l, P);
-                if (lane == 0) {
-                    const int d = t - gc;
-                    const int ddy = (d + V * s.Wp + V) / s.Wp - V, ddx = d - ddy * s.Wp;
-                    gstore_rec(seg + kk, (uint32_t)fid, pack_xy(cx, cy), pack_xy(cx + ddx, cy + ddy));
-                }
+                const int slot = resolve64_wave<V>(s, gc, u, lane, Em, l, P);
+                if (lane == 0) seg[kk] = plan_rec(lcell_of(l), slot);
             }
         }
     }
@@ -773,46 +741,39 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
 
 // One tile, V = v_max, TX = tile width (a power of two, 8..64): both fix the
 // LDS pitch, so every window offset of the agent loop is a compile-time
-// constant.  SS stages the floor-field window too (launches too small to hide
-// the global latency of the rare FP64 re-resolve).
-template <int V, int TX, bool DEBUG, bool SS>
-__device__ __forceinline__ void plan_tile(const SlotDev &s, int tile, PlanShared<SS> &sh)
+// constant.
+template <int V, int TX, bool DEBUG>
+__device__ __forceinline__ void plan_tile(const SlotDev &s, int tile, PlanShared &sh)
 {
-    // the step counter is loaded first and read once the staging loads are
-    // in flight
-    const int step = SS ? s.ctr[C_STEP] : gload(&s.ctr[C_STEP]);
-    const int limit = SS ? s.ctr[C_LIMIT] : gload(&s.ctr[C_LIMIT]);
     const TileGeom<V, TX> tg(s, tile);
-    StageRegs<SS> r;
-    stage_issue<V, TX, SS>(s, tg, r);
-    if (step >= limit) return;                                // scenario finished: nothing to do
+    int step = 0;
+    if (!stage_tile<V, TX>(s, tg, tile, sh.Em, sh.L, step)) return;
     if (tile == 0 && threadIdx.x < 4) s.ctr[C_BAR + threadIdx.x] = 0;   // fresh motion barriers
-    stage_commit<V, TX, SS>(s, tg, sh, r);
-    plan_agents<V, TX, DEBUG, SS>(s, tg, tile, sh, step, r.fb != 0);
+    plan_agents<V, TX, DEBUG>(s, tg, tile, sh.Em, sh.L, step);
 }
 
-template <int V, bool DEBUG, bool SS>
-__device__ __forceinline__ void plan_dispatch_tx(const SlotDev &s, int tile, PlanShared<SS> &sh)
+template <int V, bool DEBUG>
+__device__ __forceinline__ void plan_dispatch_tx(const SlotDev &s, int tile, PlanShared &sh)
 {
     switch (s.tx) {
-        case 8: plan_tile<V, 8, DEBUG, SS>(s, tile, sh); break;
-        case 16: plan_tile<V, 16, DEBUG, SS>(s, tile, sh); break;
-        case 32: plan_tile<V, 32, DEBUG, SS>(s, tile, sh); break;
-        case 64: plan_tile<V, 64, DEBUG, SS>(s, tile, sh); break;
+        case 8: plan_tile<V, 8, DEBUG>(s, tile, sh); break;
+        case 16: plan_tile<V, 16, DEBUG>(s, tile, sh); break;
+        case 32: plan_tile<V, 32, DEBUG>(s, tile, sh); break;
+        case 64: plan_tile<V, 64, DEBUG>(s, tile, sh); break;
         default: break;
     }
 }
 
 // Device-side dispatch over (v_max, tile width): one launch can mix scenarios.
-template <bool DEBUG, bool SS>
-__device__ __forceinline__ void plan_dispatch(const SlotDev &s, int tile, PlanShared<SS> &sh)
+template <bool DEBUG>
+__device__ __forceinline__ void plan_dispatch(const SlotDev &s, int tile, PlanShared &sh)
 {
     switch (s.v) {
-        case 1: plan_dispatch_tx<1, DEBUG, SS>(s, tile, sh); break;
-        case 2: plan_dispatch_tx<2, DEBUG, SS>(s, tile, sh); break;
-        case 3: plan_dispatch_tx<3, DEBUG, SS>(s, tile, sh); break;
-        case 4: plan_dispatch_tx<4, DEBUG, SS>(s, tile, sh); break;
-        case 5: plan_dispatch_tx<5, DEBUG, SS>(s, tile, sh); break;
+        case 1: plan_dispatch_tx<1, DEBUG>(s, tile, sh); break;
+        case 2: plan_dispatch_tx<2, DEBUG>(s, tile, sh); break;
+        case 3: plan_dispatch_tx<3, DEBUG>(s, tile, sh); break;
+        case 4: plan_dispatch_tx<4, DEBUG>(s, tile, sh); break;
+        case 5: plan_dispatch_tx<5, DEBUG>(s, tile, sh); break;
         default: break;
     }
 }

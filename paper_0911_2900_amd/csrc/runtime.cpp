@@ -398,10 +398,10 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     // carve one block: 256-byte aligned sub-buffers
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-    const size_t o_S = take(cells * 8), o_res = take(cells * 16), o_G = take(cells * 4),
+    const size_t o_S = take(cells * 8), o_res = take(cells * 16), o_D = take(cells * 4),
                  o_occ = take(cells * 4), o_type = take(cells), o_tm = take(tm * 4),
                  o_fb = take(ntiles), o_scnt = take(ntiles * 4),
-                 o_seg = take(tcells * sizeof(fk::MoveRec)), o_ka = take(lcells * sizeof(fk::Mover)),
+                 o_seg = take(tcells * 4), o_ka = take(lcells * sizeof(fk::Mover)),
                  o_kb = take(lcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
                  o_mitems = take(fk::MOVE_GROUP_MAX * 4),
@@ -426,13 +426,13 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     sd.res0 = (unsigned long long *)(base + o_res);
     sd.res1 = (unsigned long long *)(base + o_res + cells * 8);
 
-    sd.G = (const float *)(base + o_G);
+    sd.D = (uint32_t *)(base + o_D);
     sd.occ = (int32_t *)(base + o_occ);
     sd.cell = (const uint8_t *)(base + o_type);
     sd.tile_m = (const int32_t *)(base + o_tm);
     sd.tile_fb = (const uint8_t *)(base + o_fb);
     sd.seg_cnt = (int32_t *)(base + o_scnt);
-    sd.seg = (fk::MoveRec *)(base + o_seg);
+    sd.seg = (uint32_t *)(base + o_seg);
     sd.mv_a = (fk::Mover *)(base + o_ka);
     sd.mv_b = (fk::Mover *)(base + o_kb);
     sd.hand = (fk::Mover *)(base + o_hand);
@@ -457,7 +457,14 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     };
     cp(o_S, b.S.data(), cells * 8);
     if (e == hipSuccess) e = hipMemset(base + o_res, 0, cells * 16);
-    cp(o_G, b.G.data(), cells * 4);
+    // D: each cell's table entry, bit 31 set under an agent
+    std::vector<uint32_t> dtab(cells);
+    for (size_t g = 0; g < cells; ++g) {
+        uint32_t bits;
+        std::memcpy(&bits, &b.G[g], 4);
+        dtab[g] = bits | (b.occ[g] >= 0 ? fk::D_OCC : 0u);
+    }
+    cp(o_D, dtab.data(), cells * 4);
     cp(o_occ, b.occ.data(), cells * 4);
     const std::vector<uint8_t> cellb = fh::cell_bytes(b);
     cp(o_type, cellb.data(), cells);
@@ -541,19 +548,32 @@ fast_status read_state(fast_ctx *c, Slot *s, int32_t *xy, uint8_t *alive, int32_
     for (size_t g = 0; g < cells; ++g)
         if (occ[g] >= 0 && occ[g] < n) pos[occ[g]] = (int32_t)g;
     const int Wp = d.Wp, pad = d.pad, W = d.W;
+    // desired cells: the records of the last plan, while its motion phase has
+    // not run (the record's agent is the occupant of its start cell until then)
     std::vector<int32_t> tgt;
     if (desired) {
-        const size_t ntiles = (size_t)d.ntx * d.nty, tc = (size_t)d.tx * d.ty;
-        std::vector<int32_t> cnt(ntiles);
-        std::vector<fk::MoveRec> rec(ntiles * tc);
-        HIP_TRY(hipMemcpy(cnt.data(), d.seg_cnt, ntiles * 4, hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(rec.data(), d.seg, rec.size() * sizeof(fk::MoveRec), hipMemcpyDeviceToHost));
-        tgt = pos;                                          // no record: the agent stays
-        for (size_t t = 0; t < ntiles; ++t)
-            for (int k = 0; k < cnt[t]; ++k) {
-                const fk::MoveRec &r = rec[t * tc + k];
-                if (r.id < (uint32_t)n) tgt[r.id] = (int32_t)((r.dxy >> 16) * Wp + (r.dxy & 0xFFFFu));
+        tgt.assign((size_t)std::max(n, 1), -1);
+        if (s->planned) {
+            const size_t ntiles = (size_t)d.ntx * d.nty, tc = (size_t)d.tx * d.ty;
+            const int side = 2 * d.v + 1;
+            std::vector<int32_t> cnt(ntiles);
+            std::vector<uint32_t> rec(ntiles * tc);
+            HIP_TRY(hipMemcpy(cnt.data(), d.seg_cnt, ntiles * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(rec.data(), d.seg, rec.size() * 4, hipMemcpyDeviceToHost));
+            for (size_t t = 0; t < ntiles; ++t) {
+                const int tyy = (int)(t / d.ntx), txx = (int)(t % d.ntx);
+                for (int k = 0; k < cnt[t]; ++k) {
+                    const uint32_t r = rec[t * tc + k];
+                    const int lc = (int)(r & ((1u << fk::REC_SLOT_SHIFT) - 1u));
+                    const int slot = (int)(r >> fk::REC_SLOT_SHIFT);
+                    const int cx = txx * d.tx + d.pad + lc % d.tx, cy = tyy * d.ty + d.pad + lc / d.tx;
+                    const int g = cy * Wp + cx;
+                    const int id = occ[(size_t)g];
+                    if (id < 0 || id >= n) continue;
+                    tgt[id] = g + (slot / side - d.v) * Wp + (slot % side - d.v);
+                }
             }
+        }
     }
     for (int i = 0; i < n; ++i) {
         const int p = pos[i];
@@ -580,11 +600,19 @@ fast_status batch_items(fast_ctx *c, const std::vector<int32_t> &hs, BatchItems 
     std::stable_sort(p.order.begin(), p.order.end(), [&](int32_t a, int32_t b) {
         return c->slots[a].n_agents > c->slots[b].n_agents;
     });
-    p.items.clear();
     p.het.clear();
+    p.v = p.tx = 0;
+    bool first = true;
     for (int32_t h : p.order) {
         const Slot &s = c->slots[h];
         if (s.het) { p.het.push_back(h); continue; }
+        if (first) { p.v = s.dev.v; p.tx = s.dev.tx; first = false; }
+        else if (s.dev.v != p.v || s.dev.tx != p.tx) p.v = p.tx = 0;
+    }
+    p.items.clear();
+    for (int32_t h : p.order) {
+        const Slot &s = c->slots[h];
+        if (s.het) continue;
         for (int i = 0; i < s.n_items; ++i) p.items.push_back(((uint32_t)h << 20) | (uint32_t)i);
     }
     const std::vector<int> G = batch_groups(c, p.order);
@@ -592,14 +620,6 @@ fast_status batch_items(fast_ctx *c, const std::vector<int32_t> &hs, BatchItems 
     for (size_t i = 0; i < p.order.size(); ++i)
         for (int g = 0; g < G[i]; ++g)
             p.mitems.push_back(motion_item(p.order[i], g, G[i], p.order.size() == 1));
-    p.v = p.tx = 0;
-    bool first = true;
-    for (int32_t h : p.order) {
-        const Slot &s = c->slots[h];
-        if (s.het) continue;
-        if (first) { p.v = s.dev.v; p.tx = s.dev.tx; first = false; }
-        else if (s.dev.v != p.v || s.dev.tx != p.tx) p.v = p.tx = 0;
-    }
     p.rj.clear();
     p.max_regions = 0;
     for (int32_t h : p.order)
