@@ -130,7 +130,7 @@ struct SlotDev {
     int32_t *seg_cnt;        // ntx*nty: agents planned per tile
     uint32_t *seg;           // ntx*nty*tx*ty: their records (plan_rec), tile by tile
     Mover *mv_a, *mv_b;      // (ntx*nty + 2 MOVE_GROUP_MAX)*tx*ty each: movers of the current / next round
-    Mover *hand;             // MOVE_GROUP_MAX*MOVE_SOLO_MAX: movers handed to workgroup 0
+    Mover *hand;             // (motion workgroups)*MOVE_SOLO_MAX: movers handed to workgroup 0
     int32_t *ctr;            // C_NCTR
     unsigned long long *stat;// S_NSTAT
     float *dbg_w;            // optional debug outputs (null in normal runs)

@@ -129,6 +129,7 @@ __device__ int group_sync_count(const SlotDev &s, int G, int r, int n, unsigned 
             w = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((w >> 32) >= target) { total = (int)((uint32_t)w - (uint32_t)seen); seen = w; break; }
             if (++spins > SPIN_LIMIT) { atomicOr(&s.ctr[C_ERR], 1); break; }
+            __builtin_amdgcn_s_sleep(1);           // back off: fewer polls of the shared word
         }
         if (acquire) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         sh_total = total;
@@ -142,25 +143,30 @@ __device__ __forceinline__ int mover_reach(unsigned long long key)
     return (int)((key >> MEFF_SHIFT) & 7ull);
 }
 
+// Reserves a mover's reach, cells 0..m_eff of its line, for a round: the
+// largest word on a cell is the round's earliest mover there.
+template <int V>
+__device__ __forceinline__ void reserve_reach(const SlotDev &s, unsigned long long *res,
+                                              const Mover &mv, unsigned long long tagw)
+{
+    const Line L = make_line(mv.cxy, mv.dxy);
+    const int me = mover_reach(mv.key);
+    const unsigned long long word = (mv.key & KEY_MASK) | tagw;
+#pragma unroll
+    for (int k = 0; k <= V; ++k) {
+        if (k <= me) {
+            int x, y;
+            L.at(k, x, y);
+            atomicMax(&res[y * s.Wp + x], word);
+        }
+    }
+}
+
 template <int V>
 __device__ __forceinline__ void reserve_list(const SlotDev &s, unsigned long long *res,
                                              const Mover *list, int n, unsigned long long tagw)
 {
-    const int Wp = s.Wp;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const Mover mv = list[i];
-        const Line L = make_line(mv.cxy, mv.dxy);
-        const int me = mover_reach(mv.key);
-        const unsigned long long word = (mv.key & KEY_MASK) | tagw;
-#pragma unroll
-        for (int k = 0; k <= V; ++k) {
-            if (k <= me) {
-                int x, y;
-                L.at(k, x, y);
-                atomicMax(&res[y * Wp + x], word);
-            }
-        }
-    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) reserve_reach<V>(s, res, list[i], tagw);
 }
 
 // Priority word [~x0:32][~id:20] of agent id in this step's motion order.
@@ -229,77 +235,124 @@ __device__ unsigned long long line_reach(const SlotDev &s, const Mover &mv, int 
            (ex ? (1ull << EXIT_BIT) : 0ull);
 }
 
-// Check-and-commit for the workgroup's list (see the protocol above); movers
-// that cannot commit yet are appended to `nxt` (the workgroup's own list).
-// Returns the number appended.  Reservations and occupancy are read with
+__device__ __forceinline__ int lanes_below(unsigned long long mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Appends the kept movers of one pass of the workgroup to list + n (the
+// count comes from sh_kept after the caller's barrier).
+__device__ __forceinline__ void append_kept(Mover *list, int n, bool keep, const Mover &mv, int *sh_kept)
+{
+    const unsigned long long m = __ballot(keep);
+    if (m) {
+        const int lane = __lane_id();
+        int base = 0;
+        if (lane == 0) base = atomicAdd(sh_kept, __popcll(m));
+        base = __shfl(base, 0);
+        if (keep) list[n + base + lanes_below(m)] = mv;
+    }
+}
+
+// Check-and-commit of one mover (see the protocol above).  Returns true if
+// it cannot commit yet; then, when res_next is given, it reserves its reach
+// for the next round there with tagw_next (the other array: this round's
+// checks never read it).  Reservations and occupancy are read with
 // agent-scope loads, or with plain (cacheable) ones when the last barrier
 // ended with an acquire fence (`acquired`): either way they see every
 // reservation of the round and at least the occupancy at its start (commits
 // of this round may or may not be seen, which the protocol allows).
 template <int V>
+__device__ __forceinline__ bool commit_one(const SlotDev &s, const unsigned long long *res,
+                                           const Mover &mv, unsigned long long tagw, bool acquired,
+                                           unsigned long long *res_next,
+                                           unsigned long long tagw_next)
+{
+    const int Wp = s.Wp;
+    const Line L = make_line(mv.cxy, mv.dxy);
+    const int me = mover_reach(mv.key);
+    const uint32_t hp = (uint32_t)(mv.key >> HP_SHIFT) & 0x1Fu;
+    const unsigned long long word = (mv.key & KEY_MASK) | tagw;
+    int cell[V + 1];
+    unsigned long long w[V + 1];
+    int o[V + 1];
+#pragma unroll
+    for (int k = 0; k <= V; ++k) {
+        int x = L.cx, y = L.cy;
+        if (k <= me) L.at(k, x, y);
+        cell[k] = y * Wp + x;
+        const bool in = k >= 1 && k <= me;
+        if (acquired) {
+            w[k] = in ? res[cell[k]] : word;
+            o[k] = in ? s.occ[cell[k]] : -1;
+        } else {
+            w[k] = in ? ld_res(&res[cell[k]]) : word;
+            o[k] = in ? ld_agent(&s.occ[cell[k]]) : -1;
+        }
+    }
+    // j: the reach cells still enterable; the mover must hold all of them
+    int j = me;
+#pragma unroll
+    for (int k = V; k >= 1; --k)
+        if (k <= me && o[k] >= 0 && !((hp >> (k - 1)) & 1u)) j = k - 1;
+    bool holds = true;
+#pragma unroll
+    for (int k = 1; k <= V; ++k) holds &= (k > j) || (w[k] == word);
+    if (!holds) {
+        if (res_next) {
+            const unsigned long long wn = (mv.key & KEY_MASK) | tagw_next;
+#pragma unroll
+            for (int k = 0; k <= V; ++k)
+                if (k <= me) atomicMax(&res_next[cell[k]], wn);
+        }
+        return true;
+    }
+    const int id = (int)(~(uint32_t)mv.key & ID_MASK);
+    const int c = cell[0];
+    int at = c, reached = 0;
+#pragma unroll
+    for (int k = 1; k <= V; ++k) {
+        if (k > j || o[k] >= 0) break;
+        at = cell[k];
+        reached = k;
+    }
+    const bool gone = reached == me && me > 0 && ((mv.key >> EXIT_BIT) & 1ull);
+    if (gone) {
+        st_agent(&s.occ[c], -1);
+        atomicAnd(&s.D[c], ~D_OCC);
+        atomicAdd(&s.ctr[C_EXITED], 1);
+        atomicSub(&s.ctr[C_NACTIVE], 1);
+    } else if (at != c) {
+        st_agent(&s.occ[c], -1);
+        atomicAnd(&s.D[c], ~D_OCC);
+        st_agent(&s.occ[at], id);
+        atomicOr(&s.D[at], D_OCC);
+    }
+    return false;
+}
+
+// Check-and-commit for the workgroup's list; movers that cannot commit yet
+// are appended to `nxt` (the workgroup's own list, one LDS atomic per
+// wavefront) and reserve the next round (commit_one).  Returns the number
+// appended.
+template <int V>
 __device__ int commit_list(const SlotDev &s, const unsigned long long *res, const Mover *cur,
-                           Mover *nxt, int n, unsigned long long tagw, bool acquired)
+                           Mover *nxt, int n, unsigned long long tagw, bool acquired,
+                           unsigned long long *res_next, unsigned long long tagw_next)
 {
     __shared__ int sh_cnt;
-    const int Wp = s.Wp;
     if (threadIdx.x == 0) sh_cnt = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const Mover mv = cur[i];
-        const Line L = make_line(mv.cxy, mv.dxy);
-        const int me = mover_reach(mv.key);
-        const uint32_t hp = (uint32_t)(mv.key >> HP_SHIFT) & 0x1Fu;
-        const unsigned long long word = (mv.key & KEY_MASK) | tagw;
-        int cell[V + 1];
-        unsigned long long w[V + 1];
-        int o[V + 1];
-#pragma unroll
-        for (int k = 0; k <= V; ++k) {
-            int x = L.cx, y = L.cy;
-            if (k <= me) L.at(k, x, y);
-            cell[k] = y * Wp + x;
-            const bool in = k >= 1 && k <= me;
-            if (acquired) {
-                w[k] = in ? res[cell[k]] : word;
-                o[k] = in ? s.occ[cell[k]] : -1;
-            } else {
-                w[k] = in ? ld_res(&res[cell[k]]) : word;
-                o[k] = in ? ld_agent(&s.occ[cell[k]]) : -1;
-            }
+    for (int i0 = 0; i0 < n; i0 += blockDim.x) {
+        const int i = i0 + (int)threadIdx.x;
+        Mover mv{};
+        bool lose = false;
+        if (i < n) {
+            mv = cur[i];
+            lose = commit_one<V>(s, res, mv, tagw, acquired, res_next, tagw_next);
         }
-        // j: the reach cells still enterable; the mover must hold all of them
-        int j = me;
-#pragma unroll
-        for (int k = V; k >= 1; --k)
-            if (k <= me && o[k] >= 0 && !((hp >> (k - 1)) & 1u)) j = k - 1;
-        bool holds = true;
-#pragma unroll
-        for (int k = 1; k <= V; ++k) holds &= (k > j) || (w[k] == word);
-        if (!holds) {
-            nxt[atomicAdd(&sh_cnt, 1)] = mv;
-            continue;
-        }
-        const int id = (int)(~(uint32_t)mv.key & ID_MASK);
-        const int c = cell[0];
-        int at = c, reached = 0;
-#pragma unroll
-        for (int k = 1; k <= V; ++k) {
-            if (k > j || o[k] >= 0) break;
-            at = cell[k];
-            reached = k;
-        }
-        const bool gone = reached == me && me > 0 && ((mv.key >> EXIT_BIT) & 1ull);
-        if (gone) {
-            st_agent(&s.occ[c], -1);
-            atomicAnd(&s.D[c], ~D_OCC);
-            atomicAdd(&s.ctr[C_EXITED], 1);
-            atomicSub(&s.ctr[C_NACTIVE], 1);
-        } else if (at != c) {
-            st_agent(&s.occ[c], -1);
-            atomicAnd(&s.D[c], ~D_OCC);
-            st_agent(&s.occ[at], id);
-            atomicOr(&s.D[at], D_OCC);
-        }
+        append_kept(nxt, 0, lose, mv, &sh_cnt);
     }
     __syncthreads();
     return sh_cnt;
@@ -352,11 +405,6 @@ __device__ int gather_lists(const SlotDev &s, int G, Mover *to, int *sh_scan)
     return total;
 }
 
-__device__ __forceinline__ int lanes_below(unsigned long long mask)
-{
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
 // Inclusive prefix sum of sh[0 .. MOVE_THREADS) in place (all threads call;
 // each thread's own element must be in place): a shuffle scan within each
@@ -416,20 +464,6 @@ __device__ __forceinline__ bool gather_one(const SlotDev &s, uint32_t rec, int t
     return mover_reach(mv.key) > 0;
 }
 
-// Appends the kept movers of one pass of the workgroup to list + n (the
-// count comes from sh_kept after the caller's barrier).
-__device__ __forceinline__ void append_kept(Mover *list, int n, bool keep, const Mover &mv, int *sh_kept)
-{
-    const unsigned long long m = __ballot(keep);
-    if (m) {
-        const int lane = __lane_id();
-        int base = 0;
-        if (lane == 0) base = atomicAdd(sh_kept, __popcll(m));
-        base = __shfl(base, 0);
-        if (keep) list[n + base + lanes_below(m)] = mv;
-    }
-}
-
 // sh_scan[MOVE_THREADS], sh_tp[GATHER_TILES_MAX], sh_kept: LDS of the kernel
 // (declared there once, not per v_max).
 template <int V>
@@ -442,6 +476,10 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
     Mover *cur = s.mv_a + (long)g * cap, *nxt = s.mv_b + (long)g * cap;
     unsigned long long seen0 = 0, seen1 = 0;
     uint32_t tag = (uint32_t)s.ctr[C_TAG];
+    // movers reserve round 0 as they are gathered unless the tags run out
+    // first (then the arrays are wiped before the first reservation)
+    const bool early0 = tag < TAG_LIMIT;
+    const unsigned long long tagw0 = (unsigned long long)(tag + 1) << TAG_SHIFT;
     if (g == 0 && tid == 0)   // agents planned this step, for the throughput counters
         atomicAdd(&s.stat[S_PLANNED], (unsigned long long)s.ctr[C_NACTIVE]);
 
@@ -486,6 +524,7 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
                 const int k = i - (a ? sh_tp[a - 1] : 0);
                 const int tile = c + a * stride;
                 keep = gather_one<V>(s, s.seg[(long)tile * TC + k], tile, step, mv);
+                if (keep && early0) reserve_reach<V>(s, s.res0, mv, tagw0);
             }
             append_kept(cur, n, keep, mv, &sh_kept);
         }
@@ -516,6 +555,7 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
                     const int k = i - (a ? sh_scan[a - 1] : 0);
                     const int tile = t0 + j0 + a;
                     keep = gather_one<V>(s, s.seg[(long)tile * TC + k], tile, step, mv);
+                    if (keep && early0) reserve_reach<V>(s, s.res0, mv, tagw0);
                 }
                 append_kept(cur, n, keep, mv, &sh_kept);
             }
@@ -534,11 +574,18 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
     bool acq = false;                              // the last barrier ended with an acquire
     for (int r = 0; total > 0; ++r) {
         unsigned long long *res = (r & 1) ? s.res1 : s.res0;
+        // this round's reservations made already: by the gather (round 0) or
+        // by the losers as they failed their checks (later rounds); not when
+        // the tags must be restarted first
+        bool reserved = r == 0 && early0;
         if (r > 0) {
             // round r's movers are the losers of round r - 1 (this workgroup's share)
+            const bool merge = tag < TAG_LIMIT;
             n = commit_list<V>(s, (r & 1) ? s.res0 : s.res1, cur, nxt, n,
-                               (unsigned long long)tag << TAG_SHIFT, acq);
+                               (unsigned long long)tag << TAG_SHIFT, acq, merge ? res : nullptr,
+                               (unsigned long long)(tag + 1) << TAG_SHIFT);
             Mover *t = cur; cur = nxt; nxt = t;
+            reserved = merge;
         }
         if (tag >= TAG_LIMIT) {
             // tags are exhausted: once every check of the last round is done,
@@ -553,7 +600,7 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
             if (group_sync_count(s, Gr, bar_r++, 0, seen0, seen1) < 0) return;
         }
         ++tag;
-        reserve_list<V>(s, res, cur, n, (unsigned long long)tag << TAG_SHIFT);
+        if (!reserved) reserve_list<V>(s, res, cur, n, (unsigned long long)tag << TAG_SHIFT);
         if (Gr > 1 && n <= MOVE_SOLO_MAX) {         // workgroup 0 may take these over
             Mover *h = s.hand + (long)g * MOVE_SOLO_MAX;
             for (int i = tid; i < n; i += blockDim.x) {

@@ -405,7 +405,9 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
                  o_kb = take(lcells * sizeof(fk::Mover)), o_ctr = take(fk::C_NCTR * 4),
                  o_stat = take(fk::S_NSTAT * 8), o_items = take(ntiles * 4), o_self = take(4),
                  o_mitems = take(fk::MOVE_GROUP_MAX * 4),
-                 o_hand = take((size_t)fk::MOVE_GROUP_MAX * fk::MOVE_SOLO_MAX * sizeof(fk::Mover)),
+                 // every motion group of this scenario has at most motion_group(n)
+                 // workgroups, each handing over at most MOVE_SOLO_MAX movers
+                 o_hand = take((size_t)motion_group(b.n) * fk::MOVE_SOLO_MAX * sizeof(fk::Mover)),
                  o_vi = take(b.vi.size()), o_fi = take(b.fi.size()),
                  o_Sf = take(b.Sf.size() * 8);
     void *block = nullptr;
