@@ -102,20 +102,20 @@ typedef struct {
                                     tile_w * tile_h <= 1024                          */
     const uint8_t *agent_v;      /* host, n_agents speeds in 1..v_max (agent i reaches
                                     dx^2 + dy^2 <= agent_v[i]^2), or NULL: all v_max.
-                                    Such a scenario plans every draw in FP64 (a
-                                    slower path); in a batch (and when served) it
-                                    gets a planning launch of its own beside the
-                                    shared one.  fast_debug_plan refuses it with
-                                    FAST_E_INVALID                                   */
+                                    Such a scenario is planned by a kernel of its
+                                    own (the FP32 table path with each agent's
+                                    disc as a mask); in a batch (and when served)
+                                    it gets a planning launch of its own beside
+                                    the shared one                                   */
     int32_t n_fields;            /* floor fields: 0 or 1 = one field from every exit;
                                     2..8 = route choice / counterflow (Sec. 3's richer
                                     situations): field g is the exact floor field
                                     from the exit cells tagged g alone, and agent i
                                     weighs its window with field agent_field[i].
                                     Walls stay those of the all-exit field and an
-                                    agent leaves at any exit cell.  Planned in FP64
-                                    like per-agent speeds (a launch of its own in a
-                                    batch); fast_debug_plan refuses it              */
+                                    agent leaves at any exit cell.  Each field has
+                                    its own FP32 exp table; planned like per-agent
+                                    speeds (a launch of its own in a batch)         */
     const uint8_t *exit_field;   /* host, width*height, read at exit cells: the field
                                     (0..n_fields-1) the exit belongs to; every field
                                     needs an exit.  NULL when n_fields <= 1          */
@@ -237,8 +237,9 @@ fast_status fast_get_stats(fast_ctx *ctx, int32_t handle, fast_stats *out);
  *       in-row running sum); the window's last slot, a corner outside every
  *       disc, holds the FP32 total W.  All zero on fallback tiles, which have
  *       no FP32 CDF.
- * Host buffers sized for n_agents; any may be NULL.  Refuses scenarios with
- * per-agent speeds or several fields (FAST_E_INVALID).  Synchronises. */
+ * Host buffers sized for n_agents; any may be NULL.  With per-agent speeds
+ * the reach set is the agent's own disc; with several fields the weights are
+ * those of the agent's field.  Synchronises. */
 fast_status fast_debug_plan(fast_ctx *ctx, int32_t handle, float *w32, uint8_t *flag,
                             float *margin, float *cdf32);
 

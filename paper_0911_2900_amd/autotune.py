@@ -75,16 +75,18 @@ def _key(v: int, cells: int, density: float) -> dict:
             "density": round(float(density), 3)}
 
 
-# Scenarios with a speed per agent run the FP64 kernel (one wavefront per
-# draw): 16 x 8 tiles measured fastest for it on the 40,000-agent room with
-# speeds 1..5 (30 us per launch; 8 x 8: 37, 32 x 8: 33, 64 x 8: 39, 32 x 32: 58).
-HET_TILE = (16, 8)
+# Scenarios with a speed per agent or several fields run the per-agent kernel
+# (FP32 table path, a window per field).  On the 400 x 400 room with 40,000
+# agents and speeds 1..5, launches took 9.6-10.2 us over tiles 16 x 8 .. 64 x 16;
+# on the two-field counterflow hall 8.9-9.2 us; 32 x 8 is within 2 % of the
+# best of both.
+HET_TILE = (32, 8)
 
 
 def choose_tile(v: int, width: int, height: int, n_agents: int, batched: bool = False,
                 het: bool = False):
     """Tuned tile for a scenario (nearest table entry), or None without a table;
-    het: the scenario has a speed per agent."""
+    het: the scenario has a speed per agent or several floor fields."""
     if het:
         return HET_TILE
     if not os.path.exists(TABLE):

@@ -19,11 +19,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["plan_batch.hip", "plan_one.hip", "motion.hip", "stream.hip", "cus.hip", "regions.hip", "plan_het.hip", "scratch.hip",
+SOURCES = ["plan_batch.hip", "plan_one.hip", "motion.hip", "stream.hip", "cus.hip", "regions.hip", "scratch.hip",
            "builder.cpp",
            "runtime.cpp"]
-# plan_fixed.hip is compiled once per v_max (PLAN_V), into one object each.
-FIXED = "plan_fixed.hip"
+# plan_fixed.hip and plan_het.hip are compiled once per v_max (PLAN_V), into
+# one object each.
+PER_V = ("plan_fixed.hip", "plan_het.hip")
 V_MAX = 5
 
 
@@ -53,7 +54,7 @@ def build(verbose: bool = False) -> str:
     from concurrent.futures import ThreadPoolExecutor
 
     os.makedirs(BUILD, exist_ok=True)
-    jobs = [_compile_cmd(FIXED, v) for v in range(V_MAX, 0, -1)]
+    jobs = [_compile_cmd(src, v) for src in PER_V for v in range(V_MAX, 0, -1)]
     jobs += [_compile_cmd(src) for src in SOURCES]
     if verbose:
         for cmd, _ in jobs:

@@ -178,6 +178,62 @@ std::vector<uint8_t> cell_bytes(const Built &b)
     return out;
 }
 
+// The FP32 exp table of one floor field S (padded layout of b): per tile T
+// the scale m_T = round(k_S * mid(S over T's window) / ln 2), every cell's
+// entry G = fl32(exp(m_T ln 2 - k_S S)) in the scale of its own tile (0 for
+// walls, unreachable cells and entries beyond e^+-80), and the fallback flag
+// of every tile whose window holds a reachable cell outside [e^-80, e^80] in
+// the tile's scale.
+void exp_table(const Built &b, const double *S, double ks, std::vector<float> &G,
+               std::vector<int32_t> &tile_m, std::vector<uint8_t> &tile_fb, int &n_fb)
+{
+    const int v = b.v, tx = b.tx, ty = b.ty, pad = b.pad;
+    const int64_t np = (int64_t)b.Wp * b.Hp;
+    const int ts = b.ntx + 2;
+    G.assign((size_t)np, 0.0f);
+    tile_m.assign((size_t)ts * (b.nty + 2), 0);
+    std::vector<int32_t> mcell((size_t)np, 0);
+    for (int j = 0; j < b.nty; ++j)
+        for (int i = 0; i < b.ntx; ++i) {
+            double lo = INFINITY, hi = -INFINITY;
+            for (int y = j * ty + pad - v; y < j * ty + pad + ty + v; ++y)
+                for (int x = i * tx + pad - v; x < i * tx + pad + tx + v; ++x) {
+                    const double s = S[(int64_t)y * b.Wp + x];
+                    if (std::isfinite(s)) { lo = std::min(lo, s); hi = std::max(hi, s); }
+                }
+            int32_t m = 0;
+            if (lo <= hi) m = (int32_t)std::llround(ks * 0.5 * (lo + hi) / kLn2);
+            tile_m[(size_t)(j + 1) * ts + i + 1] = m;
+            for (int y = j * ty + pad; y < j * ty + ty + pad; ++y)
+                for (int x = i * tx + pad; x < i * tx + tx + pad; ++x) mcell[(int64_t)y * b.Wp + x] = m;
+        }
+    // table entries in the scale of their own tile
+    std::vector<char> cell_ok((size_t)np, 1);
+    for (int64_t g = 0; g < np; ++g) {
+        const double s = S[g];
+        if (!std::isfinite(s)) continue;
+        const double ex = (double)mcell[g] * kLn2 - ks * s;
+        if (std::fabs(ex) > kRange) { cell_ok[g] = 0; continue; }
+        G[g] = (float)std::exp(ex);
+    }
+    // fallback tiles: some window cell outside [e^-80, e^80] in the tile's scale
+    tile_fb.assign((size_t)b.ntx * b.nty, 0);
+    n_fb = 0;
+    for (int j = 0; j < b.nty; ++j)
+        for (int i = 0; i < b.ntx; ++i) {
+            const int32_t m = tile_m[(size_t)(j + 1) * ts + i + 1];
+            bool ok = true;
+            for (int y = j * ty + pad - v; ok && y < j * ty + pad + ty + v; ++y)
+                for (int x = i * tx + pad - v; x < i * tx + pad + tx + v; ++x) {
+                    const int64_t g = (int64_t)y * b.Wp + x;
+                    const double s = S[g];
+                    if (!std::isfinite(s)) continue;
+                    if (!cell_ok[g] || std::fabs((double)m * kLn2 - ks * s) > kRange) { ok = false; break; }
+                }
+            if (!ok) { tile_fb[(size_t)j * b.ntx + i] = 1; ++n_fb; }
+        }
+}
+
 int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::string &err)
 {
     const int W = d.width, H = d.height, v = d.v_max;
@@ -254,7 +310,6 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
     const int64_t np = (int64_t)b.Wp * b.Hp;
     b.type.assign((size_t)np, fk::CELL_WALL);
     b.S.assign((size_t)np, INFINITY);
-    b.G.assign((size_t)np, 0.0f);
     b.occ.assign((size_t)np, -1);
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
@@ -277,50 +332,26 @@ int build_scenario(const fast_scenario_desc &d, int tx, int ty, Built &b, std::s
         b.occ[g] = i;
     }
 
-    // per-tile scale m_T from the midpoint of k_S S over the tile's window
-    const double ks = d.k_s;
-    const int ts = b.ntx + 2;
-    b.tile_m.assign((size_t)ts * (b.nty + 2), 0);
-    std::vector<int32_t> mcell((size_t)np, 0);
-    for (int j = 0; j < b.nty; ++j)
-        for (int i = 0; i < b.ntx; ++i) {
-            double lo = INFINITY, hi = -INFINITY;
-            for (int y = j * ty + pad - v; y < j * ty + pad + ty + v; ++y)
-                for (int x = i * tx + pad - v; x < i * tx + pad + tx + v; ++x) {
-                    const double s = b.S[(int64_t)y * b.Wp + x];
-                    if (std::isfinite(s)) { lo = std::min(lo, s); hi = std::max(hi, s); }
-                }
-            int32_t m = 0;
-            if (lo <= hi) m = (int32_t)std::llround(ks * 0.5 * (lo + hi) / kLn2);
-            b.tile_m[(size_t)(j + 1) * ts + i + 1] = m;
-            for (int y = j * ty + pad; y < j * ty + ty + pad; ++y)
-                for (int x = i * tx + pad; x < i * tx + tx + pad; ++x) mcell[(int64_t)y * b.Wp + x] = m;
+    exp_table(b, b.S.data(), d.k_s, b.G, b.tile_m, b.tile_fb, b.n_fb);
+    // several fields: one table per field, each with its own tile scales and
+    // fallback flags
+    if (nf >= 2) {
+        b.Gf.resize((size_t)nf * np);
+        b.tile_mf.resize((size_t)nf * (b.ntx + 2) * (b.nty + 2));
+        b.tile_fbf.resize((size_t)nf * b.ntx * b.nty);
+        b.n_fbf = 0;
+        for (int g = 0; g < nf; ++g) {
+            std::vector<float> G;
+            std::vector<int32_t> tm;
+            std::vector<uint8_t> fb;
+            int nfb = 0;
+            exp_table(b, b.Sf.data() + (size_t)g * np, d.k_s, G, tm, fb, nfb);
+            std::copy(G.begin(), G.end(), b.Gf.begin() + (size_t)g * np);
+            std::copy(tm.begin(), tm.end(), b.tile_mf.begin() + (size_t)g * tm.size());
+            std::copy(fb.begin(), fb.end(), b.tile_fbf.begin() + (size_t)g * fb.size());
+            b.n_fbf += nfb;
         }
-    // table entries in the scale of their own tile
-    std::vector<char> cell_ok((size_t)np, 1);
-    for (int64_t g = 0; g < np; ++g) {
-        const double s = b.S[g];
-        if (!std::isfinite(s)) continue;
-        const double ex = (double)mcell[g] * kLn2 - ks * s;
-        if (std::fabs(ex) > kRange) { cell_ok[g] = 0; continue; }
-        b.G[g] = (float)std::exp(ex);
     }
-    // fallback tiles: some window cell outside [e^-80, e^80] in the tile's scale
-    b.tile_fb.assign((size_t)b.ntx * b.nty, 0);
-    b.n_fb = 0;
-    for (int j = 0; j < b.nty; ++j)
-        for (int i = 0; i < b.ntx; ++i) {
-            const int32_t m = b.tile_m[(size_t)(j + 1) * ts + i + 1];
-            bool ok = true;
-            for (int y = j * ty + pad - v; ok && y < j * ty + pad + ty + v; ++y)
-                for (int x = i * tx + pad - v; x < i * tx + pad + tx + v; ++x) {
-                    const int64_t g = (int64_t)y * b.Wp + x;
-                    const double s = b.S[g];
-                    if (!std::isfinite(s)) continue;
-                    if (!cell_ok[g] || std::fabs((double)m * kLn2 - ks * s) > kRange) { ok = false; break; }
-                }
-            if (!ok) { b.tile_fb[(size_t)j * b.ntx + i] = 1; ++b.n_fb; }
-        }
     b.eps = guard_band(v);
     return FAST_OK;
 }

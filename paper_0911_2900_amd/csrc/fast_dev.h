@@ -139,6 +139,21 @@ struct SlotDev {
     float *dbg_cdf;
 };
 
+// Per-agent speeds and several floor fields of a scenario (the richer
+// situations of Sec. 3).  Each field has its own exp table, tile scales and
+// fallback flags, laid out like the scenario's own, field_cells apart.
+struct HetDev {
+    const uint8_t *vi;       // n_agents maximum speeds in 1..v, or null (all v)
+    const uint8_t *fi;       // n_agents field indices, or null (one field: the scenario's own)
+    const uint32_t *Gf;      // nf exp tables as FP32 bits (nf >= 2)
+    const double *Sf;        // nf floor fields (nf >= 2)
+    const int32_t *tile_mf;  // nf x (ntx+2)*(nty+2) tile scales (nf >= 2)
+    const uint8_t *tile_fbf; // nf x ntx*nty fallback flags (nf >= 2)
+    long field_cells;        // Wp*Hp
+    int nf;                  // fields; 1 = the scenario's own (D, S, tile_m, tile_fb)
+};
+constexpr int MAX_FIELDS = 8;
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), word 0 of the output
 // block for counter (c0, c1, c2, c3) and key (k0, k1).
 __host__ __device__ inline uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2,

@@ -28,8 +28,12 @@ struct Built {
     std::vector<uint8_t> vi;       // per-agent speeds (empty: every agent has v)
     std::vector<uint8_t> fi;       // per-agent floor field (empty: one field for all)
     std::vector<double> Sf;        // padded floor fields of the exit groups, one after another
+    std::vector<float> Gf;         // their exp tables, one after another (several fields only)
+    std::vector<int32_t> tile_mf;  // their tile scales, (ntx+2)*(nty+2) each
+    std::vector<uint8_t> tile_fbf; // their fallback flags, ntx*nty each
     int n = 0;
     int n_fb = 0;
+    int n_fbf = 0;                 // fallback (tile, field) pairs
     float eps = 0.0f;
 };
 
@@ -63,7 +67,10 @@ extern "C" hipError_t fk_launch_plan(const fk::SlotDev *table, const uint32_t *i
                                                     hipEvent_t stop);                              \
     extern "C" hipError_t fk_launch_plan_one_fixed_v##V(const fk::SlotDev *slot, int n_tiles,      \
                                                         hipStream_t stream, hipEvent_t start,      \
-                                                        hipEvent_t stop);
+                                                        hipEvent_t stop);                          \
+    extern "C" hipError_t fk_launch_plan_het_v##V(const fk::SlotDev *slot, const fk::HetDev *h,    \
+                                                  int n_tiles, int debug, hipStream_t stream,      \
+                                                  hipEvent_t start, hipEvent_t stop);
 FK_FIXED_LAUNCHERS(1)
 FK_FIXED_LAUNCHERS(2)
 FK_FIXED_LAUNCHERS(3)
@@ -76,9 +83,8 @@ extern "C" hipError_t fk_launch_move(const fk::SlotDev *table, const uint32_t *m
                                      hipStream_t stream);
 extern "C" hipError_t fk_move_per_cu(int *per_cu);
 extern "C" hipError_t fk_cu_probe(hipStream_t stream, int n_wg, uint32_t *ids_host);
-extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const uint8_t *vi,
-                                         const uint8_t *fi, const double *Sf, long field_cells,
-                                         int n_tiles, hipStream_t stream, hipEvent_t start,
+extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const fk::HetDev *h, int n_tiles,
+                                         int debug, hipStream_t stream, hipEvent_t start,
                                          hipEvent_t stop);
 extern "C" hipError_t fk_launch_count(const fk::RegionDev *jobs, int n_jobs, int max_regions,
                                       hipStream_t stream);

@@ -74,6 +74,7 @@ extern "C" hipError_t FK_CAT(fk_launch_plan_one_fixed_v, PLAN_V)(const fk::SlotD
                                                                   hipEvent_t start, hipEvent_t stop)
 {
     if (n_tiles <= 0) return hipSuccess;
+    if (slot->v != PLAN_V) return hipErrorInvalidValue;
     const int cells = slot->tx * slot->ty;
     const int threads = cells < fk::PLAN_THREADS ? fk::PLAN_THREADS
                         : cells > fk::ONE_MAX_THREADS ? fk::ONE_MAX_THREADS : cells;

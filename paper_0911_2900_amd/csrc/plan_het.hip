@@ -1,187 +1,207 @@
-// plan_het.hip -- planning with a maximum speed per agent.
+// plan_het.hip -- planning with a maximum speed per agent and with several
+// floor fields (one per exit group), the richer situations that Sec. 3 of the
+// paper expects to cost more planning work.
 //
-// Sec. 3 of the paper expects richer situations than one speed for everybody
-// to cost more planning work.  Here agent i reaches only the cells of its own
-// disc dx^2 + dy^2 <= v_i^2 (v_i <= the scenario's v_max, which sets the
-// staged window).  The same kernel plans scenarios with several floor fields
-// (one per exit group): agent i then weighs its window with field fi[i].
-// Every draw is made in FP64, one wavefront per agent, and
-// chooses what the paper's order gives: weights exp(k_S (S(c) - S(t))) over
-// the window in raster order (zero outside the reach set), the sequential sum
-// W, tau = u W with the agent's Philox u, and the first cell whose prefix
-// exceeds tau.  The tile's agents are listed by the same staging as the
-// uniform kernels.
+// Agent i reaches only its own disc dx^2 + dy^2 <= v_i^2 (v_i <= the
+// scenario's v_max, which sets the staged window), and weighs its window with
+// the floor field of its group.  The draw is the uniform model's -- weights
+// exp(k_S (S(c) - S(t))) over the window in raster order, zero outside the
+// reach set, the sequential sum W, tau = u W, the first cell whose prefix
+// exceeds tau -- made on the same FP32 table path: each field has its own
+// exp table (per-tile scales, range-fallback flags), the tile stages one
+// window per field, and an agent's slots outside its own disc take an exact
+// 0, which leaves the rounding structure of the sums, and so the guard band,
+// unchanged.  Draws inside the band are re-resolved in FP64 by the wavefront
+// with the agent's own field and reach; agents of a field for which the tile
+// is a range-fallback tile draw in FP64.
+//
+// This file is compiled once per v_max (PLAN_V), like plan_fixed.hip.
 #include <hip/hip_ext.h>
 
 #include "plan_tile.h"
 
+#ifndef PLAN_V
+#error "PLAN_V (the v_max this object is compiled for) must be defined"
+#endif
+
+#define FK_CAT2(a, b) a##b
+#define FK_CAT(a, b) FK_CAT2(a, b)
+
 namespace fk {
 
-// The draw of the agent at padded cell gc with reach vr, by a whole
-// wavefront: lane j takes raster slot j of the (2V+1)^2 window (and slot
-// j + 64 when the window has more than 64 slots) and evaluates its weight;
-// an FP64 wavefront scan gives the prefixes.  As in the uniform kernels' FP64
-// path, a scanned prefix of at most 128 non-negative terms lies within
-// 1.5e-14 W of the sequential one, so when no prefix is within s.near64 W
-// (1e-12 W) of tau every comparison tau < C_j, and with it the choice, is the
-// sequential sum's; otherwise the prefix is rebuilt strictly sequentially,
-// slot by slot (slots outside the reach set add exactly nothing).  Every lane
-// returns the chosen raster slot of the window.
-template <int V>
-__device__ int draw_het_wave(const SlotDev &s, const double *__restrict__ S, int gc, float u32,
-                             int lane, int vr)
-{
-    constexpr int SIDE = 2 * V + 1, NS = SIDE * SIDE, NH = (NS + 63) / 64;
-    const double NEAR = s.near64;
-    const double Sc = S[gc];
-    const double ks = s.k_s;
-    const double u = (double)u32;
-    double w[NH], C[NH];
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-        const int j = lane + 64 * h;
-        w[h] = 0.0;
-        if (j < NS) {
-            // the three reads of the slot are independent (every slot lies in
-            // the padded grid), so they are issued together
-            const int dy = j / SIDE - V, dx = j % SIDE - V;
-            const int t = gc + dy * s.Wp + dx;
-            const uint8_t ct = s.cell[t];
-            const int o = s.occ[t];
-            const double St = S[t];
-            const bool reach = dx * dx + dy * dy <= vr * vr && (ct & CELL_TYPE_MASK) != CELL_WALL &&
-                               (o < 0 || t == gc);
-            if (reach) w[h] = exp(ks * (Sc - St));
-        }
-    }
-    C[0] = wave_scan64(w[0]);
-    if constexpr (NH == 2) C[1] = wave_scan64(w[1]) + lane_value(C[0], 63);
-    const double Wt = lane_value(C[NH - 1], (NS - 1) % 64);
-    const double tp = u * Wt;
-    bool near = false;
-#pragma unroll
-    for (int h = 0; h < NH; ++h) near = near || (lane + 64 * h < NS && fabs(tp - C[h]) <= NEAR * Wt);
-    unsigned long long m[NH];
-    if (__ballot(near) == 0) {
-#pragma unroll
-        for (int h = 0; h < NH; ++h) m[h] = __ballot(lane + 64 * h < NS && tp < C[h]);
-    } else {
-        double acc = 0.0, my[NH];
-#pragma unroll
-        for (int h = 0; h < NH; ++h) my[h] = 0.0;
-#pragma unroll 1
-        for (int j = 0; j < NS; ++j) {
-            const double wj = NH == 2 && j >= 64 ? lane_value(w[NH - 1], j - 64) : lane_value(w[0], j & 63);
-            acc = acc + wj;
-            if (j < 64) { if (lane == j) my[0] = acc; }
-            else if (lane == j - 64) my[NH - 1] = acc;
-        }
-        const double tau = u * acc;
-#pragma unroll
-        for (int h = 0; h < NH; ++h) m[h] = __ballot(lane + 64 * h < NS && tau < my[h]);
-    }
-    int jw = (NS - 1) / 2;                                    // own cell if unreached
-    if (m[0]) jw = __builtin_ctzll(m[0]);
-    else if (NH == 2 && m[NH - 1]) jw = 64 + __builtin_ctzll(m[NH - 1]);
-    return jw;
-}
+// LDS of the kernel besides the staged windows (dynamic: one per field and,
+// with several fields, the window of D for the occupancy bits).
+struct HetShared {
+    TileLists L;
+    uint8_t a_gv[MAX_TILE_CELLS];      // per listed agent: field << 4 | maximum speed
+    int32_t m_nbf[MAX_FIELDS * 9];     // per field: exponents of the 3 x 3 tiles around
+    int fbf[MAX_FIELDS];               // per field: the tile is a range-fallback tile
+};
 
-// Workgroup i plans tile i with HET_THREADS threads; wavefront q draws the
-// tile's agents q, q + HET_THREADS / 64, ...; vi[id] is agent id's speed.
-// FIELDS: agent id follows the floor field at Sf + fi[id] * field_cells and
-// vi may be NULL (every agent has V); otherwise the scenario's one field
-// s.S, with vi set.  Each form is its own kernel, so the single-field form
-// does no per-agent field lookup.
-constexpr int HET_THREADS = 1024;
-
-template <int V, int TX, bool FIELDS>
-__global__ __launch_bounds__(HET_THREADS) void plan_kernel_het(const SlotDev s,
-                                                               const uint8_t *__restrict__ vi,
-                                                               const uint8_t *__restrict__ fi,
-                                                               const double *__restrict__ Sf,
-                                                               long field_cells)
+// One tile of a scenario with per-agent speeds and / or several fields:
+// workgroup i plans tile i.
+template <int V, int TX, bool DEBUG>
+__global__ __launch_bounds__(ONE_MAX_THREADS) void plan_kernel_het(const SlotDev s, const HetDev h)
 {
-    __shared__ PlanShared sh;
     using T = TileGeom<V, TX>;
-    constexpr int P = T::P;
+    constexpr int cpr = T::cpr;
+    extern __shared__ float4 het_dyn[];
+    __shared__ HetShared sh;
+    float *Ew = (float *)het_dyn;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = __lane_id();
     const int tile = (int)blockIdx.x;
     const T tg(s, tile);
+    const int win = 4 * tg.n_win;                             // floats per window
+    const bool fields = h.nf > 1;
+    const int nw = fields ? h.nf : 1;                         // windows of tables
+    float *Dw = Ew + (fields ? h.nf * win : 0);               // the window of D
     int step = 0;
-    if (!stage_tile<V, TX>(s, tg, tile, sh.Em, sh.L, step)) return;   // lists the tile's agents
-    if (tile == 0 && threadIdx.x < 4) s.ctr[C_BAR + threadIdx.x] = 0;   // fresh motion barriers
-    uint32_t *seg = s.seg + (long)tile * (TX * tg.ty);
-    const int na = sh.L.n_agents;
-    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
-    const int nw = (int)(blockDim.x >> 6);
-    for (int k = wave; k < na; k += nw) {
-        const int id = (int)(sh.L.a_pk[k] >> 12);
-        const int l = (int)(sh.L.a_pk[k] & 0xFFFu);
-        const int ly = l / P, lx = l - ly * P;
-        const int gc = (tg.gy0 + ly) * s.Wp + tg.gx0 + lx;
-        const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, s.scn, s.seed_lo, s.seed_hi);
-        const float u = (float)(x0 >> 8) * 0x1p-24f;
-        int slot;
-        if constexpr (FIELDS) {
-            // the whole wavefront draws agent k, so its field is uniform
-            const int f = __builtin_amdgcn_readfirstlane((int)fi[id]);
-            const int vr = vi ? (int)vi[id] : V;
-            slot = draw_het_wave<V>(s, Sf + (long)f * field_cells, gc, u, lane, vr);
-        } else {
-            slot = draw_het_wave<V>(s, s.S, gc, u, lane, (int)vi[id]);
-        }
-        if (lane == 0) seg[k] = plan_rec((ly - V) * TX + (lx - T::Hc), slot);
-    }
-    if (threadIdx.x == 0) {
-        s.seg_cnt[tile] = na;
-        if (na > 0) atomicAdd(&s.stat[S_FALLBACK], (unsigned long long)na);
-    }
-}
+    const bool live = scenario_live(s, step);
 
-template <int V>
-hipError_t launch_het_v(const SlotDev &s, const uint8_t *vi, const uint8_t *fi, const double *Sf,
-                        long fc, dim3 grid, hipStream_t stream, hipEvent_t start, hipEvent_t stop)
-{
-    const dim3 block(HET_THREADS);
-    if (fi) {
-        switch (s.tx) {
-            case 8: hipExtLaunchKernelGGL((plan_kernel_het<V, 8, true>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-            case 16: hipExtLaunchKernelGGL((plan_kernel_het<V, 16, true>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-            case 32: hipExtLaunchKernelGGL((plan_kernel_het<V, 32, true>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-            case 64: hipExtLaunchKernelGGL((plan_kernel_het<V, 64, true>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-            default: return hipErrorInvalidValue;
+    // every load: the window of D (with one field it is the table itself),
+    // each field's table window, the tile's own occupancy (ids), exponents
+    StageRegs r;
+    stage_issue<V, TX>(s, tg, tile, Dw, r);
+    int mf = 0, ff = 0;
+    if (fields) {
+        for (int g = 0; g < h.nf; ++g)
+            issue_window<V, TX>(h.Gf + g * h.field_cells, s.Wp, s.Hp, tg, Ew + g * win);
+        const int tstride = s.ntx + 2, tm_size = tstride * (s.nty + 2);
+        if (tid < 9 * h.nf) {
+            const int g = tid / 9, i = tid - 9 * g;
+            mf = gload(&h.tile_mf[g * tm_size + (tg.tile_y + i / 3) * tstride + tg.tile_x + i % 3]);
+        } else if (tid < 10 * h.nf) {
+            ff = gload(&h.tile_fbf[(tid - 9 * h.nf) * (s.ntx * s.nty) + tile]);
         }
-        return hipGetLastError();
     }
-    if (!vi) return hipErrorInvalidValue;
-    switch (s.tx) {
-        case 8: hipExtLaunchKernelGGL((plan_kernel_het<V, 8, false>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-        case 16: hipExtLaunchKernelGGL((plan_kernel_het<V, 16, false>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-        case 32: hipExtLaunchKernelGGL((plan_kernel_het<V, 32, false>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-        case 64: hipExtLaunchKernelGGL((plan_kernel_het<V, 64, false>), grid, block, 0, stream, start, stop, 0, s, vi, fi, Sf, fc); break;
-        default: return hipErrorInvalidValue;
+    __builtin_amdgcn_s_waitcnt(0);
+    if (!live) return;                                        // scenario finished
+    if (tile == 0 && tid < 4) s.ctr[C_BAR + tid] = 0;         // fresh motion barriers
+    if (fields) {
+        if (tid < 9 * h.nf) sh.m_nbf[tid] = mf;
+        else if (tid < 10 * h.nf) sh.fbf[tid - 9 * h.nf] = ff;
+    } else {
+        if (tid < 9) sh.m_nbf[tid] = r.mnb;
+        if (tid == 9) sh.fbf[0] = r.fb;
     }
-    return hipGetLastError();
+    if (tid == 0) { sh.L.n_agents = 0; sh.L.n_flag = 0; sh.L.fb = 0; }
+    __syncthreads();
+
+    // list the tile's agents from the occupancy bits of D (lane-major order,
+    // as in the uniform kernels)
+    {
+        const bool lv = tid < tg.n_in;
+        const int j = T::in_chunk(lv ? tid : 0);
+        uint4 d = make_uint4(0, 0, 0, 0);
+        if (lv) d = *(const uint4 *)&Dw[4 * j];
+        const uint32_t dv[4] = {d.x, d.y, d.z, d.w};
+        const int ov[4] = {r.oc.x, r.oc.y, r.oc.z, r.oc.w};
+        unsigned long long m[4];
+        int tot = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { m[k] = __ballot(lv && (dv[k] & D_OCC)); tot += __popcll(m[k]); }
+        if (tot) {
+            int idx0 = 0;
+            if (lane == 0) idx0 = atomicAdd(&sh.L.n_agents, tot);
+            int idx = __shfl(idx0, 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) idx += lanes_below(m[k]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (lv && (dv[k] & D_OCC)) sh.L.a_pk[idx++] = ((uint32_t)ov[k] << 12) | (uint32_t)(4 * j + k);
+        }
+    }
+    __syncthreads();
+    // each agent's field, speed and own-cell value (its field's table entry,
+    // read before the windows are masked)
+    const int na = sh.L.n_agents;
+    for (int k = tid; k < na; k += nthr) {
+        const uint32_t pk = sh.L.a_pk[k];
+        const int id = (int)(pk >> 12), l = (int)(pk & 0xFFFu);
+        const int g = fields ? (int)h.fi[id] : 0;
+        const int vr = h.vi ? (int)h.vi[id] : V;
+        sh.a_gv[k] = (uint8_t)((g << 4) | vr);
+        const uint32_t raw = fields ? __float_as_uint(Ew[g * win + l]) : __float_as_uint(Dw[l]);
+        sh.L.a_ec[k] = __uint_as_float(raw & ~D_OCC);
+    }
+    __syncthreads();
+    // every window: occupied cells 0, halo chunks rescaled to this tile's
+    // exponent of the window's field
+    for (int c = tid; c < nw * tg.n_win; c += nthr) {
+        const int g = c / tg.n_win, j = c - g * tg.n_win;
+        const int row = (int)((unsigned)j / cpr), cc = j - row * cpr;
+        const int nby = (row >= V) + (row >= V + tg.ty);
+        const int nbx = (cc >= T::hc4) + (cc >= T::hc4 + T::cw);
+        const int dm = sh.m_nbf[g * 9 + 4] - sh.m_nbf[g * 9 + nby * 3 + nbx];
+        // (with one field, the table window is the window of D itself)
+        const uint4 o = *(const uint4 *)&Dw[4 * j];
+        const uint4 d = *(const uint4 *)&Ew[g * win + 4 * j];
+        auto val = [&](uint32_t occ, uint32_t x) {
+            return (occ & D_OCC) ? 0.0f : ldexpf(__uint_as_float(x & ~D_OCC), dm);
+        };
+        *(float4 *)&Ew[g * win + 4 * j] = make_float4(val(o.x, d.x), val(o.y, d.y), val(o.z, d.z),
+                                                       val(o.w, d.w));
+    }
+    __syncthreads();
+    HetView hv;
+    hv.a_gv = sh.a_gv;
+    hv.fbf = sh.fbf;
+    hv.Sf = fields ? h.Sf : nullptr;
+    hv.field_cells = h.field_cells;
+    hv.win = win;
+    plan_agents<V, TX, DEBUG, true>(s, tg, tile, Ew, sh.L, step, hv);
 }
 
 }  // namespace fk
 
-// Planning launch of one scenario with per-agent speeds vi and per-agent floor
-// fields fi (device, n_agents each, or NULL), the fields at Sf, field_cells
-// padded cells apart (Sf NULL: the scenario's one field).
-extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const uint8_t *vi,
-                                         const uint8_t *fi, const double *Sf, long field_cells,
-                                         int n_tiles, hipStream_t stream, hipEvent_t start,
-                                         hipEvent_t stop)
+namespace {
+
+// (Internal linkage: this file is compiled once per v_max, and each object
+// must launch its own kernels.)
+template <int V, bool DEBUG, int TX>
+hipError_t launch_het_tx(const fk::SlotDev &s, const fk::HetDev &h, int n_tiles, hipStream_t stream,
+                         hipEvent_t start, hipEvent_t stop)
+{
+    using T = fk::TileGeom<V, TX>;
+    const int cells = s.tx * s.ty;
+    const int threads = cells < fk::PLAN_THREADS ? fk::PLAN_THREADS
+                        : cells > fk::ONE_MAX_THREADS ? fk::ONE_MAX_THREADS : cells;
+    const size_t n_win = (size_t)T::cpr * (s.ty + 2 * V);
+    const size_t lds = (size_t)(h.nf > 1 ? h.nf + 1 : 1) * n_win * 16;
+    hipExtLaunchKernelGGL((fk::plan_kernel_het<V, TX, DEBUG>), dim3(n_tiles), dim3(threads), lds,
+                          stream, start, stop, 0, s, h);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Planning launch of one scenario with per-agent speeds and / or several
+// fields (h), one workgroup per tile; debug: also the weights, flags,
+// margins and CDF of every draw (the descriptor's debug outputs).
+extern "C" hipError_t FK_CAT(fk_launch_plan_het_v, PLAN_V)(const fk::SlotDev *slot,
+                                                            const fk::HetDev *h, int n_tiles,
+                                                            int debug, hipStream_t stream,
+                                                            hipEvent_t start, hipEvent_t stop)
 {
     if (n_tiles <= 0) return hipSuccess;
-    const dim3 grid(n_tiles);
-    if (!Sf) { Sf = slot->S; fi = nullptr; }
-    switch (slot->v) {
-        case 1: return fk::launch_het_v<1>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
-        case 2: return fk::launch_het_v<2>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
-        case 3: return fk::launch_het_v<3>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
-        case 4: return fk::launch_het_v<4>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
-        case 5: return fk::launch_het_v<5>(*slot, vi, fi, Sf, field_cells, grid, stream, start, stop);
+    if (slot->v != PLAN_V) return hipErrorInvalidValue;
+    // (fi may be null when the scenario has no agents)
+    if (h->nf < 1 || h->nf > fk::MAX_FIELDS || (h->nf > 1 && (!h->Gf || !h->Sf)))
+        return hipErrorInvalidValue;
+    if (debug) {
+        switch (slot->tx) {
+            case 8: return launch_het_tx<PLAN_V, true, 8>(*slot, *h, n_tiles, stream, start, stop);
+            case 16: return launch_het_tx<PLAN_V, true, 16>(*slot, *h, n_tiles, stream, start, stop);
+            case 32: return launch_het_tx<PLAN_V, true, 32>(*slot, *h, n_tiles, stream, start, stop);
+            case 64: return launch_het_tx<PLAN_V, true, 64>(*slot, *h, n_tiles, stream, start, stop);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (slot->tx) {
+        case 8: return launch_het_tx<PLAN_V, false, 8>(*slot, *h, n_tiles, stream, start, stop);
+        case 16: return launch_het_tx<PLAN_V, false, 16>(*slot, *h, n_tiles, stream, start, stop);
+        case 32: return launch_het_tx<PLAN_V, false, 32>(*slot, *h, n_tiles, stream, start, stop);
+        case 64: return launch_het_tx<PLAN_V, false, 64>(*slot, *h, n_tiles, stream, start, stop);
         default: return hipErrorInvalidValue;
     }
 }

@@ -37,3 +37,18 @@ extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, i
         default: return hipErrorInvalidValue;
     }
 }
+
+// Scenarios with per-agent speeds or several fields (plan_het.hip).
+extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const fk::HetDev *h, int n_tiles,
+                                         int debug, hipStream_t stream, hipEvent_t start,
+                                         hipEvent_t stop)
+{
+    switch (slot->v) {
+        case 1: return fk_launch_plan_het_v1(slot, h, n_tiles, debug, stream, start, stop);
+        case 2: return fk_launch_plan_het_v2(slot, h, n_tiles, debug, stream, start, stop);
+        case 3: return fk_launch_plan_het_v3(slot, h, n_tiles, debug, stream, start, stop);
+        case 4: return fk_launch_plan_het_v4(slot, h, n_tiles, debug, stream, start, stop);
+        case 5: return fk_launch_plan_het_v5(slot, h, n_tiles, debug, stream, start, stop);
+        default: return hipErrorInvalidValue;
+    }
+}

@@ -64,9 +64,11 @@ struct Window {
 };
 
 // Row R (dy = R - V) of the reach disc: its 2a+1 masked exp values; the
-// agent's own cell takes e_c.
-template <int V, int P, int R>
-__device__ __forceinline__ void load_row(const Window<V, P> &w, float ec, float (&x)[2 * V + 1])
+// agent's own cell takes e_c.  MASK (an agent whose own maximum speed vr may
+// be below V): slots with dx^2 + dy^2 > vr2 = vr^2 take an exact 0, so the
+// sums keep their rounding structure.
+template <int V, int P, int R, bool MASK>
+__device__ __forceinline__ void load_row(const Window<V, P> &w, float ec, int vr2, float (&x)[2 * V + 1])
 {
     constexpr int a = half_width(V, R - V);
     const float *rp = w.template row<R>();
@@ -74,24 +76,29 @@ __device__ __forceinline__ void load_row(const Window<V, P> &w, float ec, float 
     for (int k = 0; k <= 2 * a; ++k) {
         if (R == V && k == a) x[k] = ec;
         else x[k] = rp[(V - a) + k];
+        if constexpr (MASK) {
+            constexpr int dy = R - V;
+            const int dx = k - a;
+            if (dx * dx + dy * dy > 0) x[k] = dx * dx + dy * dy <= vr2 ? x[k] : 0.0f;
+        }
     }
 }
 
 // Row sums, software-pipelined by two rows: the loads of row R+2 are issued
 // before row R is summed, and the scheduling barrier keeps later rows from
 // being hoisted, so at most three rows of values are live.
-template <int V, int P, int R>
+template <int V, int P, int R, bool MASK>
 struct RowPipe {
-    static __device__ __forceinline__ void run(const Window<V, P> &w, float ec, float *Rs,
+    static __device__ __forceinline__ void run(const Window<V, P> &w, float ec, int vr2, float *Rs,
                                                const float (&cur)[2 * V + 1],
                                                const float (&nx1)[2 * V + 1])
     {
         constexpr int a = half_width(V, R - V);
         float nx2[2 * V + 1];
-        if constexpr (R + 2 < 2 * V + 1) load_row<V, P, R + 2>(w, ec, nx2);
+        if constexpr (R + 2 < 2 * V + 1) load_row<V, P, R + 2, MASK>(w, ec, vr2, nx2);
         Rs[R] = Tree<2 * a + 1, 0>::sum(cur);
         __builtin_amdgcn_sched_barrier(0);
-        if constexpr (R + 1 < 2 * V + 1) RowPipe<V, P, R + 1>::run(w, ec, Rs, nx1, nx2);
+        if constexpr (R + 1 < 2 * V + 1) RowPipe<V, P, R + 1, MASK>::run(w, ec, vr2, Rs, nx1, nx2);
     }
 };
 
@@ -100,10 +107,9 @@ struct RowPipe {
 // the square window in raster order (zero outside the reach set), sequential
 // sum, tau = u * W, first slot with tau < C.  One lane does one agent.
 // ---------------------------------------------------------------------------
-template <int V>
-__device__ __forceinline__ bool reach_ok(const SlotDev &s, int gc, int t, int dx, int dy)
+__device__ __forceinline__ bool reach_ok(const SlotDev &s, int gc, int t, int dx, int dy, int vr)
 {
-    if (dx * dx + dy * dy > V * V) return false;
+    if (dx * dx + dy * dy > vr * vr) return false;
     if ((s.cell[t] & CELL_TYPE_MASK) == CELL_WALL) return false;
     const int o = s.occ[t];
     return o < 0 || t == gc;
@@ -114,11 +120,14 @@ __device__ __forceinline__ bool reach_ok(const SlotDev &s, int gc, int t, int dx
 // also writes each slot's weight over the largest weight of the reach set,
 // rounded to FP32 (every such ratio lies in [0, 1], so FP32 holds it whatever
 // the range of the weights themselves).
+// S: the agent's floor field (the scenario's, or its exit group's); vr: its
+// maximum speed (V unless it has one of its own).
 template <int V, bool DEBUG>
-__device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
+__device__ int resolve64_lane(const SlotDev &s, const double *__restrict__ S, int gc, int id,
+                              float u32, int vr)
 {
     constexpr int SIDE = 2 * V + 1;
-    const double Sc = s.S[gc];
+    const double Sc = S[gc];
     const double ks = s.k_s;
     double C = 0.0, wmax = 0.0;
 #pragma unroll 1
@@ -126,8 +135,8 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
 #pragma unroll 1
         for (int dx = -V; dx <= V; ++dx) {
             const int t = gc + dy * s.Wp + dx;
-            if (reach_ok<V>(s, gc, t, dx, dy)) {
-                const double w = exp(ks * (Sc - s.S[t]));
+            if (reach_ok(s, gc, t, dx, dy, vr)) {
+                const double w = exp(ks * (Sc - S[t]));
                 C = C + w;
                 wmax = fmax(wmax, w);
             }
@@ -138,9 +147,9 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
 #pragma unroll 1
             for (int dx = -V; dx <= V; ++dx) {
                 const int t = gc + dy * s.Wp + dx;
-                if (reach_ok<V>(s, gc, t, dx, dy))
+                if (reach_ok(s, gc, t, dx, dy, vr))
                     s.dbg_w[(size_t)id * SIDE * SIDE + (dy + V) * SIDE + dx + V] =
-                        (float)(exp(ks * (Sc - s.S[t])) / wmax);
+                        (float)(exp(ks * (Sc - S[t])) / wmax);
             }
     }
     const double tau = (double)u32 * C;
@@ -150,8 +159,8 @@ __device__ int resolve64_lane(const SlotDev &s, int gc, int id, float u32)
 #pragma unroll 1
         for (int dx = -V; dx <= V; ++dx) {
             const int t = gc + dy * s.Wp + dx;
-            if (reach_ok<V>(s, gc, t, dx, dy)) {
-                C2 = C2 + exp(ks * (Sc - s.S[t]));
+            if (reach_ok(s, gc, t, dx, dy, vr)) {
+                C2 = C2 + exp(ks * (Sc - S[t]));
                 if (tau < C2) return (dy + V) * SIDE + dx + V;
             }
         }
@@ -238,8 +247,8 @@ __device__ __forceinline__ double lane_value(double x, int j)
 // or occupied, so only the floor field is read, from global memory (the draws
 // that come here are rare).  Returns the chosen raster slot of the window.
 template <int V>
-__device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, const float *Em,
-                              int l, int P)
+__device__ int resolve64_wave(const SlotDev &s, const double *__restrict__ S, int gc, float u32,
+                              int lane, const float *Em, int l, int P, int vr)
 {
     // The lane index passes through an empty asm here, inside the rare branch
     // that calls this: otherwise the compiler hoists the lane-dependent set-up
@@ -248,7 +257,6 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
     asm volatile("" : "+v"(lane));
     constexpr int SIDE = 2 * V + 1;
     const double NEAR = s.near64;
-    const double *__restrict__ S = s.S;
     const double Sc = S[gc];
     const double ks = s.k_s;
     const double u = (double)u32;
@@ -257,7 +265,8 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
         double w = 0.0;
         int dx = 0, dy = 0;
         disc_slot<V>(lane, dx, dy);
-        if (lane < ND && ((dx == 0 && dy == 0) || Em[l + dy * P + dx] != 0.0f))
+        if (lane < ND && dx * dx + dy * dy <= vr * vr &&
+            ((dx == 0 && dy == 0) || Em[l + dy * P + dx] != 0.0f))
             w = exp(ks * (Sc - S[gc + dy * s.Wp + dx]));
         const double Cp = wave_scan64(w);
         const double Wp = lane_value(Cp, ND - 1);
@@ -289,7 +298,7 @@ __device__ int resolve64_wave(const SlotDev &s, int gc, float u32, int lane, con
             if (j < NS) {
                 const int dy = j / SIDE - V, dx = j % SIDE - V;
                 const bool own = dx == 0 && dy == 0;
-                if (dx * dx + dy * dy <= V * V && (own || Em[l + dy * P + dx] != 0.0f))
+                if (dx * dx + dy * dy <= vr * vr && (own || Em[l + dy * P + dx] != 0.0f))
                     w[h] = exp(ks * (Sc - S[gc + dy * s.Wp + dx]));
             }
         }
@@ -432,26 +441,37 @@ struct StageRegs {
 // Issues every load of tile `tile`'s staging without waiting for any: the
 // window of D goes straight from memory into the LDS table Em (one 16-byte
 // chunk per lane, no registers), the rest into registers.
+// Issues the loads of a tile's window of a per-cell 4-byte array `src`
+// (Wp x Hp) straight into LDS at Em, chunk j at float 4j.
 template <int V, int TX>
-__device__ __forceinline__ void stage_issue(const SlotDev &s, const TileGeom<V, TX> &tg, int tile,
-                                            float *Em, StageRegs &r)
+__device__ __forceinline__ void issue_window(const void *src, int Wp, int Hp,
+                                             const TileGeom<V, TX> &tg, float *Em)
 {
-    using T = TileGeom<V, TX>;
-    constexpr int cpr = T::cpr;
+    constexpr int cpr = TileGeom<V, TX>::cpr;
     const int tid = threadIdx.x, nthr = blockDim.x, lane = __lane_id();
     const int wbase = tid - lane;
-    const int Wp = s.Wp;
     const int base = tg.gy0 * Wp + tg.gx0;                    // padded cell of window (0, 0)
-    const __amdgpu_buffer_rsrc_t rD = lds_rsrc(s.D, (uint32_t)((size_t)Wp * s.Hp * 4));
+    const __amdgpu_buffer_rsrc_t rs = lds_rsrc(src, (uint32_t)((size_t)Wp * Hp * 4));
     for (int j0 = 0; j0 < tg.n_win; j0 += nthr) {
         const int j = j0 + tid;
         if (j < tg.n_win) {
             const int row = (int)((unsigned)j / cpr), cc = j - row * cpr;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rD, (lds_ptr_t)(&Em[4 * (j0 + wbase)]), 16, (uint32_t)(base + row * Wp + 4 * cc) * 4u,
+                rs, (lds_ptr_t)(&Em[4 * (j0 + wbase)]), 16, (uint32_t)(base + row * Wp + 4 * cc) * 4u,
                 0, 0, 0);
         }
     }
+}
+
+template <int V, int TX>
+__device__ __forceinline__ void stage_issue(const SlotDev &s, const TileGeom<V, TX> &tg, int tile,
+                                            float *Em, StageRegs &r)
+{
+    using T = TileGeom<V, TX>;
+    const int tid = threadIdx.x;
+    const int Wp = s.Wp;
+    const int base = tg.gy0 * Wp + tg.gx0;                    // padded cell of window (0, 0)
+    issue_window<V, TX>(s.D, Wp, s.Hp, tg, Em);
     r.oc = make_int4(-1, -1, -1, -1);
     if (tid < tg.n_in)
         r.oc = gload_i4(s.occ + base + (V + (tid >> T::cw_log)) * Wp + T::Hc + 4 * (tid & (T::cw - 1)));
@@ -550,16 +570,32 @@ __device__ __forceinline__ bool stage_tile(const SlotDev &s, const TileGeom<V, T
     return true;
 }
 
+// What the draws of a tile need for per-agent speeds and several floor fields
+// (the richer situations of Sec. 3; see plan_het.hip): each listed agent's
+// field and maximum speed, one staged window per field, per-field fallback
+// flags, and the fields themselves for the FP64 paths.
+struct HetView {
+    const uint8_t *a_gv;      // LDS, per listed agent: field << 4 | maximum speed
+    const int *fbf;           // LDS, per field: the tile is a range-fallback tile for it
+    const double *Sf;         // floor fields field_cells apart, or null: the scenario's S
+    long field_cells;
+    int win;                  // floats per staged window
+};
+
 // The draws of a staged tile: one lane per agent (FP32 from the LDS table,
 // flagged draws re-resolved in FP64 by their wavefront), or every draw in
 // FP64 on a fallback tile.  The record of the tile's k-th agent (its cell in
 // the tile and the window slot it chose; the middle slot when it stays) goes
 // to slot k of the tile's segment, and the segment count is the tile's agent
-// count.  Ends with a workgroup barrier after which only thread 0 touches the
-// LDS counters.
-template <int V, int TX, bool DEBUG>
+// count.  HET: agent k reads its field's window (Em + field * win) and
+// reaches only its own disc dx^2 + dy^2 <= vr^2 (the other slots weigh an
+// exact 0); a field for which the tile is a fallback tile draws in FP64.
+// Ends with a workgroup barrier after which only thread 0 touches the LDS
+// counters.
+template <int V, int TX, bool DEBUG, bool HET>
 __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, TX> &tg, int tile,
-                                            const float *Em, TileLists &sh, int step)
+                                            const float *Em, TileLists &sh, int step,
+                                            const HetView &hv)
 {
     using T = TileGeom<V, TX>;
     constexpr int SIDE = T::SIDE, P = T::P, Hc = T::Hc;
@@ -574,20 +610,36 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
         const int ly = (int)((unsigned)l / P);
         return (ly - V) * TX + (l - ly * P - Hc);
     };
+    auto cell_of = [&](int l) {
+        const int ly = (int)((unsigned)l / P);
+        return (tg.gy0 + ly) * s.Wp + tg.gx0 + (l - ly * P);
+    };
+    // agent k's field, window, floor field, reach and fallback flag
+    auto agent_view = [&](int k, int &vr, const float *&E, const double *&S, bool &fb) {
+        vr = V;
+        E = Em;
+        S = s.S;
+        fb = false;
+        if constexpr (HET) {
+            const int gv = hv.a_gv[k], g = gv >> 4;
+            vr = gv & 15;
+            E = Em + g * hv.win;
+            if (hv.Sf) S = hv.Sf + g * hv.field_cells;
+            fb = hv.fbf[g] != 0;
+        }
+    };
 
-    if (sh.fb) {
+    if (!HET && sh.fb) {
         // every draw of this tile in FP64, one lane per agent
         for (int base = 0; base < na; base += nthr) {
             const int k = base + tid;
             if (k < na) {
                 const int id = (int)(sh.a_pk[k] >> 12);
                 const int l = (int)(sh.a_pk[k] & 0xFFFu);
-                const int ly = (int)((unsigned)l / P);
-                const int gc = (tg.gy0 + ly) * s.Wp + tg.gx0 + (l - ly * P);
                 const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0,
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const int slot = resolve64_lane<V, DEBUG>(s, gc, id, u);
+                const int slot = resolve64_lane<V, DEBUG>(s, s.S, cell_of(l), id, u, V);
                 seg[k] = plan_rec(lcell_of(l), slot);
                 if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
                 if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
@@ -602,6 +654,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
     }
 
     // --- one lane per agent, FP32 from the LDS table
+    int n_fb = 0;                        // HET: draws of this thread on fallback fields
     for (int base = 0; base < na; base += nthr) {
         const int k = base + tid;
         bool flagged = false;
@@ -609,16 +662,31 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             const int id = (int)(sh.a_pk[k] >> 12);
             const int l = (int)(sh.a_pk[k] & 0xFFFu);
             const float ec = sh.a_ec[k];
-
-            const Window<V, P> win(Em, l - V * P - V);     // origin (dy, dx) = (-V, -V)
+            int vr;
+            const float *E;
+            const double *S;
+            bool fbk;
+            agent_view(k, vr, E, S, fbk);
+            if (HET && fbk) {
+                const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0,
+                                                   kseed1);
+                const float u = (float)(x0 >> 8) * 0x1p-24f;
+                const int slot = resolve64_lane<V, DEBUG>(s, S, cell_of(l), id, u, vr);
+                seg[k] = plan_rec(lcell_of(l), slot);
+                if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
+                if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
+                ++n_fb;
+            } else {
+            const int vr2 = vr * vr;
+            const Window<V, P> win(E, l - V * P - V);         // origin (dy, dx) = (-V, -V)
             float Rs[SIDE], row0[SIDE], row1[SIDE];
-            load_row<V, P, 0>(win, ec, row0);
-            load_row<V, P, 1>(win, ec, row1);
+            load_row<V, P, 0, HET>(win, ec, vr2, row0);
+            load_row<V, P, 1, HET>(win, ec, vr2, row1);
             __builtin_amdgcn_sched_barrier(0);
             // the draw's counter-based word overlaps the first rows' LDS reads
             const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0, kseed1);
             __builtin_amdgcn_sched_barrier(0);
-            RowPipe<V, P, 0>::run(win, ec, Rs, row0, row1);
+            RowPipe<V, P, 0, HET>::run(win, ec, vr2, Rs, row0, row1);
             float Pr[SIDE + 1];
             Pr[0] = 0.0f;
             Pr[1] = Rs[0];
@@ -649,6 +717,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             for (int d = 0; d < SIDE; ++d) rv[d] = rb[d];
             // (the own cell is the middle slot, d = V, of the middle row)
             const bool own_row = rs == V;
+            const int rdy2 = (rs - V) * (rs - V);
             const float thr = eps * Wsum;
             float Q = 0.0f;
             float margin = fabsf(tau - Ps);                  // smallest |tau - C| (debug output)
@@ -657,7 +726,8 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
 #pragma unroll
             for (int d = 0; d < SIDE; ++d) {
                 if (d <= 2 * as) {
-                    const float val = (d == V && own_row) ? ec : rv[d];
+                    float val = (d == V && own_row) ? ec : rv[d];
+                    if constexpr (HET) val = (d - as) * (d - as) + rdy2 <= vr2 ? val : 0.0f;
                     Q = Q + val;
                     const float C = Ps + Q;
                     const float diff = tau - C;
@@ -674,20 +744,20 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 // FP32 CDF at every disc slot exactly as the draw forms it
                 // (row prefix Pr plus the sequential in-row sum), and the
                 // total W in the window's last slot, a corner outside the disc
+                auto wt = [&](int dx, int dy) {
+                    if (dx == 0 && dy == 0) return ec;
+                    return dx * dx + dy * dy <= vr2 ? E[l + dy * P + dx] : 0.0f;
+                };
                 float emax = ec;
                 for (int dy = -V; dy <= V; ++dy)
                     for (int dx = -V; dx <= V; ++dx)
-                        if (dx * dx + dy * dy <= V * V && !(dx == 0 && dy == 0))
-                            emax = fmaxf(emax, Em[l + dy * P + dx]);
+                        if (dx * dx + dy * dy <= V * V) emax = fmaxf(emax, wt(dx, dy));
                 if (s.dbg_w) {
                     float *wd = s.dbg_w + (size_t)id * SIDE * SIDE;
                     for (int dy = -V; dy <= V; ++dy)
-                        for (int dx = -V; dx <= V; ++dx) {
-                            float wv = 0.0f;
-                            if (dx * dx + dy * dy <= V * V)
-                                wv = ((dx == 0 && dy == 0) ? ec : Em[l + dy * P + dx]) / emax;
-                            wd[(dy + V) * SIDE + dx + V] = wv;
-                        }
+                        for (int dx = -V; dx <= V; ++dx)
+                            wd[(dy + V) * SIDE + dx + V] =
+                                dx * dx + dy * dy <= V * V ? wt(dx, dy) / emax : 0.0f;
                 }
                 if (s.dbg_cdf) {
                     float *cd = s.dbg_cdf + (size_t)id * SIDE * SIDE;
@@ -695,8 +765,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                         const int a = (int)((row_half_widths(V) >> (4 * r)) & 15u);
                         float q = 0.0f;
                         for (int d = 0; d <= 2 * a; ++d) {
-                            const int dx = d - a, dy = r - V;
-                            q = q + ((dx == 0 && dy == 0) ? ec : Em[l + dy * P + dx]);
+                            q = q + wt(d - a, r - V);
                             cd[r * SIDE + (V - a) + d] = Pr[r] + q;
                         }
                     }
@@ -707,6 +776,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             }
             if (!flag) seg[k] = plan_rec(lcell_of(l), rs * SIDE + (ks - as + V));
             flagged = flag;
+            }
         }
 
         // FP64 re-resolve of this wavefront's flagged draws, one draw at a
@@ -720,16 +790,20 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const int kk = base + (tid & ~63) + src;
                 const int fid = (int)(sh.a_pk[kk] >> 12);
                 const int l = (int)(sh.a_pk[kk] & 0xFFFu);
-                const int ly = (int)((unsigned)l / P);
-                const int gc = (tg.gy0 + ly) * s.Wp + tg.gx0 + (l - ly * P);
+                int vr;
+                const float *E;
+                const double *S;
+                bool fbk;
+                agent_view(kk, vr, E, S, fbk);
                 const uint32_t x0 = plan_draw_word((uint32_t)fid, (uint32_t)step, scn, kseed0,
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const int slot = resolve64_wave<V>(s, gc, u, lane, Em, l, P);
+                const int slot = resolve64_wave<V>(s, S, cell_of(l), u, lane, E, l, P, vr);
                 if (lane == 0) seg[kk] = plan_rec(lcell_of(l), slot);
             }
         }
     }
+    if (HET && n_fb) atomicAdd(&s.stat[S_FALLBACK], (unsigned long long)n_fb);
     __syncthreads();
     if (tid == 0) {
         const int nf = sh.n_flag;
@@ -749,7 +823,7 @@ __device__ __forceinline__ void plan_tile(const SlotDev &s, int tile, PlanShared
     int step = 0;
     if (!stage_tile<V, TX>(s, tg, tile, sh.Em, sh.L, step)) return;
     if (tile == 0 && threadIdx.x < 4) s.ctr[C_BAR + threadIdx.x] = 0;   // fresh motion barriers
-    plan_agents<V, TX, DEBUG>(s, tg, tile, sh.Em, sh.L, step);
+    plan_agents<V, TX, DEBUG, false>(s, tg, tile, sh.Em, sh.L, step, HetView{});
 }
 
 template <int V, bool DEBUG>

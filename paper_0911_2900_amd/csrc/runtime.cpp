@@ -64,11 +64,8 @@ struct Slot {
     int host_steps = 0;          // steps launched (== device step once the stream drains)
     bool planned = false;        // a plan was launched after the last motion phase
     int n_agents = 0;
-    uint8_t *vi = nullptr;       // device: per-agent speeds (NULL: every agent has v_max)
-    uint8_t *fi = nullptr;       // device: per-agent floor field (NULL: one field for all)
-    const double *Sf = nullptr;  // device: the exit groups' floor fields, field_cells apart
-    long field_cells = 0;
-    bool het = false;            // planned by the FP64 per-agent kernel (vi or fi set)
+    fk::HetDev hd{};             // device: per-agent speeds and several fields (plan_het.hip)
+    bool het = false;            // planned by the per-agent kernel (speeds or fields)
     // region counts (fast_set_regions)
     fk::RegionDev rhost{};       // host copy of the job
     fk::RegionDev *rdev = nullptr;  // device: the job, then its series
@@ -409,7 +406,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
                  // workgroups, each handing over at most MOVE_SOLO_MAX movers
                  o_hand = take((size_t)motion_group(b.n) * fk::MOVE_SOLO_MAX * sizeof(fk::Mover)),
                  o_vi = take(b.vi.size()), o_fi = take(b.fi.size()),
-                 o_Sf = take(b.Sf.size() * 8);
+                 o_Sf = take(b.Sf.size() * 8), o_Gf = take(b.Gf.size() * 4),
+                 o_tmf = take(b.tile_mf.size() * 4), o_fbf = take(b.tile_fbf.size());
     void *block = nullptr;
     st = dev_alloc(c, off, &block);
     if (st) return st;
@@ -481,6 +479,9 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     cp(o_vi, b.vi.data(), b.vi.size());
     cp(o_fi, b.fi.data(), b.fi.size());
     cp(o_Sf, b.Sf.data(), b.Sf.size() * 8);
+    cp(o_Gf, b.Gf.data(), b.Gf.size() * 4);
+    cp(o_tmf, b.tile_mf.data(), b.tile_mf.size() * 4);
+    cp(o_fbf, b.tile_fbf.data(), b.tile_fbf.size());
     if (e == hipSuccess) e = hipMemcpy(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         dev_free(c, block, off);
@@ -498,13 +499,17 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     s.mitems = (uint32_t *)(base + o_mitems);
     s.group = group;
     s.n_items = (int)ntiles;
-    s.n_fb_tiles = b.n_fb;
+    s.n_fb_tiles = b.Gf.empty() ? b.n_fb : b.n_fbf;   // several fields: (tile, field) pairs
     s.n_agents = b.n;
-    s.vi = b.vi.empty() ? nullptr : (uint8_t *)(base + o_vi);
-    s.fi = b.fi.empty() ? nullptr : (uint8_t *)(base + o_fi);
-    s.Sf = b.Sf.empty() ? nullptr : (const double *)(base + o_Sf);
-    s.field_cells = (long)cells;
-    s.het = s.vi || s.fi;
+    s.hd.vi = b.vi.empty() ? nullptr : (const uint8_t *)(base + o_vi);
+    s.hd.fi = b.fi.empty() ? nullptr : (const uint8_t *)(base + o_fi);
+    s.hd.Sf = b.Sf.empty() ? nullptr : (const double *)(base + o_Sf);
+    s.hd.Gf = b.Gf.empty() ? nullptr : (const uint32_t *)(base + o_Gf);
+    s.hd.tile_mf = b.tile_mf.empty() ? nullptr : (const int32_t *)(base + o_tmf);
+    s.hd.tile_fbf = b.tile_fbf.empty() ? nullptr : (const uint8_t *)(base + o_fbf);
+    s.hd.field_cells = (long)cells;
+    s.hd.nf = s.hd.Gf ? (int)(b.Sf.size() / cells) : 1;
+    s.het = s.hd.vi || s.hd.Gf;
     *handle = h;
     return FAST_OK;
 }
@@ -681,8 +686,8 @@ hipError_t launch_het_members(fast_ctx *c, const std::vector<int32_t> &het)
 {
     for (int32_t h : het) {
         const Slot &s = c->slots[h];
-        const hipError_t e = fk_launch_plan_het(&s.dev, s.vi, s.fi, s.Sf, s.field_cells, s.n_items,
-                                                c->stream, nullptr, nullptr);
+        const hipError_t e = fk_launch_plan_het(&s.dev, &s.hd, s.n_items, 0, c->stream, nullptr,
+                                                nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1115,8 +1120,7 @@ fast_status fast_plan_step(fast_ctx *c, int32_t h)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     next_timing_pair(c, &e0, &e1);
     if (s->het)
-        HIP_TRY(fk_launch_plan_het(&s->dev, s->vi, s->fi, s->Sf, s->field_cells, s->n_items,
-                                   c->stream, e0, e1));
+        HIP_TRY(fk_launch_plan_het(&s->dev, &s->hd, s->n_items, 0, c->stream, e0, e1));
     else
         HIP_TRY(fk_launch_plan_one(&s->dev, s->n_items, 0, c->stream, e0, e1));
     s->planned = true;
@@ -1394,8 +1398,6 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     std::lock_guard<std::recursive_mutex> g(c->mu);
     Slot *s = get_slot(c, h);
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
-    if (s->het)
-        return fail(FAST_E_INVALID, "scenario %d has per-agent speeds or fields: no debug dump", h);
     const int n = std::max(s->n_agents, 1);
     const int side = 2 * s->dev.v + 1;
     const size_t bw = align_up((size_t)n * side * side * 4, 256), bf = align_up((size_t)n, 256),
@@ -1410,7 +1412,9 @@ fast_status fast_debug_plan(fast_ctx *c, int32_t h, float *w32, uint8_t *flag, f
     sd.dbg_margin = (float *)((char *)block + bw + bf);
     sd.dbg_cdf = (float *)((char *)block + bw + bf + bm);
     hipError_t e = hipMemsetAsync(block, 0, total, c->stream);
-    if (e == hipSuccess) e = fk_launch_plan_one(&sd, s->n_items, 1, c->stream, nullptr, nullptr);
+    if (e == hipSuccess)
+        e = s->het ? fk_launch_plan_het(&sd, &s->hd, s->n_items, 1, c->stream, nullptr, nullptr)
+                   : fk_launch_plan_one(&sd, s->n_items, 1, c->stream, nullptr, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) {
         s->planned = true;
