@@ -48,6 +48,8 @@ class _State(ctypes.Structure):
         ("occ", ctypes.c_void_p), ("exited", ctypes.c_int64),
         ("vi", ctypes.c_void_p),
         ("Sf", ctypes.c_void_p), ("fi", ctypes.c_void_p),
+        ("Tr", ctypes.c_void_p), ("dep", ctypes.c_void_p),
+        ("k_d", ctypes.c_double), ("decay", ctypes.c_double), ("diffusion", ctypes.c_double),
     ]
 
 
@@ -135,7 +137,7 @@ class Sim:
 
     def __init__(self, cell_type: np.ndarray, v: int, k_s: float, seed: int, scn: int,
                  n_agents: int | None = None, agent_xy=None, agent_v=None,
-                 exit_field=None, agent_field=None):
+                 exit_field=None, agent_field=None, trail=None):
         self.type, self.S, self.a, self.b = floor_field(cell_type)
         self.H, self.W = self.type.shape
         if agent_xy is None:
@@ -186,6 +188,14 @@ class Sim:
                 np.stack([floor_field_of(self.type, ef, g) for g in range(G)]))
             self._st.Sf = _ptr(self.Sf)
             self._st.fi = _ptr(self.agent_field) if self.n else None
+        # dynamic floor field (reading R14): trail = (k_D, delta, alpha)
+        self.Tr = self.dep = None
+        if trail is not None:
+            k_d, decay, diffusion = (float(x) for x in trail)
+            self.Tr = np.zeros((self.H, self.W), dtype=np.float64)
+            self.dep = np.zeros((self.H, self.W), dtype=np.int32)
+            self._st.Tr, self._st.dep = _ptr(self.Tr), _ptr(self.dep)
+            self._st.k_d, self._st.decay, self._st.diffusion = k_d, decay, diffusion
         if lib().oracle_reset_occ(ctypes.byref(self._st)) != 0:
             raise ValueError("invalid agent positions")
 
@@ -231,8 +241,14 @@ class Sim:
             raise RuntimeError("plan failed")
 
     def move(self):
+        """One motion phase (with a trail field, R14's update closes it)."""
         if lib().oracle_move_step(ctypes.byref(self._st)) != 0:
             raise RuntimeError("move failed")
+
+    def trail_update(self):
+        """R14's update of the trail field alone (deposits in self.dep)."""
+        if self.Tr is None or lib().oracle_trail_update(ctypes.byref(self._st)) != 0:
+            raise RuntimeError("no trail field")
 
     def end_step(self):
         self._st.step += 1

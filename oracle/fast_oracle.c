@@ -51,6 +51,17 @@
  *      the exit cells tagged g alone, +inf where those exits do not reach;
  *      agent i weighs its window with its own field in R2; walls stay those
  *      of R7 (all exits), and R6 removes an agent at any exit cell.
+ *  R14 dynamic floor field (one of the couplings k_other that Sec. 2 sets to
+ *      0; the paper cites its definition without restating it): every cell
+ *      holds a trail value T >= 0, zero at the start.  An agent that leaves
+ *      the cell it started the step on (it moves, or it exits) adds 1 to that
+ *      cell's deposit count during the motion phase.  After the motion phase
+ *      every non-wall cell takes T' = (1 - delta) * ((1 - alpha) * T +
+ *      (alpha / 8) * N) + deposits, N the sum of T over its 8 neighbours in
+ *      raster order (walls and cells off the grid count 0); walls keep 0; the
+ *      deposits restart at 0.  R2's weight becomes w(t) = exp(k_S * (S(c) -
+ *      S(t)) + k_D * (T(t) - T(c))): agents lean towards cells others have
+ *      just left.  k_D = 0 leaves R2's weights unchanged bit for bit.
  *
  * Philox4x32-10 follows its published definition: J. K. Salmon, M. A. Moraes,
  * R. O. Dror, D. E. Shaw, "Parallel random numbers: as easy as 1, 2, 3",
@@ -321,6 +332,9 @@ typedef struct {
                                another (oracle_floor_field_of)                      */
     const uint8_t *fi;      /* optional, n: the field agent i follows; NULL: every
                                agent follows S                                      */
+    double *Tr;             /* optional, W*H: the trail field of R14; NULL: none  */
+    int32_t *dep;           /* W*H deposit counts of the running motion phase (with Tr) */
+    double k_d, decay, diffusion;  /* R14's k_D, delta, alpha                      */
 } oracle_state;
 
 /* Rebuilds occupancy from positions; returns -1 if an agent is off-grid, on
@@ -377,8 +391,12 @@ int32_t oracle_plan_agent(const oracle_state *st, int32_t i, double *w_out,
             if (in_reach && in_grid) {
                 int64_t t = (int64_t)ty * W + tx;
                 int free_or_own = st->occ[t] == -1 || t == c;
-                if (st->type[t] != CELL_WALL && free_or_own)
-                    wt = exp(st->k_s * (S[c] - S[t]));
+                if (st->type[t] != CELL_WALL && free_or_own) {
+                    if (st->Tr)     /* R14 */
+                        wt = exp(st->k_s * (S[c] - S[t]) + st->k_d * (st->Tr[t] - st->Tr[c]));
+                    else
+                        wt = exp(st->k_s * (S[c] - S[t]));
+                }
             }
             w[slot] = wt;
         }
@@ -480,6 +498,8 @@ int oracle_plan_step_threads(oracle_state *st, int32_t threads)
 /* Motion phase (readings R4-R6).                                            */
 /* ------------------------------------------------------------------------- */
 
+int oracle_trail_update(oracle_state *st);
+
 typedef struct { uint32_t key; int32_t id; } order_item;
 
 static int order_cmp(const void *pa, const void *pb)
@@ -514,6 +534,7 @@ static void move_agent(oracle_state *st, int32_t i)
             if (st->type[(int64_t)ny * W + px] == CELL_WALL) break;
         }
         st->occ[(int64_t)py * W + px] = -1;
+        if (k == 1 && st->Tr) st->dep[(int64_t)cy * W + cx] += 1;   /* R14: it leaves */
         if (st->type[nc] == CELL_EXIT) {
             st->alive[i] = 0;
             st->x[i] = -1; st->y[i] = -1;
@@ -527,7 +548,36 @@ static void move_agent(oracle_state *st, int32_t i)
     st->x[i] = px; st->y[i] = py;
 }
 
-/* One motion phase: agents one after another in the order of reading R4. */
+/* The trail update of reading R14 that closes a motion phase: every non-wall
+ * cell from the values before the update, then the deposits restart. */
+int oracle_trail_update(oracle_state *st)
+{
+    const int32_t W = st->W, H = st->H;
+    const double keep = 1.0 - st->decay, stay = 1.0 - st->diffusion, share = st->diffusion / 8.0;
+    double *nt = malloc(sizeof(double) * (size_t)W * (size_t)H);
+    if (!nt) return -1;
+    for (int32_t y = 0; y < H; ++y)
+        for (int32_t x = 0; x < W; ++x) {
+            const int64_t c = (int64_t)y * W + x;
+            if (st->type[c] == CELL_WALL) { nt[c] = 0.0; continue; }
+            double nb = 0.0;
+            for (int32_t dy = -1; dy <= 1; ++dy)
+                for (int32_t dx = -1; dx <= 1; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    const int32_t qx = x + dx, qy = y + dy;
+                    if (qx < 0 || qy < 0 || qx >= W || qy >= H) continue;
+                    nb = nb + st->Tr[(int64_t)qy * W + qx];    /* walls hold 0 */
+                }
+            nt[c] = keep * (stay * st->Tr[c] + share * nb) + (double)st->dep[c];
+        }
+    memcpy(st->Tr, nt, sizeof(double) * (size_t)W * (size_t)H);
+    for (int64_t c = 0; c < (int64_t)W * H; ++c) st->dep[c] = 0;
+    free(nt);
+    return 0;
+}
+
+/* One motion phase: agents one after another in the order of reading R4,
+ * then (with a trail field) R14's update. */
 int oracle_move_step(oracle_state *st)
 {
     int32_t n = st->n, k = 0;
@@ -546,6 +596,7 @@ int oracle_move_step(oracle_state *st)
         move_agent(st, i);
     }
     free(ord);
+    if (st->Tr) return oracle_trail_update(st);
     return 0;
 }
 
