@@ -122,6 +122,22 @@ typedef struct {
     const uint8_t *agent_field;  /* host, n_agents fields in 0..n_fields-1; an agent
                                     must stand where its field is finite.  NULL when
                                     n_fields <= 1                                    */
+    double k_d;                  /* dynamic floor field, one of the couplings k_other
+                                    that Sec. 2 sets to 0 (this library's reading of
+                                    it): every cell holds a trail value T, zero at
+                                    the start; an agent that leaves the cell it
+                                    started the step on deposits 1 there; after each
+                                    motion phase every non-wall cell takes
+                                    T' = (1 - trail_decay) ((1 - trail_diffusion) T
+                                    + (trail_diffusion / 8) N) + deposits, N the sum
+                                    of its 8 neighbours (walls 0); the planning
+                                    weight becomes exp(k_S (S(c) - S(t)) +
+                                    k_d (T(t) - T(c))).  The field is kept when any of
+                                    k_d, trail_decay, trail_diffusion is nonzero
+                                    (k_d = 0 then gives the static model's weights).
+                                    k_d >= 0 and finite; not with n_fields >= 2    */
+    double trail_decay;          /* delta in 0..1                                    */
+    double trail_diffusion;      /* alpha in 0..1                                    */
 } fast_scenario_desc;
 
 /* Counters of one scenario. */
@@ -218,6 +234,15 @@ fast_status fast_move_batch(fast_ctx *ctx, const int32_t *handles, int32_t n);
  * the chosen window slot of the agent's start cell). */
 fast_status fast_get_state(fast_ctx *ctx, int32_t handle, int32_t *xy, uint8_t *alive,
                            int32_t *desired, int32_t *step, int32_t *n_active);
+
+/* Copies the trail field T of a scenario that keeps one (descriptor fields
+ * k_d, trail_decay, trail_diffusion; the dynamic floor field that the paper
+ * counts among the couplings k_other of Sec. 2) as it stands for the next
+ * planning phase: out[y*width + x], FP64, capacity >= width*height.  Each
+ * motion phase's deposits and the update that follows are included.
+ * Synchronises the stream.  FAST_E_INVALID for a scenario without the field
+ * or a short buffer. */
+fast_status fast_get_trail(fast_ctx *ctx, int32_t handle, double *out, int64_t capacity);
 
 /* Counters of a scenario (synchronises the stream). */
 fast_status fast_get_stats(fast_ctx *ctx, int32_t handle, fast_stats *out);

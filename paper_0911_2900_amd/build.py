@@ -19,7 +19,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["plan_batch.hip", "plan_one.hip", "motion.hip", "stream.hip", "cus.hip", "regions.hip", "scratch.hip",
+SOURCES = ["plan_batch.hip", "plan_one.hip", "motion.hip", "stream.hip", "cus.hip", "regions.hip", "scratch.hip", "trail.hip",
            "builder.cpp",
            "runtime.cpp"]
 # plan_fixed.hip and plan_het.hip are compiled once per v_max (PLAN_V), into

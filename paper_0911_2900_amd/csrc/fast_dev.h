@@ -123,7 +123,7 @@ struct SlotDev {
     uint32_t *D;             // Wp*Hp: exp table bits | D_OCC while occupied
     const double *S;         // Wp*Hp
     const int32_t *tile_m;   // (ntx+2)*(nty+2), a ring of zeros around
-    const uint8_t *tile_fb;  // ntx*nty
+    uint8_t *tile_fb;        // ntx*nty (rewritten every step with a trail field)
     int32_t *occ;            // Wp*Hp
     unsigned long long *res0;// Wp*Hp, reservations of even rounds
     unsigned long long *res1;// Wp*Hp, reservations of odd rounds
@@ -133,6 +133,11 @@ struct SlotDev {
     Mover *hand;             // (motion workgroups)*MOVE_SOLO_MAX: movers handed to workgroup 0
     int32_t *ctr;            // C_NCTR
     unsigned long long *stat;// S_NSTAT
+    // dynamic floor field (trail; null when the scenario has none): the trail
+    // of step s in Tr + (s & 1) Wp Hp, deposits of the running motion phase
+    double *Tr;              // 2 Wp*Hp
+    int32_t *dep;            // Wp*Hp
+    double k_d, t_decay, t_diff;
     float *dbg_w;            // optional debug outputs (null in normal runs)
     uint8_t *dbg_flag;
     float *dbg_margin;

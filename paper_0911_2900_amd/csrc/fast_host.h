@@ -89,5 +89,6 @@ extern "C" hipError_t fk_launch_plan_het(const fk::SlotDev *slot, const fk::HetD
 extern "C" hipError_t fk_launch_count(const fk::RegionDev *jobs, int n_jobs, int max_regions,
                                       hipStream_t stream);
 extern "C" hipError_t fk_scratch_ptr(int device, void **out);
+extern "C" hipError_t fk_launch_trail(const fk::SlotDev *slot, int n_tiles, hipStream_t stream);
 extern "C" hipError_t fk_launch_stream(float4 *base, size_t n4, hipStream_t stream,
                                        hipEvent_t start, hipEvent_t stop);

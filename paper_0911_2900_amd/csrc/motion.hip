@@ -329,6 +329,7 @@ __device__ __forceinline__ bool commit_one(const SlotDev &s, const unsigned long
         st_agent(&s.occ[at], id);
         atomicOr(&s.D[at], D_OCC);
     }
+    if (s.dep && (gone || at != c)) atomicAdd(&s.dep[c], 1);   // it left its cell: a trail deposit
     return false;
 }
 
@@ -482,6 +483,14 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
     const unsigned long long tagw0 = (unsigned long long)(tag + 1) << TAG_SHIFT;
     if (g == 0 && tid == 0)   // agents planned this step, for the throughput counters
         atomicAdd(&s.stat[S_PLANNED], (unsigned long long)s.ctr[C_NACTIVE]);
+    // a trail field: this phase's deposits start from 0 (agent-scope stores,
+    // complete before the first group barrier, after which movers commit)
+    if (s.dep) {
+        const long cells = (long)s.Wp * s.Hp;
+        for (long i = cells * g / G + tid; i < cells * (g + 1) / G; i += blockDim.x)
+            st_agent(&s.dep[i], 0);
+        __builtin_amdgcn_s_waitcnt(0);   // (a one-workgroup barrier waits for none)
+    }
 
     // gather this workgroup's movers from the planned records
     int n = 0;

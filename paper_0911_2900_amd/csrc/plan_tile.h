@@ -122,13 +122,21 @@ __device__ __forceinline__ bool reach_ok(const SlotDev &s, int gc, int t, int dx
 // the range of the weights themselves).
 // S: the agent's floor field (the scenario's, or its exit group's); vr: its
 // maximum speed (V unless it has one of its own).
+// The FP64 weight of window cell t for an agent on cell gc: exp(k_S (S(c) -
+// S(t))), times exp(k_D (T(t) - T(c))) with a trail field T (evaluated as
+// one exponent, in the order the model's definition writes it).
+__device__ __forceinline__ double weight64(const SlotDev &s, const double *__restrict__ S,
+                                           const double *__restrict__ T, int gc, int t)
+{
+    if (T) return exp(s.k_s * (S[gc] - S[t]) + s.k_d * (T[t] - T[gc]));
+    return exp(s.k_s * (S[gc] - S[t]));
+}
+
 template <int V, bool DEBUG>
-__device__ int resolve64_lane(const SlotDev &s, const double *__restrict__ S, int gc, int id,
-                              float u32, int vr)
+__device__ int resolve64_lane(const SlotDev &s, const double *__restrict__ S,
+                              const double *__restrict__ T, int gc, int id, float u32, int vr)
 {
     constexpr int SIDE = 2 * V + 1;
-    const double Sc = S[gc];
-    const double ks = s.k_s;
     double C = 0.0, wmax = 0.0;
 #pragma unroll 1
     for (int dy = -V; dy <= V; ++dy)
@@ -136,7 +144,7 @@ __device__ int resolve64_lane(const SlotDev &s, const double *__restrict__ S, in
         for (int dx = -V; dx <= V; ++dx) {
             const int t = gc + dy * s.Wp + dx;
             if (reach_ok(s, gc, t, dx, dy, vr)) {
-                const double w = exp(ks * (Sc - S[t]));
+                const double w = weight64(s, S, T, gc, t);
                 C = C + w;
                 wmax = fmax(wmax, w);
             }
@@ -149,7 +157,7 @@ __device__ int resolve64_lane(const SlotDev &s, const double *__restrict__ S, in
                 const int t = gc + dy * s.Wp + dx;
                 if (reach_ok(s, gc, t, dx, dy, vr))
                     s.dbg_w[(size_t)id * SIDE * SIDE + (dy + V) * SIDE + dx + V] =
-                        (float)(exp(ks * (Sc - S[t])) / wmax);
+                        (float)(weight64(s, S, T, gc, t) / wmax);
             }
     }
     const double tau = (double)u32 * C;
@@ -160,7 +168,7 @@ __device__ int resolve64_lane(const SlotDev &s, const double *__restrict__ S, in
         for (int dx = -V; dx <= V; ++dx) {
             const int t = gc + dy * s.Wp + dx;
             if (reach_ok(s, gc, t, dx, dy, vr)) {
-                C2 = C2 + exp(ks * (Sc - S[t]));
+                C2 = C2 + weight64(s, S, T, gc, t);
                 if (tau < C2) return (dy + V) * SIDE + dx + V;
             }
         }
@@ -247,8 +255,9 @@ __device__ __forceinline__ double lane_value(double x, int j)
 // or occupied, so only the floor field is read, from global memory (the draws
 // that come here are rare).  Returns the chosen raster slot of the window.
 template <int V>
-__device__ int resolve64_wave(const SlotDev &s, const double *__restrict__ S, int gc, float u32,
-                              int lane, const float *Em, int l, int P, int vr)
+__device__ int resolve64_wave(const SlotDev &s, const double *__restrict__ S,
+                              const double *__restrict__ T, int gc, float u32, int lane,
+                              const float *Em, int l, int P, int vr)
 {
     // The lane index passes through an empty asm here, inside the rare branch
     // that calls this: otherwise the compiler hoists the lane-dependent set-up
@@ -257,8 +266,6 @@ __device__ int resolve64_wave(const SlotDev &s, const double *__restrict__ S, in
     asm volatile("" : "+v"(lane));
     constexpr int SIDE = 2 * V + 1;
     const double NEAR = s.near64;
-    const double Sc = S[gc];
-    const double ks = s.k_s;
     const double u = (double)u32;
     if constexpr (disc_count(V) <= 64) {
         constexpr int ND = disc_count(V);
@@ -267,7 +274,7 @@ __device__ int resolve64_wave(const SlotDev &s, const double *__restrict__ S, in
         disc_slot<V>(lane, dx, dy);
         if (lane < ND && dx * dx + dy * dy <= vr * vr &&
             ((dx == 0 && dy == 0) || Em[l + dy * P + dx] != 0.0f))
-            w = exp(ks * (Sc - S[gc + dy * s.Wp + dx]));
+            w = weight64(s, S, T, gc, gc + dy * s.Wp + dx);
         const double Cp = wave_scan64(w);
         const double Wp = lane_value(Cp, ND - 1);
         const double tp = u * Wp;
@@ -299,7 +306,7 @@ __device__ int resolve64_wave(const SlotDev &s, const double *__restrict__ S, in
                 const int dy = j / SIDE - V, dx = j % SIDE - V;
                 const bool own = dx == 0 && dy == 0;
                 if (dx * dx + dy * dy <= vr * vr && (own || Em[l + dy * P + dx] != 0.0f))
-                    w[h] = exp(ks * (Sc - S[gc + dy * s.Wp + dx]));
+                    w[h] = weight64(s, S, T, gc, gc + dy * s.Wp + dx);
             }
         }
         const double C0 = wave_scan64(w[0]);
@@ -610,6 +617,8 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
         const int ly = (int)((unsigned)l / P);
         return (ly - V) * TX + (l - ly * P - Hc);
     };
+    // the trail of this step, when the scenario keeps one
+    const double *Tcur = s.Tr ? s.Tr + (long)(step & 1) * ((long)s.Wp * s.Hp) : nullptr;
     auto cell_of = [&](int l) {
         const int ly = (int)((unsigned)l / P);
         return (tg.gy0 + ly) * s.Wp + tg.gx0 + (l - ly * P);
@@ -639,7 +648,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0,
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const int slot = resolve64_lane<V, DEBUG>(s, s.S, cell_of(l), id, u, V);
+                const int slot = resolve64_lane<V, DEBUG>(s, s.S, Tcur, cell_of(l), id, u, V);
                 seg[k] = plan_rec(lcell_of(l), slot);
                 if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
                 if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
@@ -671,7 +680,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const uint32_t x0 = plan_draw_word((uint32_t)id, (uint32_t)step, scn, kseed0,
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const int slot = resolve64_lane<V, DEBUG>(s, S, cell_of(l), id, u, vr);
+                const int slot = resolve64_lane<V, DEBUG>(s, S, Tcur, cell_of(l), id, u, vr);
                 seg[k] = plan_rec(lcell_of(l), slot);
                 if (DEBUG && s.dbg_flag) s.dbg_flag[id] = 2;
                 if (DEBUG && s.dbg_margin) s.dbg_margin[id] = -1.0f;
@@ -798,7 +807,7 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
                 const uint32_t x0 = plan_draw_word((uint32_t)fid, (uint32_t)step, scn, kseed0,
                                                    kseed1);
                 const float u = (float)(x0 >> 8) * 0x1p-24f;
-                const int slot = resolve64_wave<V>(s, S, cell_of(l), u, lane, E, l, P, vr);
+                const int slot = resolve64_wave<V>(s, S, Tcur, cell_of(l), u, lane, E, l, P, vr);
                 if (lane == 0) seg[kk] = plan_rec(lcell_of(l), slot);
             }
         }

@@ -84,6 +84,7 @@ struct Batch {
     fk::RegionDev *rjobs = nullptr;  // device: region-count jobs of the members that have them
     int n_rjobs = 0, max_regions = 0;
     std::vector<int32_t> het;        // members with per-agent speeds: a planning launch each
+    std::vector<int32_t> trails;     // members with a trail field: its update after motion
     void *block = nullptr;
     size_t bytes = 0;
     std::vector<int32_t> members;
@@ -97,6 +98,7 @@ struct BatchItems {
     std::vector<int32_t> order;
     std::vector<uint32_t> items, mitems;
     std::vector<int32_t> het;
+    std::vector<int32_t> trails;     // members with a trail field: its launches after motion
     std::vector<fk::RegionDev> rj;
     int v = 0, tx = 0, max_regions = 0;
 };
@@ -314,6 +316,12 @@ hipError_t stream_cus(hipStream_t s, int device, int *n_cus)
     return hipSuccess;
 }
 
+// The scenario keeps a trail field (the dynamic floor field of fast.h).
+bool has_trail(const fast_scenario_desc *d)
+{
+    return d->k_d != 0.0 || d->trail_decay != 0.0 || d->trail_diffusion != 0.0;
+}
+
 fast_status check_desc(const fast_scenario_desc *d)
 {
     if (!d) return fail(FAST_E_INVALID, "descriptor is NULL");
@@ -324,6 +332,14 @@ fast_status check_desc(const fast_scenario_desc *d)
         return fail(FAST_E_INVALID, "v_max %d outside 1..5", d->v_max);
     if (!(d->k_s >= 0.0) || !std::isfinite(d->k_s))
         return fail(FAST_E_INVALID, "k_s must be finite and >= 0");
+    if (!(d->k_d >= 0.0) || !std::isfinite(d->k_d))
+        return fail(FAST_E_INVALID, "k_d must be finite and >= 0");
+    if (!(d->trail_decay >= 0.0 && d->trail_decay <= 1.0) ||
+        !(d->trail_diffusion >= 0.0 && d->trail_diffusion <= 1.0))
+        return fail(FAST_E_INVALID, "trail_decay and trail_diffusion must lie in 0..1");
+    if (has_trail(d) && d->n_fields >= 2)
+        return fail(FAST_E_INVALID, "a trail field (k_d, trail_decay, trail_diffusion) does not "
+                    "combine with several floor fields");
     if (d->n_agents < 0 || d->n_agents > FAST_MAX_AGENTS)
         return fail(FAST_E_INVALID, "n_agents %d outside 0..%d", d->n_agents, FAST_MAX_AGENTS);
     if (d->tile_w || d->tile_h) {
@@ -408,6 +424,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
                  o_vi = take(b.vi.size()), o_fi = take(b.fi.size()),
                  o_Sf = take(b.Sf.size() * 8), o_Gf = take(b.Gf.size() * 4),
                  o_tmf = take(b.tile_mf.size() * 4), o_fbf = take(b.tile_fbf.size());
+    const bool trail = has_trail(d);
+    const size_t o_Tr = take(trail ? cells * 16 : 0), o_dep = take(trail ? cells * 4 : 0);
     void *block = nullptr;
     st = dev_alloc(c, off, &block);
     if (st) return st;
@@ -430,7 +448,14 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     sd.occ = (int32_t *)(base + o_occ);
     sd.cell = (const uint8_t *)(base + o_type);
     sd.tile_m = (const int32_t *)(base + o_tm);
-    sd.tile_fb = (const uint8_t *)(base + o_fb);
+    sd.tile_fb = (uint8_t *)(base + o_fb);
+    if (trail) {
+        sd.Tr = (double *)(base + o_Tr);
+        sd.dep = (int32_t *)(base + o_dep);
+        sd.k_d = d->k_d;
+        sd.t_decay = d->trail_decay;
+        sd.t_diff = d->trail_diffusion;
+    }
     sd.seg_cnt = (int32_t *)(base + o_scnt);
     sd.seg = (uint32_t *)(base + o_seg);
     sd.mv_a = (fk::Mover *)(base + o_ka);
@@ -482,6 +507,8 @@ fast_status upload_slot(fast_ctx *c, const fast_scenario_desc *d, const fh::Buil
     cp(o_Gf, b.Gf.data(), b.Gf.size() * 4);
     cp(o_tmf, b.tile_mf.data(), b.tile_mf.size() * 4);
     cp(o_fbf, b.tile_fbf.data(), b.tile_fbf.size());
+    if (trail && e == hipSuccess) e = hipMemset(base + o_Tr, 0, cells * 16);   // T of steps 0 and 1
+    if (trail && e == hipSuccess) e = hipMemset(base + o_dep, 0, cells * 4);
     if (e == hipSuccess) e = hipMemcpy(c->table + h, &sd, sizeof sd, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         dev_free(c, block, off);
@@ -608,6 +635,9 @@ fast_status batch_items(fast_ctx *c, const std::vector<int32_t> &hs, BatchItems 
         return c->slots[a].n_agents > c->slots[b].n_agents;
     });
     p.het.clear();
+    p.trails.clear();
+    for (int32_t h : p.order)
+        if (c->slots[h].dev.Tr) p.trails.push_back(h);
     p.v = p.tx = 0;
     bool first = true;
     for (int32_t h : p.order) {
@@ -650,6 +680,7 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     Batch b;
     b.members = hs;
     b.het = p.het;
+    b.trails = p.trails;
     b.v = p.v;
     b.tx = p.tx;
     b.max_regions = p.max_regions;
@@ -693,6 +724,17 @@ hipError_t launch_het_members(fast_ctx *c, const std::vector<int32_t> &het)
     return hipSuccess;
 }
 
+// The trail-field launches that close the motion phase of each listed member.
+hipError_t launch_trails(fast_ctx *c, const std::vector<int32_t> &trails)
+{
+    for (int32_t h : trails) {
+        const Slot &s = c->slots[h];
+        const hipError_t e = fk_launch_trail(&s.dev, s.n_items, c->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // One time step of a batch captured as a HIP graph: one planning launch over
 // every tile of every member, one motion launch over their workgroup groups.
 fast_status batch_graph(fast_ctx *c, Batch *b)
@@ -702,6 +744,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b)
     hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
     if (e1 == hipSuccess) e1 = launch_het_members(c, b->het);
     hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
+    if (e2 == hipSuccess) e2 = launch_trails(c, b->trails);
     if (e2 == hipSuccess) e2 = fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream);
     hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -743,6 +786,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
         HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr));
         HIP_TRY(launch_het_members(c, b->het));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
+        HIP_TRY(launch_trails(c, b->trails));
         HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream));
     }
     for (int32_t h : hs) c->slots[h].host_steps += steps;
@@ -1135,6 +1179,7 @@ fast_status fast_move_step(fast_ctx *c, int32_t h)
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     if (!s->planned) return fail(FAST_E_STATE, "scenario %d: motion without a plan of this step", h);
     HIP_TRY(fk_launch_move(c->table, s->mitems, s->group, c->stream));
+    HIP_TRY(fk_launch_trail(&s->dev, s->n_items, c->stream));
     if (s->n_regions) HIP_TRY(fk_launch_count(s->rdev, 1, s->n_regions, c->stream));
     s->planned = false;
     s->host_steps += 1;
@@ -1188,6 +1233,7 @@ fast_status fast_run_noalloc(fast_ctx *c, const int32_t *hs, int32_t n, int32_t 
                                nullptr));
         HIP_TRY(launch_het_members(c, p.het));
         HIP_TRY(fk_launch_move(c->table, mitems, (int)p.mitems.size(), c->stream));
+        HIP_TRY(launch_trails(c, p.trails));
         HIP_TRY(fk_launch_count(rjobs, (int)p.rj.size(), p.max_regions, c->stream));
     }
     for (int32_t h : v) c->slots[h].host_steps += steps;
@@ -1259,6 +1305,7 @@ fast_status fast_move_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     st = get_batch(c, v, &b);
     if (st) return st;
     HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
+    HIP_TRY(launch_trails(c, b->trails));
     HIP_TRY(fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream));
     for (int32_t h : v) {
         c->slots[h].planned = false;
@@ -1358,6 +1405,29 @@ fast_status fast_get_state(fast_ctx *c, int32_t h, int32_t *xy, uint8_t *alive, 
     Slot *s = get_slot(c, h);
     if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
     return read_state(c, s, xy, alive, desired, step, n_active);
+}
+
+fast_status fast_get_trail(fast_ctx *c, int32_t h, double *out, int64_t capacity)
+{
+    if (!c || !out) return fail(FAST_E_INVALID, "ctx or out is NULL");
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    Slot *s = get_slot(c, h);
+    if (!s) return fail(FAST_E_NOTFOUND, "unknown scenario handle %d", h);
+    const fk::SlotDev &d = s->dev;
+    if (!d.Tr) return fail(FAST_E_INVALID, "scenario %d keeps no trail field (k_d, trail_decay and trail_diffusion are 0)", h);
+    if (capacity < (int64_t)d.W * d.H)
+        return fail(FAST_E_INVALID, "out holds %lld doubles; the grid has %lld", (long long)capacity,
+                    (long long)d.W * d.H);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int32_t step = 0;
+    HIP_TRY(hipMemcpy(&step, d.ctr + fk::C_STEP, 4, hipMemcpyDeviceToHost));
+    const size_t cells = (size_t)d.Wp * d.Hp;
+    std::vector<double> t(cells);
+    HIP_TRY(hipMemcpy(t.data(), d.Tr + (size_t)(step & 1) * cells, cells * 8, hipMemcpyDeviceToHost));
+    for (int y = 0; y < d.H; ++y)
+        for (int x = 0; x < d.W; ++x)
+            out[(size_t)y * d.W + x] = t[(size_t)(y + d.pad) * d.Wp + x + d.pad];
+    return FAST_OK;
 }
 
 fast_status fast_get_stats(fast_ctx *c, int32_t h, fast_stats *out)

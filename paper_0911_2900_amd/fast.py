@@ -36,6 +36,8 @@ class ScenarioDesc(ctypes.Structure):
         ("agent_v", ctypes.c_void_p),
         ("n_fields", ctypes.c_int32), ("exit_field", ctypes.c_void_p),
         ("agent_field", ctypes.c_void_p),
+        ("k_d", ctypes.c_double), ("trail_decay", ctypes.c_double),
+        ("trail_diffusion", ctypes.c_double),
     ]
 
 
@@ -81,6 +83,7 @@ def lib() -> ctypes.CDLL:
         "fast_move_batch": [P, P, I32],
         "fast_get_state": [P, I32, P, P, P, P, P],
         "fast_get_stats": [P, I32, P],
+        "fast_get_trail": [P, I32, P, ctypes.c_int64],
         "fast_debug_plan": [P, I32, P, P, P, P],
         "fast_timing_start": [P, I32],
         "fast_timing_read": [P, P, I32, P],
@@ -181,10 +184,11 @@ class CUStream:
 
 def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, seed: int = 1,
               scn: int = 0, agent_xy=None, tile=None, agent_v=None, exit_field=None,
-              agent_field=None):
+              agent_field=None, trail=None):
     """Descriptor plus the host arrays it points to (keep both alive).
     exit_field (H, W) and agent_field (n,) give several floor fields: exit
-    cells tagged g lead field g, and agent i follows field agent_field[i]."""
+    cells tagged g lead field g, and agent i follows field agent_field[i].
+    trail = (k_d, decay, diffusion): the dynamic floor field."""
     ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
     H, W = ct.shape
     xy = None
@@ -221,6 +225,8 @@ def make_desc(cell_type: np.ndarray, n_agents: int, v: int, k_s: float = 1.2, se
         if nf >= 2:
             d.exit_field = _ptr(ef)
             d.agent_field = _ptr(af) if len(af) else None
+    if trail is not None:
+        d.k_d, d.trail_decay, d.trail_diffusion = (float(x) for x in trail)
     return d, (ct, xy, sv, ef, af)
 
 
@@ -256,6 +262,7 @@ class Context:
         self.ctx = ctx
         self.n_agents = {}
         self.v = {}
+        self.shape = {}
 
     def cus(self) -> int:
         """CUs this context's stream reaches (see fast_ctx_cus)."""
@@ -266,9 +273,10 @@ class Context:
     # -- scenarios ---------------------------------------------------------
     def init_scenario(self, cell_type, n_agents=0, v=4, k_s=1.2, seed=1, scn=0, agent_xy=None,
                       tile="auto", batched=False, agent_v=None, exit_field=None,
-                      agent_field=None) -> int:
+                      agent_field=None, trail=None) -> int:
         """tile: (tx, ty); "auto" = the autotuner's table (planned alone, or in
-        a batched launch when `batched`), None = the library's own rule."""
+        a batched launch when `batched`), None = the library's own rule.
+        trail: (k_d, decay, diffusion) of the dynamic floor field, or None."""
         if isinstance(tile, str):
             from . import autotune
             ct = np.asarray(cell_type)
@@ -276,11 +284,12 @@ class Context:
             tile = autotune.choose_tile(int(v), int(ct.shape[1]), int(ct.shape[0]), n, batched,
                                         het=agent_v is not None or agent_field is not None)
         d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_xy, tile, agent_v,
-                            exit_field, agent_field)
+                            exit_field, agent_field, trail)
         h = ctypes.c_int32(-1)
         _check(lib().fast_init_scenario(self.ctx, ctypes.byref(d), ctypes.byref(h)))
         self.n_agents[h.value] = d.n_agents
         self.v[h.value] = int(v)
+        self.shape[h.value] = (int(d.height), int(d.width))
         return h.value
 
     def init_from(self, sc, tile="auto", batched=False) -> int:
@@ -348,6 +357,13 @@ class Context:
         return {"xy": xy[:n], "alive": alive[:n], "desired": desired[:n], "step": step.value,
                 "n_active": n_active.value}
 
+    def trail(self, h: int) -> np.ndarray:
+        """(height, width) float64: the trail field T for the next planning
+        phase of a scenario that keeps one."""
+        out = np.zeros(self.shape[h], dtype=np.float64)
+        _check(lib().fast_get_trail(self.ctx, h, _ptr(out), out.size))
+        return out
+
     def stats(self, h: int) -> dict:
         st = Stats()
         _check(lib().fast_get_stats(self.ctx, h, ctypes.byref(st)))
@@ -392,9 +408,9 @@ class Context:
         _check(lib().fast_serve_start(self.ctx, int(budget), int(max_active)))
 
     def serve_submit(self, cell_type, n_agents, v, k_s=1.2, seed=1, scn=0, steps=396,
-                     agent_v=None, exit_field=None, agent_field=None) -> int:
+                     agent_v=None, exit_field=None, agent_field=None, trail=None) -> int:
         d, keep = make_desc(cell_type, n_agents, v, k_s, seed, scn, agent_v=agent_v,
-                            exit_field=exit_field, agent_field=agent_field)
+                            exit_field=exit_field, agent_field=agent_field, trail=trail)
         t = ctypes.c_uint64(0)
         _check(lib().fast_serve_submit(self.ctx, ctypes.byref(d), int(steps), ctypes.byref(t)))
         self.n_agents[("ticket", t.value)] = d.n_agents

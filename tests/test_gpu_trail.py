@@ -1,0 +1,244 @@
+"""GPU parity of the dynamic floor field (the trail field, reading R14: one of
+the couplings k_other that the paper sets to 0 in Sec. 2).
+
+The bar is the uniform model's: plans, positions, alive flags and the trail
+field itself bit-identical to the oracle's, step by step, on the same seeded
+inputs; the FP32 table weights (now carrying exp(k_D (T(t) - T(c)))) within
+1e-6 relative of the oracle's FP64 ratios and the FP32 CDF within half the
+guard band, as in the uniform parity tests.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0911_2900_amd import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+TRAIL = (1.0, 0.3, 0.2)            # k_D, delta, alpha
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0911_2900_amd import fast
+    c = fast.Context()
+    yield c
+    c.close()
+
+
+def _pair(ctx, s, trail=TRAIL, tile=None, k_s=None, vi=None, batched=False):
+    k_s = s.k_s if k_s is None else k_s
+    sim = oracle.Sim(s.cell_type, s.v, k_s, s.seed, s.scn, n_agents=s.n_agents, agent_v=vi,
+                     trail=trail)
+    h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, k_s, s.seed, s.scn, tile=tile,
+                          agent_v=vi, trail=trail, batched=batched)
+    return sim, h
+
+
+def _compare(ctx, sim, h, where, desired=False):
+    st = ctx.state(h)
+    n = sim.n
+    alive = sim.alive[:n].astype(bool)
+    assert np.array_equal(st["alive"].astype(bool), alive), f"alive differs {where}"
+    assert np.array_equal(st["xy"], sim.positions()), f"positions differ {where}"
+    if desired:
+        bad = np.nonzero(st["desired"][alive] != sim.desired[:n][alive])[0]
+        assert len(bad) == 0, f"plan differs for {len(bad)} agents {where}"
+    T = ctx.trail(h)
+    if not np.array_equal(T, sim.Tr):
+        d = np.abs(T - sim.Tr)
+        y, x = np.unravel_index(int(d.argmax()), d.shape)
+        raise AssertionError(f"trail differs {where}: {int((d > 0).sum())} cells, worst at "
+                             f"({x}, {y}): {T[y, x]!r} vs {sim.Tr[y, x]!r}")
+
+
+def _step_both(ctx, sim, h, steps, where):
+    for k in range(steps):
+        ctx.plan(h)
+        sim.plan()
+        _compare(ctx, sim, h, f"after plan {k} {where}", desired=True)
+        ctx.move(h)
+        sim.move()
+        sim.end_step()
+        _compare(ctx, sim, h, f"after step {k} {where}")
+
+
+def _check_weights(ctx, sim, h, sample):
+    """The debug plan's FP32 weights and CDF against the oracle's FP64 draw
+    (with the trail term) of a sample of agents."""
+    from paper_0911_2900_amd import fast
+    w32, flag, margin, cdf32 = ctx.debug_plan(h)
+    sim.plan()
+    eps = fast.guard_band(sim.v)
+    side = 2 * sim.v + 1
+    dy, dx = np.divmod(np.arange(side * side), side)
+    disc = (dx - sim.v) ** 2 + (dy - sim.v) ** 2 <= sim.v ** 2
+    alive = np.nonzero(sim.alive[: sim.n])[0]
+    ids = np.random.default_rng(0).choice(alive, min(sample, len(alive)), replace=False)
+    worst = 0.0
+    for i in ids:
+        d, w64, C, u, slot = sim.plan_agent(int(i))
+        W64 = C[-1]
+        wmax = w64.max()
+        w = w32[i].astype(np.float64)
+        big = w64 >= 2.0 ** -60 * W64
+        rel = np.abs(w[big] - w64[big] / wmax) / (w64[big] / wmax)
+        worst = max(worst, float(rel.max()))
+        assert rel.max() <= 1e-6, f"agent {i} (flag {flag[i]}): weight rel err {rel.max():.3e}"
+        if flag[i] != 2:
+            c = cdf32[i].astype(np.float64)
+            err = np.abs(c[disc] / c[-1] - C[disc] / W64).max()
+            assert err < eps / 2, f"agent {i}: FP32 CDF error {err:.3e} W"
+    st = ctx.state(h)
+    a = sim.alive[: sim.n].astype(bool)
+    assert np.array_equal(st["desired"][a], sim.desired[: sim.n][a])
+    return worst, flag
+
+
+@pytest.mark.parametrize("v,tile", [(4, None), (2, (16, 16)), (5, (32, 8))])
+def test_trail_room_matches_oracle(ctx, v, tile):
+    """A room of 20,000 agents with k_D = 1, delta = 0.3, alpha = 0.2: every
+    plan, position and the whole trail field equal the oracle's for 12
+    steps; then the table weights (trail term included) against the
+    oracle's FP64 weights."""
+    s = sc.room(n_agents=20000, v=v)
+    say(f"trail room v={v} tile {tile}")
+    sim, h = _pair(ctx, s, tile=tile)
+    _step_both(ctx, sim, h, 12, f"v={v}")
+    assert ctx.trail(h).max() > 1.0                     # deposits accumulated
+    worst, flag = _check_weights(ctx, sim, h, sample=3000)
+    say(f"  weights rel err {worst:.2e}, flagged {int((flag == 1).sum())}")
+    ctx.move(h)
+    sim.move()
+    sim.end_step()
+    _compare(ctx, sim, h, "after the debug plan's motion phase")
+    ctx.destroy(h)
+
+
+def test_trail_long_run_corridor(ctx):
+    """The corridor's 396 steps with a trail field, compared every 30 steps."""
+    s = sc.corridor()
+    sim, h = _pair(ctx, s, trail=(2.0, 0.1, 0.3))
+    for k in range(0, 396, 30):
+        n = min(30, 396 - k)
+        ctx.run([h], n)
+        sim.run(n)
+        _compare(ctx, sim, h, f"at step {k + n}")
+    ctx.destroy(h)
+
+
+def test_trail_k_d_zero_is_the_static_model(ctx):
+    """k_D = 0 with the field kept: the trajectories of the plain kernels
+    (and the oracle's trail field)."""
+    s = sc.room(n_agents=12000, v=4, size=200)
+    sim, h = _pair(ctx, s, trail=(0.0, 0.25, 0.5))
+    hp = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn)
+    ctx.run([h], 20)
+    ctx.run([hp], 20)
+    sim.run(20)
+    _compare(ctx, sim, h, "k_D = 0")
+    assert np.array_equal(ctx.state(h)["xy"], ctx.state(hp)["xy"])
+    ctx.destroy(h)
+    ctx.destroy(hp)
+
+
+def test_trail_strong_coupling_fallback_tiles(ctx):
+    """k_D = 45: as deposits pile up, window exponents leave the FP32 table's
+    range, the trail launch flags those tiles and their agents draw in FP64;
+    everything stays the oracle's."""
+    s = sc.room(n_agents=6000, v=3, size=160)
+    sim, h = _pair(ctx, s, trail=(45.0, 0.3, 0.1), tile=(16, 16))
+    _step_both(ctx, sim, h, 8, "k_D = 45")
+    st = ctx.stats(h)
+    say(f"  fallback draws {st['fallback']}, flagged {st['flagged']}")
+    assert st["fallback"] > 0
+    ctx.destroy(h)
+
+
+def test_trail_with_per_agent_speeds(ctx):
+    """Per-agent speeds (their own planning kernel) on a trail field."""
+    s = sc.room(n_agents=15000, v=5)
+    vi = np.random.default_rng(3).integers(1, 6, size=s.n_agents)
+    sim, h = _pair(ctx, s, vi=vi, tile=(32, 8))
+    _step_both(ctx, sim, h, 10, "speeds + trail")
+    worst, flag = _check_weights(ctx, sim, h, sample=2000)
+    say(f"  weights rel err {worst:.2e}")
+    ctx.destroy(h)
+
+
+def test_trail_in_batches(ctx):
+    """Members with and without a trail field in graph-replayed batches,
+    plain batched steps and the allocation-free batched entry point."""
+    members = [sc.ensemble_member(k) for k in (2, 3, 7, 8)]
+    pairs = []
+    for i, m in enumerate(members):
+        tr = (0.5 + 0.5 * i, 0.2, 0.1 * i) if i % 2 == 0 else None
+        sim = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents, trail=tr)
+        h = ctx.init_scenario(m.cell_type, m.n_agents, m.v, m.k_s, m.seed, m.scn, batched=True,
+                              trail=tr)
+        pairs.append((sim, h, tr))
+    hs = [h for _, h, _ in pairs]
+    ctx.run(hs, 15)
+    for _ in range(3):
+        ctx.plan_batch(hs)
+        ctx.move_batch(hs)
+    ctx.run_noalloc(hs, 7)
+    for m, (sim, h, tr) in zip(members, pairs):
+        sim.run(25)
+        st = ctx.state(h)
+        assert np.array_equal(st["xy"], sim.positions()), m.name
+        if tr is not None:
+            assert np.array_equal(ctx.trail(h), sim.Tr), m.name
+        ctx.destroy(h)
+
+
+def test_trail_served(ctx):
+    """Served requests with trail fields end where the oracle does."""
+    from paper_0911_2900_amd import fast
+    reqs = [(sc.ensemble_member(k, base_seed=9, scn_base=500), (1.0 + k, 0.2, 0.2)) for k in range(4)]
+    c = fast.Context(device=0, torch_alloc=False)
+    try:
+        c.serve_start()
+        tickets = [c.serve_submit(m.cell_type, m.n_agents, m.v, m.k_s, m.seed, m.scn, steps=30,
+                                  trail=tr) for m, tr in reqs]
+        deadline = time.time() + 120
+        for t in tickets:
+            while not c.serve_poll(t)[0]:
+                assert time.time() < deadline, "serving did not finish"
+                time.sleep(0.01)
+        res = [c.serve_result(t) for t in tickets]
+        c.serve_stop()
+    finally:
+        c.close()
+    for (m, tr), r in zip(reqs, res):
+        sim = oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents, trail=tr)
+        sim.run(30)
+        assert np.array_equal(r["xy"], sim.positions()), m.name
+
+
+def test_trail_refused_where_invalid(ctx):
+    from paper_0911_2900_amd import fast
+    s = sc.corridor()
+    for bad in ((-1.0, 0.1, 0.1), (1.0, 1.5, 0.1), (1.0, 0.1, -0.2), (float("nan"), 0.1, 0.1)):
+        with pytest.raises(fast.FastError):
+            ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, trail=bad)
+    ce = sc.counterflow()
+    with pytest.raises(fast.FastError):
+        ctx.init_scenario(ce.cell_type, ce.n_agents, ce.v, ce.k_s, ce.seed, ce.scn,
+                          exit_field=ce.meta["exit_field"], agent_field=ce.meta["agent_field"],
+                          trail=TRAIL)
+    h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn)
+    with pytest.raises(fast.FastError):
+        ctx.trail(h)                                    # no field kept
+    ctx.destroy(h)
