@@ -101,6 +101,8 @@ __host__ __device__ inline uint32_t plan_rec(int lcell, int slot)
 {
     return (uint32_t)lcell | ((uint32_t)slot << REC_SLOT_SHIFT);
 }
+// A batched planning item, (slot << 20) | tile, that plans nothing (padding).
+constexpr uint32_t PLAN_ITEM_NONE = 0xFFFFFFFFu;
 // Bit 31 of a D entry: the cell is occupied.
 constexpr uint32_t D_OCC = 0x80000000u;
 // uint64 statistics per slot

@@ -10,13 +10,14 @@
 
 namespace fk {
 
-// items[i] = (slot << 20) | tile index (row-major over the slot's tiles);
-// descriptors come from the device table.
+// items[i] = (slot << 20) | tile index (row-major over the slot's tiles), or
+// PLAN_ITEM_NONE; descriptors come from the device table.
 __global__ __launch_bounds__(PLAN_THREADS) __attribute__((amdgpu_waves_per_eu(7)))
 void plan_kernel(const SlotDev *__restrict__ table, const uint32_t *__restrict__ items)
 {
     __shared__ PlanShared sh;
     const uint32_t it = items[blockIdx.x];
+    if (it == PLAN_ITEM_NONE) return;                     // padding
     plan_dispatch<false>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
 }
 

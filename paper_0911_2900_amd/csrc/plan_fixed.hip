@@ -25,7 +25,7 @@ namespace fk {
 constexpr int FIXED_WAVES = PLAN_V >= 5 ? 7 : 8;
 
 // A batch of scenarios that all have v_max = V and tile width TX: one
-// workgroup per tile, items[i] = (slot << 20) | tile.  (V is a template
+// workgroup per tile, items[i] = (slot << 20) | tile or PLAN_ITEM_NONE.  (V is a template
 // parameter, not just PLAN_V, so that each object's kernels have names of
 // their own.)
 template <int V, int TX>
@@ -34,6 +34,7 @@ void plan_kernel_fixed(const SlotDev *__restrict__ table, const uint32_t *__rest
 {
     __shared__ PlanShared sh;
     const uint32_t it = items[blockIdx.x];
+    if (it == PLAN_ITEM_NONE) return;                     // padding
     plan_tile<V, TX, false>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
 }
 

@@ -646,12 +646,35 @@ fast_status batch_items(fast_ctx *c, const std::vector<int32_t> &hs, BatchItems 
         if (first) { p.v = s.dev.v; p.tx = s.dev.tx; first = false; }
         else if (s.dev.v != p.v || s.dev.tx != p.tx) p.v = p.tx = 0;
     }
-    p.items.clear();
+    // Planning items in an order that keeps neighbouring tiles on one XCD.
+    // A dispatch hands its workgroups to the XCDs in turn (workgroup i to
+    // XCD i mod 8), and each XCD has an L2 of its own.  Each scenario's
+    // tiles, in raster order, are cut into 8 runs of (nearly) equal length;
+    // run r goes to XCD (r + q) mod 8, q the scenario's place in the batch
+    // (which spreads small scenarios over the XCDs).  So every XCD plans
+    // bands of neighbouring tiles one after another, and the window rows
+    // they share come from its L2.  Lists of unequal length are padded with
+    // empty items.
+    std::vector<uint32_t> per[fk::DIES];
+    int q = 0;
     for (int32_t h : p.order) {
         const Slot &s = c->slots[h];
         if (s.het) continue;
-        for (int i = 0; i < s.n_items; ++i) p.items.push_back(((uint32_t)h << 20) | (uint32_t)i);
+        const int T = s.n_items;
+        for (int r = 0; r < fk::DIES; ++r) {
+            auto &l = per[(r + q) % fk::DIES];
+            for (int i = (int)((long)T * r / fk::DIES); i < (int)((long)T * (r + 1) / fk::DIES); ++i)
+                l.push_back(((uint32_t)h << 20) | (uint32_t)i);
+        }
+        ++q;
     }
+    size_t longest = 0;
+    for (const auto &l : per) longest = std::max(longest, l.size());
+    p.items.clear();
+    for (size_t j = 0; j < longest; ++j)
+        for (int x = 0; x < fk::DIES; ++x)
+            p.items.push_back(j < per[x].size() ? per[x][j] : fk::PLAN_ITEM_NONE);
+    while (!p.items.empty() && p.items.back() == fk::PLAN_ITEM_NONE) p.items.pop_back();
     const std::vector<int> G = batch_groups(c, p.order);
     p.mitems.clear();
     for (size_t i = 0; i < p.order.size(); ++i)
