@@ -101,6 +101,19 @@ __host__ __device__ inline uint32_t plan_rec(int lcell, int slot)
 {
     return (uint32_t)lcell | ((uint32_t)slot << REC_SLOT_SHIFT);
 }
+// Tiles of a single-scenario launch.  A dispatch deals its workgroups to
+// the XCDs in turn (workgroup i to XCD i mod DIES), and each XCD has an L2
+// of its own: XCD x plans the x-th of DIES equal runs of the tiles in raster
+// order, so that neighbouring tiles share their window rows through one L2.
+// Workgroup i plans band_tile(i, T) of the T tiles, or nothing (-1, the few
+// past the end of a run); the launch has band_grid(T) workgroups.
+__host__ __device__ inline int band_tile(int i, int T)
+{
+    const int x = i % DIES, j = i / DIES;
+    const int t0 = (int)((long)T * x / DIES), t1 = (int)((long)T * (x + 1) / DIES);
+    return t0 + j < t1 ? t0 + j : -1;
+}
+__host__ __device__ inline int band_grid(int T) { return DIES * ((T + DIES - 1) / DIES); }
 // A batched planning item, (slot << 20) | tile, that plans nothing (padding).
 constexpr uint32_t PLAN_ITEM_NONE = 0xFFFFFFFFu;
 // Bit 31 of a D entry: the cell is occupied.
