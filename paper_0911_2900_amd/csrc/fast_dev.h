@@ -103,17 +103,22 @@ __host__ __device__ inline uint32_t plan_rec(int lcell, int slot)
 }
 // Tiles of a single-scenario launch.  A dispatch deals its workgroups to
 // the XCDs in turn (workgroup i to XCD i mod DIES), and each XCD has an L2
-// of its own: XCD x plans the x-th of DIES equal runs of the tiles in raster
-// order, so that neighbouring tiles share their window rows through one L2.
-// Workgroup i plans band_tile(i, T) of the T tiles, or nothing (-1, the few
-// past the end of a run); the launch has band_grid(T) workgroups.
-__host__ __device__ inline int band_tile(int i, int T)
+// of its own: XCD x plans the tile rows x, x + DIES, x + 2 DIES, ..., each
+// row in order, so that a tile's left and right neighbours share their
+// window columns through one L2 (the crowded rows of a scenario still spread
+// over all the XCDs).  Workgroup i plans row_tile(i, ntx, nty) of the
+// ntx x nty tiles, or nothing (-1, past the last row); the launch has
+// row_grid(ntx, nty) workgroups.
+__host__ __device__ inline int row_tile(int i, int ntx, int nty)
 {
     const int x = i % DIES, j = i / DIES;
-    const int t0 = (int)((long)T * x / DIES), t1 = (int)((long)T * (x + 1) / DIES);
-    return t0 + j < t1 ? t0 + j : -1;
+    const int row = x + DIES * (j / ntx);
+    return row < nty ? row * ntx + j % ntx : -1;
 }
-__host__ __device__ inline int band_grid(int T) { return DIES * ((T + DIES - 1) / DIES); }
+__host__ __device__ inline int row_grid(int ntx, int nty)
+{
+    return DIES * ntx * ((nty + DIES - 1) / DIES);
+}
 // A batched planning item, (slot << 20) | tile, that plans nothing (padding).
 constexpr uint32_t PLAN_ITEM_NONE = 0xFFFFFFFFu;
 // Bit 31 of a D entry: the cell is occupied.

@@ -499,16 +499,13 @@ __device__ __forceinline__ void move_group(const SlotDev &s, int g, int G, int s
         // workgroup gets the same count, from neighbouring tiles (dealing
         // records out in turn instead balances regions, but scatters every
         // workgroup's memory accesses over the whole grid: slower).
-        // Workgroups go to the device's DIES dies in turn, and die x plans
-        // the x-th of DIES equal runs of the tiles (band_tile); so with G a
-        // multiple of DIES, workgroup g takes only the tiles of run g mod
-        // DIES: the occupancy lines its commits touch are then in the L2 of
-        // the die that plans those tiles next.
+        // Workgroups go to the device's DIES dies in turn; with G a multiple
+        // of DIES, workgroup g takes only tiles t = g (mod DIES), so that
+        // each die's workgroups share the records of one tile in DIES.
         const bool by_die = G % DIES == 0;
-        const int c = by_die ? (int)((long)T * (g % DIES) / DIES) : 0;          // first tile
+        const int c = by_die ? g % DIES : 0, stride = by_die ? DIES : 1;
         const int m = by_die ? G / DIES : G, w = by_die ? g / DIES : g;
-        const int Tc = by_die ? (int)((long)T * (g % DIES + 1) / DIES) - c : T;  // tiles c .. c + Tc - 1
-        const int stride = 1;
+        const int Tc = c < T ? (T - c + stride - 1) / stride : 0;   // tiles c, c + stride, ...
         int carry = 0;
         for (int j0 = 0; j0 < Tc; j0 += MOVE_THREADS) {
             const int nt = min(MOVE_THREADS, Tc - j0);

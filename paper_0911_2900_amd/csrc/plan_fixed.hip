@@ -38,12 +38,12 @@ void plan_kernel_fixed(const SlotDev *__restrict__ table, const uint32_t *__rest
     plan_tile<V, TX, false>(table[it >> 20], (int)(it & 0xFFFFFu), sh);
 }
 
-// One scenario, descriptor by value, workgroup i plans tile band_tile(i).
+// One scenario, descriptor by value, workgroup i plans tile row_tile(i).
 template <int V, int TX>
 __global__ __launch_bounds__(ONE_MAX_THREADS) void plan_kernel_one_fixed(const SlotDev s)
 {
     __shared__ PlanShared sh;
-    const int tile = band_tile((int)blockIdx.x, s.ntx * s.nty);
+    const int tile = row_tile((int)blockIdx.x, s.ntx, s.nty);
     if (tile < 0) return;
     plan_tile<V, TX, false>(s, tile, sh);
 }
@@ -81,7 +81,7 @@ extern "C" hipError_t FK_CAT(fk_launch_plan_one_fixed_v, PLAN_V)(const fk::SlotD
     const int cells = slot->tx * slot->ty;
     const int threads = cells < fk::PLAN_THREADS ? fk::PLAN_THREADS
                         : cells > fk::ONE_MAX_THREADS ? fk::ONE_MAX_THREADS : cells;
-    const dim3 grid(fk::band_grid(n_tiles)), block(threads);
+    const dim3 grid(fk::row_grid(slot->ntx, slot->nty)), block(threads);
     switch (slot->tx) {
         case 8: hipExtLaunchKernelGGL((fk::plan_kernel_one_fixed<PLAN_V, 8>), grid, block, 0, stream, start, stop, 0, *slot); break;
         case 16: hipExtLaunchKernelGGL((fk::plan_kernel_one_fixed<PLAN_V, 16>), grid, block, 0, stream, start, stop, 0, *slot); break;

@@ -39,7 +39,7 @@ struct HetShared {
 };
 
 // One tile of a scenario with per-agent speeds and / or several fields:
-// workgroup i plans tile band_tile(i).
+// workgroup i plans tile row_tile(i).
 template <int V, int TX, bool DEBUG>
 __global__ __launch_bounds__(ONE_MAX_THREADS) void plan_kernel_het(const SlotDev s, const HetDev h)
 {
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(ONE_MAX_THREADS) void plan_kernel_het(const SlotDev
     __shared__ HetShared sh;
     float *Ew = (float *)het_dyn;
     const int tid = threadIdx.x, nthr = blockDim.x, lane = __lane_id();
-    const int tile = band_tile((int)blockIdx.x, s.ntx * s.nty);
+    const int tile = row_tile((int)blockIdx.x, s.ntx, s.nty);
     if (tile < 0) return;
     const T tg(s, tile);
     const int win = 4 * tg.n_win;                             // floats per window
@@ -169,7 +169,7 @@ hipError_t launch_het_tx(const fk::SlotDev &s, const fk::HetDev &h, int n_tiles,
                         : cells > fk::ONE_MAX_THREADS ? fk::ONE_MAX_THREADS : cells;
     const size_t n_win = (size_t)T::cpr * (s.ty + 2 * V);
     const size_t lds = (size_t)(h.nf > 1 ? h.nf + 1 : 1) * n_win * 16;
-    hipExtLaunchKernelGGL((fk::plan_kernel_het<V, TX, DEBUG>), dim3(fk::band_grid(n_tiles)), dim3(threads), lds,
+    hipExtLaunchKernelGGL((fk::plan_kernel_het<V, TX, DEBUG>), dim3(fk::row_grid(s.ntx, s.nty)), dim3(threads), lds,
                           stream, start, stop, 0, s, h);
     return hipGetLastError();
 }

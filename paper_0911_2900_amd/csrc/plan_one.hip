@@ -12,7 +12,7 @@ namespace fk {
 __global__ __launch_bounds__(PLAN_THREADS) void plan_kernel_debug(const SlotDev s)
 {
     __shared__ PlanShared sh;
-    const int tile = band_tile((int)blockIdx.x, s.ntx * s.nty);
+    const int tile = row_tile((int)blockIdx.x, s.ntx, s.nty);
     if (tile < 0) return;
     plan_dispatch<true>(s, tile, sh);
 }
@@ -26,7 +26,7 @@ extern "C" hipError_t fk_launch_plan_one(const fk::SlotDev *slot, int n_tiles, i
 {
     if (n_tiles <= 0) return hipSuccess;
     if (debug) {
-        hipLaunchKernelGGL(fk::plan_kernel_debug, dim3(fk::band_grid(n_tiles)), dim3(fk::PLAN_THREADS), 0, stream,
+        hipLaunchKernelGGL(fk::plan_kernel_debug, dim3(fk::row_grid(slot->ntx, slot->nty)), dim3(fk::PLAN_THREADS), 0, stream,
                            *slot);
         return hipGetLastError();
     }
