@@ -96,14 +96,15 @@ def window_cells(cell_type: np.ndarray, xy: np.ndarray, v: int) -> int:
 
 
 def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4, n_agents: int = 40000,
-               agent_v=None, scenario=None):
+               agent_v=None, scenario=None, trail=None):
     from paper_0911_2900_amd import scenarios as sc
 
     s = sc.room(v=v, n_agents=n_agents) if scenario is None else scenario
-    if agent_v is None:
+    if agent_v is None and trail is None:
         h = ctx.init_from(s)
     else:
-        h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, agent_v=agent_v)
+        h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, agent_v=agent_v,
+                              trail=trail)
     for _ in range(warmup):
         ctx.plan(h)
         ctx.move(h)
@@ -484,9 +485,8 @@ def bench_fd(ctx, torch, steps: int = 396, per_density: int = 16):
 
 def bench_het(ctx, torch, warmup: int, steps: int):
     """The room (40,000 agents) with a maximum speed per agent drawn
-    uniformly from 1..5 (v_max = 5): every draw in FP64 with the agent's own
-    disc.  Beside it the same room with v_m = 5 for everybody (FP32 table
-    path)."""
+    uniformly from 1..5 (v_max = 5), on the FP32 table path with each agent's
+    own disc.  Beside it the same room with v_m = 5 for everybody."""
     vi = np.random.default_rng(11).integers(1, 6, size=40000)
     out = {}
     for key, av in (("per_agent_speeds", vi), ("uniform_v5", None)):
@@ -503,9 +503,9 @@ def bench_het(ctx, torch, warmup: int, steps: int):
 
 def bench_fields(ctx, torch, warmup: int, steps: int):
     """A 400 x 400 counterflow hall, 40,000 agents at v_m = 4 in two groups,
-    each following the floor field of its own exits (left or right wall):
-    every draw in FP64 with the agent's own field.  Beside it the 400 x 400
-    room with one exit and one field (FP32 table path)."""
+    each following the floor field of its own exits (left or right wall),
+    on the FP32 table path with one exp table per field.  Beside it the
+    400 x 400 room with one exit and one field."""
     from paper_0911_2900_amd import scenarios as sc
 
     out = {}
@@ -521,6 +521,28 @@ def bench_fields(ctx, torch, warmup: int, steps: int):
         log(f"fields {key}: {out[key]}")
     out["workload"] = ("counterflow hall 400x400, exits 4 cells on the left and right walls, "
                        "40,000 agents in two even groups, v_m=4, k_S=1.2")
+    return out
+
+
+def bench_trail(ctx, torch, warmup: int, steps: int):
+    """The room (40,000 agents, v_m = 4) with a dynamic floor field (a trail
+    that departing agents leave, decayed and diffused after every motion
+    phase, weighted by exp(k_D (T(t) - T(c)))), beside the plain room.  The
+    whole step includes the two launches that update the trail and rebuild
+    the exp table."""
+    out = {}
+    for key, tr in (("trail", (1.0, 0.3, 0.2)), ("plain_room", None)):
+        r = bench_room(ctx, torch, warmup, steps, v=4, trail=tr)
+        out[key] = {"planning_agent_updates_per_s": r["planned"] / (sum(r["plan_ms"]) / 1e3),
+                    "plan_us": float(np.mean(r["plan_ms"])) * 1e3,
+                    "whole_step_us": r["total_ms"] / steps * 1e3,
+                    "tile": [r["stats"]["tile_w"], r["stats"]["tile_h"]],
+                    "exited": r["stats"]["exited"],
+                    "fp64_draws_per_step": r["stats"]["fallback"] / (warmup + steps),
+                    "flagged_per_step": r["stats"]["flagged"] / (warmup + steps)}
+        log(f"trail {key}: {out[key]}")
+    out["workload"] = ("room 400x400, 40,000 agents, v_m=4, k_S=1.2, trail k_D=1, decay 0.3, "
+                       "diffusion 0.2")
     return out
 
 
@@ -616,6 +638,8 @@ def main():
     ap.add_argument("--fields", action="store_true",
                     help="only the counterflow hall with a floor field per exit group "
                          "(FP64 planning path)")
+    ap.add_argument("--trail", action="store_true",
+                    help="only the room with a dynamic floor field (trail) beside the plain room")
     ap.add_argument("--no-fd", action="store_true",
                     help="leave the fundamental-diagram ensemble out of the default run")
     ap.add_argument("--fd", action="store_true",
@@ -662,6 +686,10 @@ def main():
         return
     if args.het:
         print(json.dumps({"het": bench_het(ctx, torch, args.warmup, args.steps)}), flush=True)
+        ctx.close()
+        return
+    if args.trail:
+        print(json.dumps({"trail": bench_trail(ctx, torch, args.warmup, args.steps)}), flush=True)
         ctx.close()
         return
     if args.fields:
@@ -766,7 +794,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("room"),
-            "kernel": f"plan_kernel_one_fixed<4, {r['stats']['tile_w']}, true>",
+            "kernel": f"plan_kernel_one_fixed<4, {r['stats']['tile_w']}>",
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": avg_plan_ms * 1e3, "achievable": room_ach,
         },
