@@ -73,9 +73,16 @@ struct Slot {
     int n_regions = 0;
 };
 
+// Time steps a batch's long graph captures: a graph launch costs about 8 us
+// between one step's motion launch and the next step's planning launch, so
+// runs of many steps replay GRAPH_STEPS steps per launch.
+constexpr int GRAPH_STEPS = 8;
+
 struct Batch {
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr;       // one step
     hipGraph_t graph = nullptr;
+    hipGraphExec_t exec_k = nullptr;     // GRAPH_STEPS steps
+    hipGraph_t graph_k = nullptr;
     uint32_t *items = nullptr;
     uint32_t *mitems = nullptr;
     int32_t *slots = nullptr;
@@ -362,6 +369,8 @@ void drop_batches_with(fast_ctx *c, int32_t h)
         if (std::find(it->first.begin(), it->first.end(), h) != it->first.end()) {
             if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
             if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
+            if (it->second.exec_k) (void)hipGraphExecDestroy(it->second.exec_k);
+            if (it->second.graph_k) (void)hipGraphDestroy(it->second.graph_k);
             dev_free(c, it->second.block, it->second.bytes);
             it = c->batches.erase(it);
         } else {
@@ -758,29 +767,35 @@ hipError_t launch_trails(fast_ctx *c, const std::vector<int32_t> &trails)
     return hipSuccess;
 }
 
-// One time step of a batch captured as a HIP graph: one planning launch over
-// every tile of every member, one motion launch over their workgroup groups.
-fast_status batch_graph(fast_ctx *c, Batch *b)
+// Time steps of a batch captured as a HIP graph (k = 1: exec, k =
+// GRAPH_STEPS: exec_k): per step one planning launch over every tile of
+// every member, one motion launch over their workgroup groups.
+fast_status batch_graph(fast_ctx *c, Batch *b, int k)
 {
-    if (b->exec) return FAST_OK;
+    hipGraphExec_t &exec = k == 1 ? b->exec : b->exec_k;
+    hipGraph_t &graph = k == 1 ? b->graph : b->graph_k;
+    if (exec) return FAST_OK;
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
-    if (e1 == hipSuccess) e1 = launch_het_members(c, b->het);
-    hipError_t e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
-    if (e2 == hipSuccess) e2 = launch_trails(c, b->trails);
-    if (e2 == hipSuccess) e2 = fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream);
-    hipError_t e3 = hipStreamEndCapture(c->stream, &b->graph);
+    hipError_t e1 = hipSuccess, e2 = hipSuccess;
+    for (int j = 0; j < k && e1 == hipSuccess && e2 == hipSuccess; ++j) {
+        e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
+        if (e1 == hipSuccess) e1 = launch_het_members(c, b->het);
+        if (e1 == hipSuccess) e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
+        if (e2 == hipSuccess) e2 = launch_trails(c, b->trails);
+        if (e2 == hipSuccess) e2 = fk_launch_count(b->rjobs, b->n_rjobs, b->max_regions, c->stream);
+    }
+    hipError_t e3 = hipStreamEndCapture(c->stream, &graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-        if (b->graph) (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
+        if (graph) (void)hipGraphDestroy(graph);
+        graph = nullptr;
         return fail(FAST_E_DEVICE, "graph capture failed: %s / %s / %s", hipGetErrorString(e1),
                     hipGetErrorString(e2), hipGetErrorString(e3));
     }
-    hipError_t e4 = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e4 != hipSuccess) {
-        (void)hipGraphDestroy(b->graph);
-        b->graph = nullptr;
-        b->exec = nullptr;
+        (void)hipGraphDestroy(graph);
+        graph = nullptr;
+        exec = nullptr;
         return fail(FAST_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e4));
     }
     return FAST_OK;
@@ -827,9 +842,17 @@ fast_status run_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     Batch *b = nullptr;
     fast_status st = get_batch(c, hs, &b);
     if (st) return st;
-    st = batch_graph(c, b);
-    if (st) return st;
-    for (int k = 0; k < steps; ++k) HIP_TRY(hipGraphLaunch(b->exec, c->stream));
+    int left = steps;
+    if (left >= GRAPH_STEPS) {
+        st = batch_graph(c, b, GRAPH_STEPS);
+        if (st) return st;
+        for (; left >= GRAPH_STEPS; left -= GRAPH_STEPS) HIP_TRY(hipGraphLaunch(b->exec_k, c->stream));
+    }
+    if (left > 0) {
+        st = batch_graph(c, b, 1);
+        if (st) return st;
+        for (; left > 0; --left) HIP_TRY(hipGraphLaunch(b->exec, c->stream));
+    }
     for (int32_t h : hs) c->slots[h].host_steps += steps;
     return FAST_OK;
 }
@@ -1083,6 +1106,8 @@ fast_status fast_ctx_destroy(fast_ctx *c)
         for (auto &kv : c->batches) {
             if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
             if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+            if (kv.second.exec_k) (void)hipGraphExecDestroy(kv.second.exec_k);
+            if (kv.second.graph_k) (void)hipGraphDestroy(kv.second.graph_k);
             dev_free(c, kv.second.block, kv.second.bytes);
         }
         c->batches.clear();
