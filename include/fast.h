@@ -191,8 +191,9 @@ fast_status fast_move_step(fast_ctx *ctx, int32_t handle);
 /* `steps` full time steps of each of the n scenarios (Sec. 2: a run is 396
  * steps of one simulated second, each a planning phase then a motion phase),
  * run as one batch: each step is one planning launch over the tiles of all
- * scenarios and one motion launch, replayed from a captured HIP graph.  Every
- * scenario keeps its own step counter.  n >= 1, steps >= 0. */
+ * scenarios and one motion launch, replayed from captured HIP graphs (one of
+ * eight steps while at least eight are left, then one of a single step).
+ * Every scenario keeps its own step counter.  n >= 1, steps >= 0. */
 fast_status fast_run(fast_ctx *ctx, const int32_t *handles, int32_t n, int32_t steps);
 
 /* For callers that cannot allocate device memory during the call: code under
