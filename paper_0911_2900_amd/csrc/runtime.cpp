@@ -250,25 +250,30 @@ uint32_t motion_item(int32_t slot, int g, int G, bool alone = false)
 // Group sizes for a batch.  Every workgroup of the motion launch must be
 // resident at once (group barriers), so the sizes share the device's
 // capacity: every scenario gets one workgroup, and the rest go one at a time
-// to the scenario with the most agents per workgroup (the one whose rounds
-// take longest), up to its own size alone.  A batch with more scenarios than
-// the capacity runs one workgroup each (those need no group barrier).
+// to the scenario whose motion phase is expected to take longest -- agents
+// per workgroup times v_max, since a longer reach makes longer chains of
+// reservation rounds -- up to its own size alone.  A batch with more
+// scenarios than the capacity runs one workgroup each (those need no group
+// barrier).
 std::vector<int> batch_groups(const fast_ctx *c, const std::vector<int32_t> &hs)
 {
     std::vector<int> G(hs.size(), 1);
     long total = (long)hs.size();
     const long cap = std::max(1, c->move_capacity);
-    using Item = std::pair<double, size_t>;          // (agents per workgroup, index)
+    using Item = std::pair<double, size_t>;          // (expected cost per workgroup, index)
     std::priority_queue<Item> q;
+    auto cost = [&](size_t i, int g) {
+        const Slot &s = c->slots[hs[i]];
+        return (double)s.n_agents * s.dev.v / g;
+    };
     for (size_t i = 0; i < hs.size(); ++i)
-        if (motion_group(c->slots[hs[i]].n_agents) > 1) q.push({(double)c->slots[hs[i]].n_agents, i});
+        if (motion_group(c->slots[hs[i]].n_agents) > 1) q.push({cost(i, 1), i});
     while (total < cap && !q.empty()) {
         const size_t i = q.top().second;
         q.pop();
         ++G[i];
         ++total;
-        const int n = c->slots[hs[i]].n_agents;
-        if (G[i] < motion_group(n)) q.push({(double)n / G[i], i});
+        if (G[i] < motion_group(c->slots[hs[i]].n_agents)) q.push({cost(i, G[i]), i});
     }
     return G;
 }
