@@ -436,6 +436,30 @@ def test_batched_ensemble_16_members_396_steps(ctx):
     say("ensemble members", sorted(int(k) for k in picks))
 
 
+def test_eight_step_graph_replays_between_eager_steps(ctx):
+    """Runs of eight or more steps replay a graph of eight steps.  Its
+    replays are interleaved with eager batched steps, state reads (stream
+    synchronisations) and one-step replays; after every run each member
+    equals the oracle stepped as far."""
+    members = [sc.ensemble_member(k) for k in (1, 4, 12, 33)]
+    hs = [ctx.init_from(m, batched=True) for m in members]
+    sims = [oracle.Sim(m.cell_type, m.v, m.k_s, m.seed, m.scn, n_agents=m.n_agents)
+            for m in members]
+    for k, n in enumerate((8, 3, 16, 8, 11, 24)):
+        ctx.run(hs, n)
+        for sim in sims:
+            sim.run(n)
+        for m, sim, h in zip(members, sims, hs):
+            compare_state(ctx, sim, h, where=f"{m.name} after run {k} ({n} steps)")
+        ctx.plan_batch(hs)                            # one eager step between the replays
+        ctx.move_batch(hs)
+        for sim in sims:
+            sim.step_once()
+    for m, sim, h in zip(members, sims, hs):
+        compare_state(ctx, sim, h, where=f"{m.name} at the end")
+        ctx.destroy(h)
+
+
 def test_large_grid_396_steps_bit_exact(ctx):
     """One 1000 x 1000, 200,000-agent instance for the full 396 steps against
     the oracle (its planning loop on all host threads), final state and the
