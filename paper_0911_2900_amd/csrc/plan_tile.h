@@ -183,6 +183,15 @@ constexpr unsigned long long row_half_widths(int V)
     return t;
 }
 
+// The largest |dy| whose disc row holds slot d of its row (0 <= d <= 2V),
+// i.e. whose half width a satisfies 2a >= d.
+constexpr int max_dy_of_slot(int V, int d)
+{
+    for (int dy = V; dy > 0; --dy)
+        if (2 * half_width(V, dy) >= d) return dy;
+    return 0;
+}
+
 // Number of slots of the reach disc (5, 13, 29, 49, 81 for v = 1..5).
 constexpr int disc_count(int V)
 {
@@ -435,7 +444,10 @@ __device__ __forceinline__ int4 gload_i4(const int32_t *p)
     const v4 v = *(const __attribute__((address_space(1))) v4 *)p;
     return make_int4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ float fmask(uint32_t d) { return fmaxf(__uint_as_float(d), 0.0f); }
+// A D-plane word as a table value: an occupied cell (bit 31 set) reads 0.
+// Table values are non-negative floats, so as signed integers they are
+// non-negative and the flagged words negative: one integer max does it.
+__device__ __forceinline__ float fmask(uint32_t d) { return __int_as_float(max((int)d, 0)); }
 
 // What a thread loads into registers to stage a tile: its interior chunk of
 // occupancy (agent ids), and for threads 0..8 / 9 a neighbour tile's exponent
@@ -724,9 +736,15 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             float rv[SIDE];
 #pragma unroll
             for (int d = 0; d < SIDE; ++d) rv[d] = rb[d];
-            // (the own cell is the middle slot, d = V, of the middle row)
+            // (the own cell is the middle slot, d = V, of the middle row).
+            // Slots past the row's end (d > 2a) add an exact 0, so their C
+            // repeats the row's last boundary: if that boundary is <= tau,
+            // ks > 2a flags the draw whatever they add to ks; otherwise they
+            // add nothing to ks, and the near test sees the same value again.
+            // So every lane runs all SIDE slots without branching.
             const bool own_row = rs == V;
             const int rdy2 = (rs - V) * (rs - V);
+            const int ady = rs < V ? V - rs : rs - V;        // |dy| of the chosen row
             const float thr = eps * Wsum;
             float Q = 0.0f;
             float margin = fabsf(tau - Ps);                  // smallest |tau - C| (debug output)
@@ -734,16 +752,15 @@ __device__ __forceinline__ void plan_agents(const SlotDev &s, const TileGeom<V, 
             int ks = 0;
 #pragma unroll
             for (int d = 0; d < SIDE; ++d) {
-                if (d <= 2 * as) {
-                    float val = (d == V && own_row) ? ec : rv[d];
-                    if constexpr (HET) val = (d - as) * (d - as) + rdy2 <= vr2 ? val : 0.0f;
-                    Q = Q + val;
-                    const float C = Ps + Q;
-                    const float diff = tau - C;
-                    ks += diff >= 0.0f ? 1 : 0;
-                    near = near || fabsf(diff) <= thr;
-                    if constexpr (DEBUG) margin = fminf(margin, fabsf(diff));
-                }
+                float val = (d == V && own_row) ? ec : rv[d];
+                if (d > 0) val = ady <= max_dy_of_slot(V, d) ? val : 0.0f;
+                if constexpr (HET) val = (d - as) * (d - as) + rdy2 <= vr2 ? val : 0.0f;
+                Q = Q + val;
+                const float C = Ps + Q;
+                const float diff = tau - C;
+                ks += diff >= 0.0f ? 1 : 0;
+                near = near || fabsf(diff) <= thr;
+                if constexpr (DEBUG) margin = fminf(margin, fabsf(diff));
             }
             const bool flag = near || (ks > 2 * as);
 
