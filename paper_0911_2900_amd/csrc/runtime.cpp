@@ -668,10 +668,18 @@ fast_status batch_items(fast_ctx *c, const std::vector<int32_t> &hs, BatchItems 
     // (which spreads small scenarios over the XCDs).  So every XCD plans
     // bands of neighbouring tiles one after another, and the window rows
     // they share come from its L2.  Lists of unequal length are padded with
-    // empty items.
+    // empty items.  Scenarios with the larger v_max come first (a tile's
+    // draws cost more the larger the reach), so the launch ends on cheap
+    // tiles; in the 256-scenario ensemble this took about 1 us off a
+    // planning launch against the order by agent count, and the reverse
+    // order added as much.
     std::vector<uint32_t> per[fk::DIES];
     int q = 0;
-    for (int32_t h : p.order) {
+    std::vector<int32_t> porder(p.order);
+    std::stable_sort(porder.begin(), porder.end(), [&](int32_t a, int32_t b) {
+        return c->slots[a].dev.v > c->slots[b].dev.v;
+    });
+    for (int32_t h : porder) {
         const Slot &s = c->slots[h];
         if (s.het) continue;
         const int T = s.n_items;
