@@ -11,6 +11,12 @@ planning kernel, recorded by HIP events that the kernel launch itself stamps
 at the kernel's start and end (the interval a kernel trace reports).  Events
 recorded on the stream around each launch, which add the dispatch latency,
 give the `_bracketed` figures; `ms_per_step` is the whole step (plan + move).
+Those events cost the stream time of their own (about 6 us per step for the
+kernel stamps, 7 us for the bracketing pairs), so the whole step is timed in
+a run without them, and the kernel durations in a second run of the same
+scenario (same seed, so the same trajectory step for step, which is
+checked) with them.  They also slow the planning kernel itself, by about
+0.5 us per launch in a kernel trace of both runs, so `value` errs low.
 
 Also printed on the same JSON line:
   roofline      the planning kernel's algorithmic bytes per launch (5 B per
@@ -100,44 +106,61 @@ def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4, n_agents: int = 
     from paper_0911_2900_amd import scenarios as sc
 
     s = sc.room(v=v, n_agents=n_agents) if scenario is None else scenario
-    if agent_v is None and trail is None:
-        h = ctx.init_from(s)
-    else:
-        h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn, agent_v=agent_v,
-                              trail=trail)
-    for _ in range(warmup):
-        ctx.plan(h)
-        ctx.move(h)
+
+    def start():
+        if agent_v is None and trail is None:
+            h = ctx.init_from(s)
+        else:
+            h = ctx.init_scenario(s.cell_type, s.n_agents, s.v, s.k_s, s.seed, s.scn,
+                                  agent_v=agent_v, trail=trail)
+        for _ in range(warmup):
+            ctx.plan(h)
+            ctx.move(h)
+        return h
+
+    stream = ctx.stream
+    # run 1: the whole steps, nothing recorded between the launches
+    h1 = start()
+    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_start.record(stream)
+    for _ in range(steps):
+        ctx.plan(h1)
+        ctx.move(h1)
+    e_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = e_start.elapsed_time(e_end)
+    # run 2: the same steps of the same scenario, each planning launch timed
+    h = start()
     st = ctx.state(h)
     alive = st["alive"].astype(bool)
     cells = window_cells(s.cell_type, st["xy"][alive], v)
     planned0 = ctx.stats(h)["planned"]
-    stream = ctx.stream
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
-    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ctx.timing_start(steps)
-    t0 = time.perf_counter()
-    e_start.record(stream)
     for k in range(steps):
         ev[k][0].record(stream)
         ctx.plan(h)
         ev[k][1].record(stream)
         ctx.move(h)
-    e_end.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     kernel_ms = ctx.timing_read()
     assert len(kernel_ms) == steps
     bracket_ms = [a.elapsed_time(b) for a, b in ev]
-    total_ms = e_start.elapsed_time(e_end)
     stt = ctx.stats(h)
     planned = stt["planned"] - planned0
+    s1, s2 = ctx.state(h1), ctx.state(h)
+    assert np.array_equal(s1["xy"], s2["xy"]) and np.array_equal(s1["alive"], s2["alive"]), \
+        "the two runs of the room diverged"
     res = {
         "planned": planned, "plan_ms": [float(x) for x in kernel_ms], "bracket_ms": bracket_ms,
         "total_ms": total_ms, "wall_s": wall, "cells": cells, "stats": stt, "handle": h,
     }
+    ctx.destroy(h1)
     ctx.destroy(h)
     return res
 
