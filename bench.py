@@ -11,12 +11,12 @@ planning kernel, recorded by HIP events that the kernel launch itself stamps
 at the kernel's start and end (the interval a kernel trace reports).  Events
 recorded on the stream around each launch, which add the dispatch latency,
 give the `_bracketed` figures; `ms_per_step` is the whole step (plan + move).
-Those events cost the stream time of their own (about 6 us per step for the
-kernel stamps, 7 us for the bracketing pairs), so the whole step is timed in
-a run without them, and the kernel durations in a second run of the same
-scenario (same seed, so the same trajectory step for step, which is
-checked) with them.  They also slow the planning kernel itself, by about
-0.5 us per launch in a kernel trace of both runs, so `value` errs low.
+Events cost the stream time of their own, so the room runs three times
+from the same seed (the same trajectory step for step, which is checked):
+run 1 times the whole steps with nothing recorded between the launches,
+run 2 takes the kernel stamps (events created without the system-scope
+fence, which otherwise writes back and invalidates the caches and slows the
+next launch), run 3 the bracketing events.
 
 Also printed on the same JSON line:
   roofline      the planning kernel's algorithmic bytes per launch (5 B per
@@ -132,36 +132,45 @@ def bench_room(ctx, torch, warmup: int, steps: int, v: int = 4, n_agents: int = 
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = e_start.elapsed_time(e_end)
-    # run 2: the same steps of the same scenario, each planning launch timed
+    # run 2: the same steps of the same scenario, each planning launch stamped
     h = start()
     st = ctx.state(h)
     alive = st["alive"].astype(bool)
     cells = window_cells(s.cell_type, st["xy"][alive], v)
     planned0 = ctx.stats(h)["planned"]
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
     torch.cuda.synchronize()
     ctx.timing_start(steps)
-    for k in range(steps):
-        ev[k][0].record(stream)
+    for _ in range(steps):
         ctx.plan(h)
-        ev[k][1].record(stream)
         ctx.move(h)
     torch.cuda.synchronize()
     kernel_ms = ctx.timing_read()
     assert len(kernel_ms) == steps
-    bracket_ms = [a.elapsed_time(b) for a, b in ev]
     stt = ctx.stats(h)
     planned = stt["planned"] - planned0
-    s1, s2 = ctx.state(h1), ctx.state(h)
-    assert np.array_equal(s1["xy"], s2["xy"]) and np.array_equal(s1["alive"], s2["alive"]), \
-        "the two runs of the room diverged"
+    # run 3: the same again, events recorded on the stream around each launch
+    h3 = start()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        ctx.plan(h3)
+        ev[k][1].record(stream)
+        ctx.move(h3)
+    torch.cuda.synchronize()
+    bracket_ms = [a.elapsed_time(b) for a, b in ev]
+    s1 = ctx.state(h1)
+    for other in (h, h3):
+        so = ctx.state(other)
+        assert np.array_equal(s1["xy"], so["xy"]) and np.array_equal(s1["alive"], so["alive"]), \
+            "the runs of the room diverged"
     res = {
         "planned": planned, "plan_ms": [float(x) for x in kernel_ms], "bracket_ms": bracket_ms,
         "total_ms": total_ms, "wall_s": wall, "cells": cells, "stats": stt, "handle": h,
     }
-    ctx.destroy(h1)
-    ctx.destroy(h)
+    for x in (h1, h, h3):
+        ctx.destroy(x)
     return res
 
 
@@ -218,7 +227,9 @@ def bench_ensemble(ctx, torch, warmup: int, steps: int, plain_steps: int):
 def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int,
                      traffic_key: str = ""):
     """Planning kernel of many scenarios in one launch (fast_plan_batch), the
-    throughput regime: events around each launch, motion between them."""
+    throughput regime: kernel-stamped events on each launch over the timed
+    steps, motion between them; then as many steps again with events
+    recorded around each launch (the bracketed figure)."""
     t0 = time.perf_counter()
     hs = [ctx.init_from(m, batched=True) for m in scenarios]
     init_s = time.perf_counter() - t0
@@ -239,16 +250,20 @@ def bench_batch_plan(ctx, torch, scenarios, name: str, warmup: int, steps: int,
           for _ in range(steps)]
     torch.cuda.synchronize()
     ctx.timing_start(steps)
+    for _ in range(steps):
+        ctx.plan_batch(hs)
+        ctx.move_batch(hs)
+    torch.cuda.synchronize()
+    plan_ms = [float(x) for x in ctx.timing_read()]
+    assert len(plan_ms) == steps
+    planned = sum(ctx.stats(h)["planned"] for h in hs) - planned0
     for k in range(steps):
         ev[k][0].record(stream)
         ctx.plan_batch(hs)
         ev[k][1].record(stream)
         ctx.move_batch(hs)
     torch.cuda.synchronize()
-    plan_ms = [float(x) for x in ctx.timing_read()]
-    assert len(plan_ms) == steps
     bracket_ms = [a.elapsed_time(b) for a, b in ev]
-    planned = sum(ctx.stats(h)["planned"] for h in hs) - planned0
     for h in hs:
         ctx.destroy(h)
     avg_ms = float(np.mean(plan_ms))

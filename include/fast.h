@@ -274,8 +274,10 @@ fast_status fast_debug_plan(fast_ctx *ctx, int32_t handle, float *w32, uint8_t *
 /* Starts timing planning kernels: the next `max_launches` planning launches
  * of fast_plan_step and fast_plan_batch (not those inside fast_run graphs)
  * record the kernel's own start and end on the device, the same interval a
- * kernel trace reports, without waiting on the host.  Restarting discards
- * earlier records.  FAST_E_INVALID unless 1 <= max_launches <= 2^20. */
+ * kernel trace reports, without waiting on the host.  The events behind this
+ * carry no system-scope fence (no cache writeback and invalidation after the
+ * launch), so they barely disturb the launches that follow.  Restarting
+ * discards earlier records.  FAST_E_INVALID unless 1 <= max_launches <= 2^20. */
 fast_status fast_timing_start(fast_ctx *ctx, int32_t max_launches);
 
 /* Synchronises the context stream, writes the durations (milliseconds) of

@@ -1326,8 +1326,11 @@ fast_status fast_timing_start(fast_ctx *c, int32_t max_launches)
     std::lock_guard<std::recursive_mutex> g(c->mu);
     for (hipEvent_t e : c->timing) (void)hipEventDestroy(e);
     c->timing.assign((size_t)2 * max_launches, nullptr);
+    // Timing only: no system-scope fence when the event completes (its cache
+    // writeback and invalidation would slow the launches that follow).  The
+    // readers synchronise with the stream, not with these events.
     for (auto &e : c->timing) {
-        if (hipEventCreate(&e) != hipSuccess) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
             for (hipEvent_t x : c->timing) if (x) (void)hipEventDestroy(x);
             c->timing.clear();
             return fail(FAST_E_DEVICE, "hipEventCreate failed");
@@ -1574,8 +1577,8 @@ fast_status fast_stream_bandwidth(fast_ctx *c, size_t footprint, int32_t reps, d
     if (st) return st;
     std::vector<hipEvent_t> ev((size_t)2 * (reps + 2), nullptr);
     hipError_t e = hipSuccess;
-    for (auto &x : ev)
-        if (e == hipSuccess) e = hipEventCreate(&x);
+    for (auto &x : ev)                                        // timing only, as fast_timing_start's
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipMemsetAsync(block, 0, bytes, c->stream);
     for (int i = 0; i < reps + 2 && e == hipSuccess; ++i)       // two untimed launches first
         e = fk_launch_stream((float4 *)block, n4, c->stream, ev[2 * i], ev[2 * i + 1]);
