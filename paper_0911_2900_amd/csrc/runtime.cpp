@@ -757,6 +757,21 @@ fast_status get_batch(fast_ctx *c, const std::vector<int32_t> &hs, Batch **out)
     return FAST_OK;
 }
 
+// The shared planning launch of a batch.  A batch of one scenario (without
+// per-agent speeds or several fields) runs the single-scenario kernel: up to
+// one thread per tile cell and tile rows dealt to the dies, the faster launch
+// for a scenario too small to fill the device by itself.  (Its descriptor is
+// passed by value, which a captured graph keeps; a slot's descriptor never
+// changes after setup.)
+hipError_t launch_batch_plan(fast_ctx *c, const Batch *b, hipEvent_t e0, hipEvent_t e1)
+{
+    if (b->members.size() == 1 && b->het.empty()) {
+        const Slot &s = c->slots[b->members[0]];
+        return fk_launch_plan_one(&s.dev, s.n_items, 0, c->stream, e0, e1);
+    }
+    return fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, e0, e1);
+}
+
 // The planning launches of a batch's members with per-agent speeds.
 hipError_t launch_het_members(fast_ctx *c, const std::vector<int32_t> &het)
 {
@@ -791,7 +806,7 @@ fast_status batch_graph(fast_ctx *c, Batch *b, int k)
     HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = hipSuccess, e2 = hipSuccess;
     for (int j = 0; j < k && e1 == hipSuccess && e2 == hipSuccess; ++j) {
-        e1 = fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr);
+        e1 = launch_batch_plan(c, b, nullptr, nullptr);
         if (e1 == hipSuccess) e1 = launch_het_members(c, b->het);
         if (e1 == hipSuccess) e2 = fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream);
         if (e2 == hipSuccess) e2 = launch_trails(c, b->trails);
@@ -834,7 +849,7 @@ fast_status launch_batch(fast_ctx *c, const std::vector<int32_t> &hs, int steps)
     fast_status st = get_batch(c, hs, &b);
     if (st) return st;
     for (int k = 0; k < steps; ++k) {
-        HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, nullptr, nullptr));
+        HIP_TRY(launch_batch_plan(c, b, nullptr, nullptr));
         HIP_TRY(launch_het_members(c, b->het));
         HIP_TRY(fk_launch_move(c->table, b->mitems, b->n_mitems, c->stream));
         HIP_TRY(launch_trails(c, b->trails));
@@ -1313,7 +1328,7 @@ fast_status fast_plan_batch(fast_ctx *c, const int32_t *hs, int32_t n)
     if (st) return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (b->n_items > 0) next_timing_pair(c, &e0, &e1);   // times the shared planning launch
-    HIP_TRY(fk_launch_plan(c->table, b->items, b->n_items, b->v, b->tx, c->stream, e0, e1));
+    HIP_TRY(launch_batch_plan(c, b, e0, e1));
     HIP_TRY(launch_het_members(c, b->het));
     for (int32_t h : v) c->slots[h].planned = true;
     return FAST_OK;
