@@ -460,6 +460,25 @@ def test_eight_step_graph_replays_between_eager_steps(ctx):
         ctx.destroy(h)
 
 
+def test_single_scenario_run_matches_eager_steps_and_oracle(ctx):
+    """fast_run on one scenario plans with the single-scenario kernel inside
+    its graphs: 19 steps (two eight-step replays, three one-step replays),
+    then 5 more, equal the oracle and the same scenario stepped eagerly."""
+    s = sc.room(n_agents=12000, v=4, size=200)
+    sim, h = make_pair(ctx, s)
+    he = ctx.init_from(s)
+    for n in (19, 5):
+        ctx.run([h], n)
+        for _ in range(n):
+            ctx.plan(he)
+            ctx.move(he)
+        sim.run(n)
+        compare_state(ctx, sim, h, where=f"fast_run, {n} steps")
+        assert np.array_equal(ctx.state(h)["xy"], ctx.state(he)["xy"])
+    ctx.destroy(h)
+    ctx.destroy(he)
+
+
 def test_large_grid_396_steps_bit_exact(ctx):
     """One 1000 x 1000, 200,000-agent instance for the full 396 steps against
     the oracle (its planning loop on all host threads), final state and the
