@@ -473,7 +473,9 @@ def bench_fd(ctx, torch, steps: int = 396, per_density: int = 16):
     `steps` (the first step captures the graph): without region counts, and
     with the measurement area's and the upstream region's counts recorded
     after every step.  The counted run gives the diagram, binned by density,
-    with Weidmann's published fit beside it as context."""
+    with Weidmann's published fit beside it as context.  Then, untimed,
+    bottleneck corridors (exits of 1 or 2 of the 10 cells) sample the
+    congested branch that the open corridors never reach."""
     from paper_0911_2900_amd import fd
     from paper_0911_2900_amd import scenarios as sc
 
@@ -518,6 +520,40 @@ def bench_fd(ctx, torch, steps: int = 396, per_density: int = 16):
     if bins:
         top = max(bins, key=lambda b: b["flow_mean"])
         out["capacity"] = {"flow": top["flow_mean"], "at_density": top["rho_mean"]}
+    # The congested branch: bottleneck corridors, whose queue covers the
+    # measurement area; there the flow across the line is the bottleneck's
+    # outflow and the density that of the queue.
+    bm = sc.fd_bottleneck_ensemble()
+    hs = [ctx.init_scenario(m.cell_type, 0, m.v, m.k_s, m.seed, m.scn, agent_xy=m.meta["agent_xy"],
+                            tile="auto", batched=True) for m in bm]
+    for m, h in zip(bm, hs):
+        ctx.set_regions(h, [m.meta["area"], m.meta["upstream"]], steps)
+    ctx.run(hs, steps)
+    per_width, rho_b, flow_b = {}, [], []
+    for m, h in zip(bm, hs):
+        rho, flow = fd.samples(ctx.regions(h), m.meta["area_m2"], m.meta["width_m"])
+        rho_b.append(rho)
+        flow_b.append(flow)
+        w = per_width.setdefault(m.meta["exit_cells"], [[], []])
+        w[0].append(rho)
+        w[1].append(flow)
+    for h in hs:
+        ctx.destroy(h)
+    bins_b = fd.diagram(np.concatenate(rho_b), np.concatenate(flow_b))
+    for b in bins_b:
+        b["weidmann_flow"] = float(fd.weidmann_flow(np.array([b["rho_mean"]]))[0])
+    out["bottleneck"] = {
+        "workload": f"{len(bm)} corridors 100x10 cells with exits of 1 or 2 cells, "
+                    f"initial 4/5/6 P/m^2, measurement area x = 81..90, {steps} steps",
+        "scenarios": len(bm),
+        "by_exit_width": [{"exit_cells": w, "exit_m": 0.4 * w,
+                           "rho_mean": float(np.concatenate(v[0]).mean()),
+                           "flow_mean": float(np.concatenate(v[1]).mean()),
+                           "samples": int(sum(len(x) for x in v[0]))}
+                          for w, v in sorted(per_width.items())],
+        "diagram": bins_b,
+    }
+    log(f"fd bottleneck: {out['bottleneck']['by_exit_width']}")
     return out
 
 

@@ -205,22 +205,32 @@ CELL_M2 = 0.16                     # one 0.4 m x 0.4 m cell
 
 
 def fd_corridor(density: float, scn: int, length: int = 100, width: int = 10, fill: int = 50,
-                v: int = 4, seed: int = 5) -> Scenario:
+                v: int = 4, seed: int = 5, exit_cells: int = 0) -> Scenario:
     """Corridor for a fundamental diagram at an initial `density` (persons
-    per m^2) over the first `fill` columns.  meta: agent_xy (n, 2), the
-    rectangles `area` (measurement area, 10 columns from x = 61, full width)
-    and `upstream` (every cell left of the line between x = 70 and x = 71),
-    area_m2 and width_m."""
+    per m^2) over the first `fill` columns.  Its right wall is the exit, or
+    with exit_cells > 0 a bottleneck: only that many cells in the middle of
+    it.  meta: agent_xy (n, 2), the rectangles `area` (measurement area, 10
+    columns full width, from x = 61; with a bottleneck from x = 81, inside
+    the queue in front of it) and `upstream` (every cell left of the line
+    after the area's last column), area_m2 and width_m."""
     W, H = length + 2, width + 2
     t = walled_box(W, H)
-    t[1:H - 1, W - 1] = EXIT
+    if exit_cells <= 0 or exit_cells >= width:
+        t[1:H - 1, W - 1] = EXIT
+    else:
+        y0 = 1 + (width - exit_cells) // 2
+        t[y0:y0 + exit_cells, W - 1] = EXIT
     n = min(int(round(density * fill * width * CELL_M2)), fill * width)
     rng = np.random.default_rng([seed, scn])
     cells = rng.choice(fill * width, size=n, replace=False)
     xy = np.stack([1 + cells % fill, 1 + cells // fill], axis=1).astype(np.int32)
-    meta = {"agent_xy": xy, "area": (61, 1, 71, H - 1), "upstream": (0, 0, 71, H),
-            "area_m2": 10 * width * CELL_M2, "width_m": width * 0.4, "density0": density}
-    return Scenario(f"fd_{density:g}_{scn}", t, n, v, 1.2, seed, scn, meta)
+    bottleneck = 0 < exit_cells < width
+    a0 = length - 19 if bottleneck else 61
+    meta = {"agent_xy": xy, "area": (a0, 1, a0 + 10, H - 1), "upstream": (0, 0, a0 + 10, H),
+            "area_m2": 10 * width * CELL_M2, "width_m": width * 0.4, "density0": density,
+            "exit_cells": exit_cells if bottleneck else width}
+    name = f"fd_b{exit_cells}_{density:g}_{scn}" if bottleneck else f"fd_{density:g}_{scn}"
+    return Scenario(name, t, n, v, 1.2, seed, scn, meta)
 
 
 def fd_ensemble(densities=(0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0, 5.5),
@@ -228,3 +238,17 @@ def fd_ensemble(densities=(0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0, 5.5
     """fd_corridor members: per_density seeds of each initial density,
     scenario ids 1000 * (density index) + k."""
     return [fd_corridor(d, 1000 * i + k) for i, d in enumerate(densities) for k in range(per_density)]
+
+
+def fd_bottleneck_ensemble(exit_widths=(1, 2), densities=(4.0, 5.0, 6.0),
+                           per_case: int = 16) -> list:
+    """Bottleneck corridors for the congested branch: a queue builds up
+    behind an exit narrower than the corridor and covers the measurement
+    area in front of it, where the flow across the line is the bottleneck's
+    outflow and the density that of the queue (in this model an exit cell
+    removes agents as fast as they reach it, so exits of 3 cells and more
+    already keep up with the corridor).  Scenario ids 50000 + 1000 *
+    (width index) + 100 * (density index) + k."""
+    return [fd_corridor(d, 50000 + 1000 * i + 100 * j + k, exit_cells=w)
+            for i, w in enumerate(exit_widths) for j, d in enumerate(densities)
+            for k in range(per_case)]

@@ -47,6 +47,25 @@ def test_fd_corridor_inputs():
         assert (m.cell_type[1:11, 101] == sc.EXIT).all()
 
 
+def test_fd_bottleneck_corridor_inputs():
+    """A bottleneck corridor: only exit_cells cells in the middle of the right
+    wall are exit, the rest of it wall; agents as in the open corridor."""
+    for w, y0 in ((1, 5), (2, 5), (3, 4), (4, 4), (6, 3)):
+        m = sc.fd_corridor(4.0, 7, exit_cells=w)
+        col = m.cell_type[:, 101]
+        assert (col == sc.EXIT).sum() == w == m.meta["exit_cells"]
+        assert (col[y0:y0 + w] == sc.EXIT).all()
+        assert ((col == sc.EXIT) | (col == sc.WALL)).all()
+        open_ = sc.fd_corridor(4.0, 7)
+        assert open_.meta["area"] == (61, 1, 71, 11) and open_.meta["upstream"] == (0, 0, 71, 12)
+        assert m.meta["area"] == (81, 1, 91, 11) and m.meta["upstream"] == (0, 0, 91, 12)
+        assert np.array_equal(m.meta["agent_xy"], open_.meta["agent_xy"])
+        assert np.array_equal(m.cell_type[:, :101], open_.cell_type[:, :101])
+    ens = sc.fd_bottleneck_ensemble()
+    assert len({m.scn for m in ens}) == len(ens)
+    assert not {m.scn for m in ens} & {m.scn for m in sc.fd_ensemble()}
+
+
 def test_fd_samples_from_a_known_series():
     # area counts and upstream counts over 5 recorded steps (-1: not reached)
     series = np.array([[0, 50], [4, 50], [8, 47], [6, 43], [0, 43], [-1, -1]])

@@ -618,6 +618,28 @@ def _fd_pair(ctx, m):
     return sim, h
 
 
+def test_region_counts_bottleneck_corridor(ctx):
+    """A corridor whose exit is 2 of its 10 cells wide (the congested-branch
+    workload): the queue's counts and every position equal the oracle's over
+    60 graph-replayed steps."""
+    steps = 60
+    m = sc.fd_corridor(5.0, 50123, exit_cells=2)
+    sim, h = _fd_pair(ctx, m)
+    rects = [m.meta["area"], m.meta["upstream"]]
+    ctx.set_regions(h, rects, steps)
+    want = [sim.region_counts(rects)]
+    for _ in range(steps):
+        sim.step_once()
+        want.append(sim.region_counts(rects))
+    ctx.run([h], steps)
+    got = ctx.regions(h)
+    assert got.shape == (steps + 1, 2)
+    assert got.tolist() == [w.tolist() for w in want]
+    compare_state(ctx, sim, h, where="bottleneck corridor")
+    assert got[-1, 0] > 0                          # the queue still covers the area
+    ctx.destroy(h)
+
+
 def test_region_counts_match_oracle(ctx):
     """Agents in the measurement area and upstream of the flow line, recorded
     after every motion phase, equal the oracle's counts step by step: one
