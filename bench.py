@@ -724,7 +724,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs each scenario on a single MI355X and "
+        print("bench.py measures one GPU: the library runs each scenario on a single MI355X and "
               "has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
