@@ -106,12 +106,14 @@ def _check_weights(ctx, sim, h, sample):
     return worst, flag
 
 
-@pytest.mark.parametrize("v,tile", [(4, None), (2, (16, 16)), (5, (32, 8))])
+@pytest.mark.parametrize("v,tile", [(4, None), (2, (16, 16)), (5, (32, 8)), (5, (64, 16)),
+                                    (5, (16, 64)), (1, (8, 8))])
 def test_trail_room_matches_oracle(ctx, v, tile):
     """A room of 20,000 agents with k_D = 1, delta = 0.3, alpha = 0.2: every
     plan, position and the whole trail field equal the oracle's for 12
     steps; then the table weights (trail term included) against the
-    oracle's FP64 weights."""
+    oracle's FP64 weights.  (64, 16) and (16, 64) at v = 5 are the largest
+    windows the trail launch stages, (8, 8) at v = 1 the smallest.)"""
     s = sc.room(n_agents=20000, v=v)
     say(f"trail room v={v} tile {tile}")
     sim, h = _pair(ctx, s, tile=tile)
